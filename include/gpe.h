@@ -1,0 +1,193 @@
+/*
+ * gpe.h -- C ABI of the MI355X time-splitting spectral (TSSP) solver for the
+ * non-dimensional Gross-Pitaevskii equation (Numerical Scheme section, Eq. 2)
+ *
+ *     i d/dt psi = -1/2 lap psi + V psi + g |psi|^2 psi
+ *
+ * on a periodic box, in 2D or 3D, with real-time dynamics and the
+ * imaginary-time ground-state method of the same section.
+ *
+ * Conventions shared by every call
+ * --------------------------------
+ *  - Grid: x_{j,i} = lo[j] + i*h_j, h_j = (hi[j]-lo[j])/n[j], periodic.  Every
+ *    n[j] is a power of two in [8, 1024].  dim is 2 or 3; for dim = 2 only
+ *    n[0], n[1], lo[0..1], hi[0..1] are read.
+ *  - Layout: row-major over (n[0], n[1][, n[2]]), last axis contiguous,
+ *    interleaved complex (re, im).  Host state buffers are FP64 whatever the
+ *    context precision.
+ *  - Wavenumbers: k_j = 2 pi m_j / L_j with m_j = i for i < n/2, else i - n.
+ *  - Ownership: the library owns the context and all device memory it
+ *    allocates.  Host pointers passed in are borrowed for the duration of the
+ *    call and copied; outputs go to caller-owned buffers.
+ *  - Streams: every call enqueues on the context stream (the one given to
+ *    gpe_create, or a stream the library creates).  Calls that return host
+ *    values synchronise that stream; gpe_evolve and gpe_set_state_device do
+ *    not.
+ *  - Errors: status codes only; nothing throws or aborts across the ABI.
+ *    gpe_last_error() gives a message for the last failing call on a context.
+ *  - Threads: a context is used by one host thread at a time.
+ */
+#ifndef GPE_H
+#define GPE_H
+
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+typedef struct gpe_ctx gpe_ctx; /* opaque, library-owned */
+
+typedef enum {
+  GPE_OK = 0,
+  GPE_EINVAL = -1,       /* bad argument (shape, box, dt, null pointer) */
+  GPE_ENOMEM = -2,       /* device allocation failed */
+  GPE_EDEVICE = -3,      /* a HIP runtime call or kernel launch failed */
+  GPE_ENOTCONV = -4,     /* ground state not converged within max_steps */
+  GPE_ENONFINITE = -5,   /* a reduction met a NaN or Inf */
+  GPE_EBUSY = -6,        /* result not ready */
+  GPE_EUNSUPPORTED = -7  /* valid request outside what is built (e.g. n = 2048) */
+} gpe_status;
+
+typedef enum { GPE_FP64 = 0, GPE_FP32 = 1 } gpe_precision;
+
+/* Problem description (Eq. 2's grid, g and normalisation).  The state
+ * precision is GPE_FP64 or GPE_FP32; in FP32 the state and the FFT are FP32
+ * while phase arguments, sums and the imaginary-time renormalisation stay
+ * FP64.  norm_target is the value of dV * sum |psi|^2 that the ground-state
+ * method renormalises to (1 when the particle number is absorbed in g). */
+typedef struct {
+  int32_t dim;
+  int32_t n[3];
+  double lo[3], hi[3];
+  double g;
+  int32_t precision;
+  double norm_target;
+} gpe_desc;
+
+/* Analytic harmonic trap V = 1/2 sum_j w_j^2 x_j^2 (the traps of the Results
+ * section); costs no memory traffic. */
+typedef struct {
+  double w[3];
+} gpe_harmonic;
+
+/* Observables (Results section: r_rms and the axis rms sizes; Table 1: mu):
+ *   norm  = dV sum |psi|^2
+ *   e_kin = 1/2 dV/N sum |k|^2 |psi_hat|^2,  e_pot = dV sum V |psi|^2,
+ *   e_int = g/2 dV sum |psi|^4,  energy = e_kin + e_pot + e_int,
+ *   mu    = (e_kin + e_pot + 2 e_int) / norm,
+ *   sigma[j]^2 = sum x_j^2 |psi|^2 / sum |psi|^2 (from the coordinate origin),
+ *   r_rms^2 = sum_j sigma[j]^2. */
+typedef struct {
+  double norm, energy, mu, e_kin, e_pot, e_int, sigma[3], r_rms;
+} gpe_obs;
+
+/* |k|-shell spectra (feature list: particle-number, compressible and
+ * incompressible kinetic-energy spectra).  Shell n collects the k with
+ * round(|k|/dk) = n, dk = min_j 2 pi / L_j.  Values are shell sums:
+ *   n_k[n]      = dV/N sum |psi_hat|^2
+ *   e_comp[n]   = dV/(2N) sum |U^c|^2,  e_incomp[n] = dV/(2N) sum |U^i|^2,
+ *   e_qp[n]     = dV/(2N) sum |W|^2,
+ * with u = Im(conj(psi) grad psi)/|psi|, w = Re(conj(psi) grad psi)/|psi|,
+ * U = DFT(u) split into k (k.U)/|k|^2 and the rest (k = 0 is incompressible).
+ * The caller owns the arrays (nbins doubles each, any may be NULL); nbins must
+ * equal gpe_spectra_bins(); dk is written by the library. */
+typedef struct {
+  int32_t nbins;
+  double dk;
+  double *n_k, *e_comp, *e_incomp, *e_qp;
+} gpe_spectra;
+
+/* Per-kernel-kind timing collected with HIP events while enabled. */
+typedef struct {
+  int32_t count;          /* number of kinds reported */
+  char name[8][32];       /* kind names, e.g. "pass_x_fp64" */
+  double total_ms[8];     /* summed event time */
+  int64_t launches[8];    /* launches timed */
+  double bytes[8];        /* algorithmic HBM bytes per launch */
+} gpe_timing;
+
+/* Create a context: validates desc, allocates the state and work buffers on
+ * the current HIP device.  V_host (n sites of FP64, may be NULL) or V_an (may
+ * be NULL) gives the potential; neither means V = 0; both is GPE_EINVAL.
+ * hip_stream is a hipStream_t (NULL: the library creates its own).  The
+ * state starts at zero.  On failure *out is NULL. */
+gpe_status gpe_create(const gpe_desc *desc, const double *V_host,
+                      const gpe_harmonic *V_an, void *hip_stream,
+                      gpe_ctx **out);
+
+/* Replace the potential (same rules as gpe_create). */
+gpe_status gpe_set_potential(gpe_ctx *ctx, const double *V_host,
+                             const gpe_harmonic *V_an);
+
+/* Copy a host FP64 state in (interleaved complex, n sites); synchronous. */
+gpe_status gpe_set_state(gpe_ctx *ctx, const double *psi_host);
+
+/* Copy a device state in from dptr (interleaved complex of precision src,
+ * n sites, device memory of the context's device); enqueued on the stream. */
+gpe_status gpe_set_state_device(gpe_ctx *ctx, const void *dptr, int32_t src);
+
+/* Copy the state out to a host FP64 buffer (2 n doubles); synchronous. */
+gpe_status gpe_get_state(gpe_ctx *ctx, double *psi_host_out);
+
+/* Copy the state out to device memory in precision dst; enqueued. */
+gpe_status gpe_get_state_device(gpe_ctx *ctx, void *dptr, int32_t dst);
+
+/* Real-time TSSP (Numerical Scheme section): nsteps Strang steps
+ * N(dt/2) K(dt) N(dt/2), with N(tau) psi = exp(-i (V + g|psi|^2) tau) psi in
+ * real space and K(dt) = exp(-i |k|^2 dt / 2) in Fourier space.  Adjacent
+ * half-steps N(dt/2) N(dt/2) are applied as one N(dt) (exact: N leaves |psi|
+ * unchanged).  The state is a full-step state on return.  dt may be negative
+ * (time reversal); dt = 0 or nsteps < 0 is GPE_EINVAL.  Asynchronous. */
+gpe_status gpe_evolve(gpe_ctx *ctx, double dt, int64_t nsteps);
+
+/* Imaginary-time ground state (Numerical Scheme section: t -> -i t with the
+ * wavefunction normalised at every step).  Each step is
+ * N_im(dt/2) K_im(dt) N_im(dt/2) followed by psi <- psi sqrt(norm_target /
+ * (dV sum |psi|^2)), with N_im(tau) = exp(-(V + g|psi|^2) tau) (density taken
+ * at the start of the substep) and K_im(dt) = exp(-|k|^2 dt / 2).  Every
+ * check_every steps the energy is evaluated; the run stops at the first check
+ * whose energy differs from the previous check (the first check: from the
+ * starting state) by less than tol.  check_every = 0 runs exactly max_steps
+ * steps with no checks and returns GPE_OK.  Otherwise returns GPE_OK on
+ * convergence or GPE_ENOTCONV after max_steps.  steps_done and energy (the
+ * last evaluated energy; NaN if none) may be NULL.  Synchronous. */
+gpe_status gpe_ground_state(gpe_ctx *ctx, double dt, double tol,
+                            int32_t check_every, int64_t max_steps,
+                            int64_t *steps_done, double *energy);
+
+/* Observables of the current state (see gpe_obs) and, if spec is not NULL,
+ * the shell spectra (see gpe_spectra).  Synchronous.  GPE_ENONFINITE if a sum
+ * is not finite. */
+gpe_status gpe_observables(gpe_ctx *ctx, gpe_obs *out, gpe_spectra *spec);
+
+/* Number of |k| shells for this context's grid. */
+int32_t gpe_spectra_bins(const gpe_ctx *ctx);
+
+/* Discrete Fourier transform of the state in place along the axes whose bit
+ * is set in axis_mask (bit j = axis j): forward unnormalised (sign -), or
+ * inverse with 1/n_j per axis (sign +).  The spectral building block of the
+ * method, exposed for checking.  Asynchronous. */
+gpe_status gpe_transform(gpe_ctx *ctx, int32_t axis_mask, int32_t inverse);
+
+/* Wait for all work enqueued on the context stream. */
+gpe_status gpe_synchronize(gpe_ctx *ctx);
+
+/* Kernel timing with HIP events on the context stream: enable (1) or
+ * disable (0) and reset; read the per-kind totals. */
+gpe_status gpe_timing_enable(gpe_ctx *ctx, int32_t on);
+gpe_status gpe_timing_read(gpe_ctx *ctx, gpe_timing *out);
+
+/* Bytes of device memory the context holds. */
+uint64_t gpe_device_bytes(const gpe_ctx *ctx);
+
+/* Message for the last failing call on ctx (ctx may be NULL: last failure of
+ * gpe_create on this thread).  Never NULL. */
+const char *gpe_last_error(const gpe_ctx *ctx);
+
+void gpe_destroy(gpe_ctx *ctx);
+
+#ifdef __cplusplus
+}
+#endif
+#endif /* GPE_H */

@@ -1,0 +1,771 @@
+// Host runtime behind the C ABI of include/gpe.h: context and buffers, the
+// FP64 host tables (twiddles, kinetic factors), the real- and imaginary-time
+// step schedules built from fused axis passes, observables and timing.
+#include "gpe.h"
+
+#include <hip/hip_runtime.h>
+
+#include <cmath>
+#include <cstdio>
+#include <cstdlib>
+#include <cstring>
+#include <map>
+#include <string>
+#include <vector>
+
+#include "gpe_kernels.h"
+
+namespace {
+
+const double kPi = 3.14159265358979323846264338327950288;
+thread_local std::string g_create_error;
+
+struct DevBuf {
+  void *p = nullptr;
+  size_t bytes = 0;
+};
+
+// Kinds of per-frequency tables along one axis.
+enum TableKind { TB_KREAL = 0, TB_KIMAG = 1, TB_DERIV = 2, TB_INVN = 3 };
+
+struct TimedKind {
+  std::string name;
+  double total_ms = 0;
+  long long launches = 0;
+  double bytes = 0;
+};
+
+}  // namespace
+
+struct gpe_ctx {
+  gpe_desc desc{};
+  int dim = 0;
+  int n3[3] = {1, 1, 1};     // 3D view (2D problems: n3[0] = 1)
+  double lo3[3] = {0, 0, 0}, h3[3] = {0, 0, 0}, L3[3] = {1, 1, 1};
+  long long sites = 0;
+  int prec = 0;
+  size_t esize = 16;  // bytes per complex site
+  double dV = 1;
+
+  hipStream_t stream = nullptr;
+  bool own_stream = false;
+  int device = 0;
+
+  void *psi = nullptr;
+  double *V = nullptr;         // FP64 potential array (device) or null
+  double hv[3] = {0, 0, 0};    // analytic V coefficients (3D view)
+  double *partial = nullptr;   // per-workgroup partials, 3 regions
+  long long partial_region = 0;  // doubles per region
+  double *sums = nullptr;      // finalized sums, 4 x kRedSlots
+  double *scale = nullptr;     // imaginary-time c
+  void *tw[3] = {nullptr, nullptr, nullptr};  // per axis (3D view) twiddles
+  double *kw[3] = {nullptr, nullptr, nullptr};  // k^2/N weights per axis
+  std::map<std::pair<int, std::pair<int, double>>, void *> tables;  // (axis,(kind,dt))
+  size_t dev_bytes = 0;
+
+  bool timing = false;
+  std::vector<TimedKind> kinds;
+  std::vector<std::pair<int, std::pair<hipEvent_t, hipEvent_t>>> pending;
+  std::vector<std::pair<hipEvent_t, hipEvent_t>> event_pool;
+
+  std::string err;
+  int pass_order[3] = {2, 1, 0};
+};
+
+namespace {
+
+gpe_status fail(gpe_ctx *c, gpe_status st, const std::string &msg) {
+  if (c) c->err = msg; else g_create_error = msg;
+  return st;
+}
+
+gpe_status hipfail(gpe_ctx *c, hipError_t e, const char *what) {
+  std::string m = std::string(what) + ": " + hipGetErrorString(e);
+  return fail(c, e == hipErrorOutOfMemory ? GPE_ENOMEM : GPE_EDEVICE, m);
+}
+
+#define HIPCHK(ctx, call, what)                  \
+  do {                                           \
+    hipError_t e_ = (call);                      \
+    if (e_ != hipSuccess) return hipfail(ctx, e_, what); \
+  } while (0)
+
+bool pow2_in_range(int v) { return v >= 8 && v <= 1024 && (v & (v - 1)) == 0; }
+
+gpe_status dalloc(gpe_ctx *c, void **p, size_t bytes, const char *what) {
+  hipError_t e = hipMalloc(p, bytes);
+  if (e != hipSuccess) {
+    *p = nullptr;
+    return hipfail(c, e, what);
+  }
+  c->dev_bytes += bytes;
+  return GPE_OK;
+}
+
+int view_axis(const gpe_ctx *c, int user_axis) { return user_axis + (3 - c->dim); }
+
+// Signed integer mode of index i on an axis of n points.
+long signed_mode(long i, long n) { return i < n / 2 ? i : i - n; }
+
+double wavenumber(const gpe_ctx *c, int vaxis, long i) {
+  return 2 * kPi * (double)signed_mode(i, c->n3[vaxis]) / c->L3[vaxis];
+}
+
+// Host FP64 tables, rounded to the state precision on upload.
+gpe_status upload_complex(gpe_ctx *c, void **dst, const std::vector<double> &re,
+                          const std::vector<double> &im) {
+  const size_t n = re.size();
+  std::vector<double> d(2 * n);
+  std::vector<float> f(2 * n);
+  for (size_t i = 0; i < n; ++i) {
+    d[2 * i] = re[i];
+    d[2 * i + 1] = im[i];
+    f[2 * i] = (float)re[i];
+    f[2 * i + 1] = (float)im[i];
+  }
+  gpe_status st = dalloc(c, dst, n * c->esize, "table allocation");
+  if (st != GPE_OK) return st;
+  HIPCHK(c, hipMemcpy(*dst, c->prec == 1 ? (void *)f.data() : (void *)d.data(),
+                      n * c->esize, hipMemcpyHostToDevice), "table upload");
+  return GPE_OK;
+}
+
+// exp(-2 pi i j / N), j < N, each entry computed directly from its index.
+gpe_status make_twiddles(gpe_ctx *c, int vaxis) {
+  const int N = c->n3[vaxis];
+  std::vector<double> re(N), im(N);
+  for (int j = 0; j < N; ++j) {
+    const double a = 2 * kPi * (double)j / (double)N;
+    re[j] = std::cos(a);
+    im[j] = -std::sin(a);
+  }
+  return upload_complex(c, &c->tw[vaxis], re, im);
+}
+
+gpe_status make_kin_weights(gpe_ctx *c, int vaxis) {
+  const int N = c->n3[vaxis];
+  std::vector<double> w(N);
+  for (int j = 0; j < N; ++j) {
+    const double k = wavenumber(c, vaxis, j);
+    w[j] = k * k / (double)N;
+  }
+  gpe_status st = dalloc(c, (void **)&c->kw[vaxis], N * sizeof(double), "table allocation");
+  if (st != GPE_OK) return st;
+  HIPCHK(c, hipMemcpy(c->kw[vaxis], w.data(), N * sizeof(double), hipMemcpyHostToDevice),
+         "table upload");
+  return GPE_OK;
+}
+
+// Per-frequency factor along one axis, 1/N folded in:
+//   TB_KREAL exp(-i k^2 dt/2)/N, TB_KIMAG exp(-k^2 dt/2)/N, TB_DERIV i k/N,
+//   TB_INVN 1/N.  Arguments in FP64.
+gpe_status get_table(gpe_ctx *c, int vaxis, int kind, double dt, void **out) {
+  auto key = std::make_pair(vaxis, std::make_pair(kind, dt));
+  auto it = c->tables.find(key);
+  if (it != c->tables.end()) {
+    *out = it->second;
+    return GPE_OK;
+  }
+  if (c->tables.size() > 64) {  // bounded cache: drop everything but keep going
+    HIPCHK(c, hipStreamSynchronize(c->stream), "stream sync");
+    for (auto &kv : c->tables) (void)hipFree(kv.second);
+    c->tables.clear();
+  }
+  const int N = c->n3[vaxis];
+  std::vector<double> re(N), im(N);
+  for (int j = 0; j < N; ++j) {
+    const double k = wavenumber(c, vaxis, j);
+    const double inv = 1.0 / (double)N;
+    if (kind == TB_KREAL) {
+      const double ph = k * k * dt / 2;
+      re[j] = std::cos(ph) * inv;
+      im[j] = -std::sin(ph) * inv;
+    } else if (kind == TB_KIMAG) {
+      re[j] = std::exp(-k * k * dt / 2) * inv;
+      im[j] = 0;
+    } else if (kind == TB_DERIV) {
+      re[j] = 0;
+      im[j] = k * inv;
+    } else {
+      re[j] = inv;
+      im[j] = 0;
+    }
+  }
+  void *p = nullptr;
+  gpe_status st = upload_complex(c, &p, re, im);
+  if (st != GPE_OK) return st;
+  c->tables[key] = p;
+  *out = p;
+  return GPE_OK;
+}
+
+gpe::PassArgs base_args(gpe_ctx *c, int vaxis) {
+  gpe::PassArgs a{};
+  a.src = c->psi;
+  a.dst = c->psi;
+  for (int j = 0; j < 3; ++j) {
+    a.n[j] = c->n3[j];
+    a.hv[j] = c->hv[j];
+    a.lo[j] = c->lo3[j];
+    a.h[j] = c->h3[j];
+  }
+  a.axis = vaxis;
+  a.forward = 1;
+  a.inverse = 1;
+  a.store = 1;
+  a.g = c->desc.g;
+  a.V = c->V;
+  a.tw = c->tw[vaxis];
+  return a;
+}
+
+const char *kind_name(int prec, int vaxis) {
+  static const char *names[2][3] = {{"pass_x_fp64", "pass_y_fp64", "pass_z_fp64"},
+                                    {"pass_x_fp32", "pass_y_fp32", "pass_z_fp32"}};
+  return names[prec][vaxis];
+}
+
+gpe_status launch_pass(gpe_ctx *c, const gpe::PassArgs &a) {
+  int kind = -1;
+  hipEvent_t e0 = nullptr, e1 = nullptr;
+  if (c->timing) {
+    // kinds: one per axis of the 3D view; bytes = algorithmic HBM traffic
+    const char *nm = kind_name(c->prec, a.axis);
+    for (size_t i = 0; i < c->kinds.size(); ++i)
+      if (c->kinds[i].name == nm) kind = (int)i;
+    if (kind < 0) {
+      TimedKind k;
+      k.name = nm;
+      c->kinds.push_back(k);
+      kind = (int)c->kinds.size() - 1;
+    }
+    double bytes = (double)c->sites * c->esize;  // every pass reads the state once
+    bytes += a.store ? (double)c->sites * c->esize : 0;
+    if (c->V && (a.pre != gpe::PH_NONE || a.post != gpe::PH_NONE)) bytes += 8.0 * c->sites;
+    c->kinds[kind].bytes = bytes;
+    if (!c->event_pool.empty()) {
+      e0 = c->event_pool.back().first;
+      e1 = c->event_pool.back().second;
+      c->event_pool.pop_back();
+    } else {
+      HIPCHK(c, hipEventCreate(&e0), "event create");
+      HIPCHK(c, hipEventCreate(&e1), "event create");
+    }
+    HIPCHK(c, hipEventRecord(e0, c->stream), "event record");
+  }
+  hipError_t e = gpe::launch_axis_pass(c->prec, a, c->stream);
+  if (e != hipSuccess) return hipfail(c, e, "axis pass launch");
+  if (c->timing) {
+    HIPCHK(c, hipEventRecord(e1, c->stream), "event record");
+    c->pending.push_back({kind, {e0, e1}});
+    if (c->pending.size() >= 256) {
+      // drain: events complete in order on the stream
+      HIPCHK(c, hipEventSynchronize(c->pending.back().second.second), "event sync");
+      for (auto &pe : c->pending) {
+        float ms = 0;
+        hipEventElapsedTime(&ms, pe.second.first, pe.second.second);
+        c->kinds[pe.first].total_ms += ms;
+        c->kinds[pe.first].launches += 1;
+        c->event_pool.push_back(pe.second);
+      }
+      c->pending.clear();
+    }
+  }
+  return GPE_OK;
+}
+
+gpe_status drain_timing(gpe_ctx *c) {
+  if (c->pending.empty()) return GPE_OK;
+  HIPCHK(c, hipEventSynchronize(c->pending.back().second.second), "event sync");
+  for (auto &pe : c->pending) {
+    float ms = 0;
+    hipEventElapsedTime(&ms, pe.second.first, pe.second.second);
+    c->kinds[pe.first].total_ms += ms;
+    c->kinds[pe.first].launches += 1;
+    c->event_pool.push_back(pe.second);
+  }
+  c->pending.clear();
+  return GPE_OK;
+}
+
+int n_axes(const gpe_ctx *c) { return c->dim; }
+int order_axis(const gpe_ctx *c, int i) {
+  // pass order over the view axes that exist (skip axis 0 in 2D)
+  int k = 0;
+  for (int j = 0; j < 3; ++j) {
+    int ax = c->pass_order[j];
+    if (ax < 3 - c->dim) continue;
+    if (k == i) return ax;
+    ++k;
+  }
+  return -1;
+}
+
+gpe_status validate_desc(const gpe_desc *d, std::string &msg) {
+  if (!d) { msg = "desc is NULL"; return GPE_EINVAL; }
+  if (d->dim != 2 && d->dim != 3) {
+    msg = "dim must be 2 or 3";
+    return d->dim == 1 ? GPE_EUNSUPPORTED : GPE_EINVAL;
+  }
+  for (int j = 0; j < d->dim; ++j) {
+    if (d->n[j] < 1 || (d->n[j] & (d->n[j] - 1)) != 0) {
+      msg = "n[j] must be a power of two";
+      return GPE_EINVAL;
+    }
+    if (!pow2_in_range(d->n[j])) {
+      msg = "n[j] must be in [8, 1024]";
+      return GPE_EUNSUPPORTED;
+    }
+    if (!(std::isfinite(d->lo[j]) && std::isfinite(d->hi[j]) && d->hi[j] > d->lo[j])) {
+      msg = "need finite lo[j] < hi[j]";
+      return GPE_EINVAL;
+    }
+  }
+  if (!std::isfinite(d->g)) { msg = "g must be finite"; return GPE_EINVAL; }
+  if (d->precision != GPE_FP64 && d->precision != GPE_FP32) {
+    msg = "precision must be GPE_FP64 or GPE_FP32";
+    return GPE_EINVAL;
+  }
+  if (!(d->norm_target > 0) || !std::isfinite(d->norm_target)) {
+    msg = "norm_target must be positive";
+    return GPE_EINVAL;
+  }
+  return GPE_OK;
+}
+
+gpe_status set_potential(gpe_ctx *c, const double *V_host, const gpe_harmonic *V_an) {
+  if (V_host && V_an) return fail(c, GPE_EINVAL, "give V_host or V_an, not both");
+  for (int j = 0; j < 3; ++j) c->hv[j] = 0;
+  if (V_an) {
+    for (int j = 0; j < c->dim; ++j) {
+      if (!std::isfinite(V_an->w[j])) return fail(c, GPE_EINVAL, "trap frequency not finite");
+      c->hv[view_axis(c, j)] = 0.5 * V_an->w[j] * V_an->w[j];
+    }
+  }
+  if (V_host) {
+    if (!c->V) {
+      gpe_status st = dalloc(c, (void **)&c->V, c->sites * sizeof(double), "V allocation");
+      if (st != GPE_OK) return st;
+    }
+    HIPCHK(c, hipMemcpy(c->V, V_host, c->sites * sizeof(double), hipMemcpyHostToDevice),
+           "V upload");
+  } else if (c->V) {
+    HIPCHK(c, hipStreamSynchronize(c->stream), "stream sync");
+    (void)hipFree(c->V);
+    c->dev_bytes -= c->sites * sizeof(double);
+    c->V = nullptr;
+  }
+  return GPE_OK;
+}
+
+// Read-only observation passes: per axis a forward transform with the
+// kinetic-weight sum; the first also takes the real-space sums.  scale (device,
+// nullable) multiplies the state on the fly.  Fills sums[0..3*kRedSlots).
+gpe_status observe_sums(gpe_ctx *c, const double *scale, double host[3][gpe::kRedSlots]) {
+  for (int i = 0; i < n_axes(c); ++i) {
+    const int ax = order_axis(c, i);
+    gpe::PassArgs a = base_args(c, ax);
+    a.inverse = 0;
+    a.store = 0;
+    a.red = gpe::RED_KIN | (i == 0 ? gpe::RED_REAL : 0);
+    a.kw = c->kw[ax];
+    a.scale = scale;
+    a.partial = c->partial + i * c->partial_region;
+    gpe_status st = launch_pass(c, a);
+    if (st != GPE_OK) return st;
+    const gpe::PassShape sh = gpe::pass_shape(c->prec, c->n3, ax);
+    HIPCHK(c, gpe::launch_finalize(a.partial, sh.blocks, c->sums + i * gpe::kRedSlots,
+                                   nullptr, 0, 1, c->stream), "finalize launch");
+  }
+  std::vector<double> h(3 * gpe::kRedSlots, 0.0);
+  HIPCHK(c, hipMemcpyAsync(h.data(), c->sums, 3 * gpe::kRedSlots * sizeof(double),
+                           hipMemcpyDeviceToHost, c->stream), "sums download");
+  HIPCHK(c, hipStreamSynchronize(c->stream), "stream sync");
+  for (int i = 0; i < 3; ++i)
+    for (int k = 0; k < gpe::kRedSlots; ++k) host[i][k] = i < n_axes(c) ? h[i * gpe::kRedSlots + k] : 0;
+  return GPE_OK;
+}
+
+gpe_status compute_obs(gpe_ctx *c, const double *scale, gpe_obs *o) {
+  double s[3][gpe::kRedSlots];
+  gpe_status st = observe_sums(c, scale, s);
+  if (st != GPE_OK) return st;
+  const double *r = &s[0][gpe::kSlotReal];
+  double kin = 0;
+  for (int i = 0; i < n_axes(c); ++i) kin += s[i][gpe::kSlotKin];
+  gpe_obs out{};
+  out.norm = c->dV * r[0];
+  out.e_pot = c->dV * r[1];
+  out.e_int = 0.5 * c->desc.g * c->dV * r[2];
+  out.e_kin = 0.5 * c->dV * kin;
+  out.energy = out.e_kin + out.e_pot + out.e_int;
+  out.mu = (out.e_kin + out.e_pot + 2 * out.e_int) / out.norm;
+  double r2 = 0;
+  for (int j = 0; j < 3; ++j) {
+    if (j < c->dim) {
+      const double m2 = r[3 + view_axis(c, j)] / r[0];
+      out.sigma[j] = std::sqrt(m2);
+      r2 += m2;
+    } else {
+      out.sigma[j] = 0;
+    }
+  }
+  out.r_rms = std::sqrt(r2);
+  *o = out;
+  bool finite = std::isfinite(out.norm) && std::isfinite(out.energy) && std::isfinite(r2);
+  if (!finite) return fail(c, GPE_ENONFINITE, "observables are not finite");
+  return GPE_OK;
+}
+
+}  // namespace
+
+extern "C" {
+
+gpe_status gpe_create(const gpe_desc *desc, const double *V_host, const gpe_harmonic *V_an,
+                      void *hip_stream, gpe_ctx **out) {
+  if (!out) return fail(nullptr, GPE_EINVAL, "out is NULL");
+  *out = nullptr;
+  std::string msg;
+  gpe_status st = validate_desc(desc, msg);
+  if (st != GPE_OK) return fail(nullptr, st, msg);
+  if (V_host && V_an) return fail(nullptr, GPE_EINVAL, "give V_host or V_an, not both");
+
+  gpe_ctx *c = new gpe_ctx();
+  c->desc = *desc;
+  c->dim = desc->dim;
+  c->prec = desc->precision;
+  c->esize = c->prec == GPE_FP32 ? 8 : 16;
+  const int off = 3 - c->dim;
+  c->sites = 1;
+  c->dV = 1;
+  for (int j = 0; j < 3; ++j) {
+    c->n3[j] = 1;
+    c->lo3[j] = 0;
+    c->h3[j] = 0;
+    c->L3[j] = 1;
+  }
+  for (int j = 0; j < c->dim; ++j) {
+    c->n3[j + off] = desc->n[j];
+    c->lo3[j + off] = desc->lo[j];
+    c->L3[j + off] = desc->hi[j] - desc->lo[j];
+    c->h3[j + off] = c->L3[j + off] / desc->n[j];
+    c->sites *= desc->n[j];
+    c->dV *= c->h3[j + off];
+  }
+  hipError_t e = hipGetDevice(&c->device);
+  if (e != hipSuccess) {
+    delete c;
+    return fail(nullptr, GPE_EDEVICE, std::string("no HIP device: ") + hipGetErrorString(e));
+  }
+  if (hip_stream) {
+    c->stream = static_cast<hipStream_t>(hip_stream);
+  } else {
+    e = hipStreamCreateWithFlags(&c->stream, hipStreamNonBlocking);
+    if (e != hipSuccess) {
+      delete c;
+      return fail(nullptr, GPE_EDEVICE, "stream creation failed");
+    }
+    c->own_stream = true;
+  }
+  auto bail = [&](gpe_status s) {
+    g_create_error = c->err;
+    gpe_destroy(c);
+    return s;
+  };
+  if ((st = dalloc(c, &c->psi, c->sites * c->esize, "state allocation")) != GPE_OK) return bail(st);
+  if (hipMemset(c->psi, 0, c->sites * c->esize) != hipSuccess)
+    return bail(fail(c, GPE_EDEVICE, "state clear"));
+  long long maxb = 1;
+  for (int ax = 3 - c->dim; ax < 3; ++ax) {
+    const gpe::PassShape sh = gpe::pass_shape(c->prec, c->n3, ax);
+    if (sh.blocks > maxb) maxb = sh.blocks;
+  }
+  c->partial_region = maxb * gpe::kRedSlots;
+  if ((st = dalloc(c, (void **)&c->partial, 3 * c->partial_region * sizeof(double),
+                   "partials allocation")) != GPE_OK) return bail(st);
+  if ((st = dalloc(c, (void **)&c->sums, 4 * gpe::kRedSlots * sizeof(double),
+                   "sums allocation")) != GPE_OK) return bail(st);
+  if ((st = dalloc(c, (void **)&c->scale, sizeof(double), "scale allocation")) != GPE_OK)
+    return bail(st);
+  const double one = 1.0;
+  if (hipMemcpy(c->scale, &one, sizeof(double), hipMemcpyHostToDevice) != hipSuccess)
+    return bail(fail(c, GPE_EDEVICE, "scale init"));
+  for (int ax = 3 - c->dim; ax < 3; ++ax) {
+    if ((st = make_twiddles(c, ax)) != GPE_OK) return bail(st);
+    if ((st = make_kin_weights(c, ax)) != GPE_OK) return bail(st);
+  }
+  if ((st = set_potential(c, V_host, V_an)) != GPE_OK) return bail(st);
+  if (const char *ord = std::getenv("GPE_PASS_ORDER")) {
+    if (std::strlen(ord) == 3) {
+      for (int j = 0; j < 3; ++j) c->pass_order[j] = ord[j] - '0';
+    }
+  }
+  *out = c;
+  return GPE_OK;
+}
+
+gpe_status gpe_set_potential(gpe_ctx *c, const double *V_host, const gpe_harmonic *V_an) {
+  if (!c) return GPE_EINVAL;
+  return set_potential(c, V_host, V_an);
+}
+
+gpe_status gpe_set_state(gpe_ctx *c, const double *psi_host) {
+  if (!c) return GPE_EINVAL;
+  if (!psi_host) return fail(c, GPE_EINVAL, "psi_host is NULL");
+  if (c->prec == GPE_FP64) {
+    HIPCHK(c, hipMemcpyAsync(c->psi, psi_host, c->sites * 16, hipMemcpyHostToDevice, c->stream),
+           "state upload");
+  } else {
+    std::vector<float> f(2 * c->sites);
+    for (long long i = 0; i < 2 * c->sites; ++i) f[i] = (float)psi_host[i];
+    HIPCHK(c, hipMemcpyAsync(c->psi, f.data(), c->sites * 8, hipMemcpyHostToDevice, c->stream),
+           "state upload");
+    HIPCHK(c, hipStreamSynchronize(c->stream), "stream sync");
+  }
+  HIPCHK(c, hipStreamSynchronize(c->stream), "stream sync");
+  return GPE_OK;
+}
+
+gpe_status gpe_set_state_device(gpe_ctx *c, const void *dptr, int32_t src) {
+  if (!c) return GPE_EINVAL;
+  if (!dptr) return fail(c, GPE_EINVAL, "dptr is NULL");
+  if (src != GPE_FP64 && src != GPE_FP32) return fail(c, GPE_EINVAL, "bad precision");
+  HIPCHK(c, gpe::launch_convert(src, dptr, c->prec, c->psi, c->sites, c->stream),
+         "state convert");
+  return GPE_OK;
+}
+
+gpe_status gpe_get_state(gpe_ctx *c, double *psi_host_out) {
+  if (!c) return GPE_EINVAL;
+  if (!psi_host_out) return fail(c, GPE_EINVAL, "psi_host_out is NULL");
+  if (c->prec == GPE_FP64) {
+    HIPCHK(c, hipMemcpyAsync(psi_host_out, c->psi, c->sites * 16, hipMemcpyDeviceToHost,
+                             c->stream), "state download");
+    HIPCHK(c, hipStreamSynchronize(c->stream), "stream sync");
+  } else {
+    std::vector<float> f(2 * c->sites);
+    HIPCHK(c, hipMemcpyAsync(f.data(), c->psi, c->sites * 8, hipMemcpyDeviceToHost, c->stream),
+           "state download");
+    HIPCHK(c, hipStreamSynchronize(c->stream), "stream sync");
+    for (long long i = 0; i < 2 * c->sites; ++i) psi_host_out[i] = f[i];
+  }
+  return GPE_OK;
+}
+
+gpe_status gpe_get_state_device(gpe_ctx *c, void *dptr, int32_t dst) {
+  if (!c) return GPE_EINVAL;
+  if (!dptr) return fail(c, GPE_EINVAL, "dptr is NULL");
+  if (dst != GPE_FP64 && dst != GPE_FP32) return fail(c, GPE_EINVAL, "bad precision");
+  HIPCHK(c, gpe::launch_convert(c->prec, c->psi, dst, dptr, c->sites, c->stream),
+         "state convert");
+  return GPE_OK;
+}
+
+gpe_status gpe_evolve(gpe_ctx *c, double dt, int64_t nsteps) {
+  if (!c) return GPE_EINVAL;
+  if (!std::isfinite(dt) || dt == 0) return fail(c, GPE_EINVAL, "dt must be finite and nonzero");
+  if (nsteps < 0) return fail(c, GPE_EINVAL, "nsteps must be >= 0");
+  if (nsteps == 0) return GPE_OK;
+  const int na = n_axes(c);
+  void *K[3] = {nullptr, nullptr, nullptr};
+  for (int i = 0; i < na; ++i) {
+    const int ax = order_axis(c, i);
+    gpe_status st = get_table(c, ax, TB_KREAL, dt, &K[ax]);
+    if (st != GPE_OK) return st;
+  }
+  for (int64_t s = 0; s < nsteps; ++s) {
+    for (int i = 0; i < na; ++i) {
+      const int ax = order_axis(c, i);
+      gpe::PassArgs a = base_args(c, ax);
+      a.mid = gpe::MID_TABLE;
+      a.mtab = K[ax];
+      if (i == 0) {
+        a.pre = gpe::PH_REAL;
+        a.tau_pre = s == 0 ? dt / 2 : dt;
+      }
+      if (i == na - 1 && s == nsteps - 1) {
+        a.post = gpe::PH_REAL;
+        a.tau_post = dt / 2;
+      }
+      gpe_status st = launch_pass(c, a);
+      if (st != GPE_OK) return st;
+    }
+  }
+  return GPE_OK;
+}
+
+gpe_status gpe_ground_state(gpe_ctx *c, double dt, double tol, int32_t check_every,
+                            int64_t max_steps, int64_t *steps_done, double *energy) {
+  if (!c) return GPE_EINVAL;
+  if (!(std::isfinite(dt) && dt > 0)) return fail(c, GPE_EINVAL, "dt must be positive");
+  if (check_every < 0 || max_steps < 0) return fail(c, GPE_EINVAL, "negative count");
+  if (check_every > 0 && !(tol >= 0)) return fail(c, GPE_EINVAL, "tol must be >= 0");
+  const int na = n_axes(c);
+  void *K[3] = {nullptr, nullptr, nullptr};
+  for (int i = 0; i < na; ++i) {
+    const int ax = order_axis(c, i);
+    gpe_status st = get_table(c, ax, TB_KIMAG, dt, &K[ax]);
+    if (st != GPE_OK) return st;
+  }
+  const double one = 1.0;
+  HIPCHK(c, hipMemcpyAsync(c->scale, &one, sizeof(double), hipMemcpyHostToDevice, c->stream),
+         "scale reset");
+  double e_prev = NAN, e_last = NAN;
+  if (check_every > 0) {
+    gpe_obs o;
+    gpe_status st = compute_obs(c, nullptr, &o);
+    if (st != GPE_OK) return st;
+    e_prev = o.energy;
+  }
+  gpe_status result = check_every > 0 ? GPE_ENOTCONV : GPE_OK;
+  int64_t s = 0;
+  while (s < max_steps) {
+    for (int i = 0; i < na; ++i) {
+      const int ax = order_axis(c, i);
+      gpe::PassArgs a = base_args(c, ax);
+      a.mid = gpe::MID_TABLE;
+      a.mtab = K[ax];
+      if (i == 0) {
+        a.scale = c->scale;
+        a.pre = gpe::PH_IMAG;
+        a.tau_pre = dt / 2;
+      }
+      if (i == na - 1) {
+        a.post = gpe::PH_IMAG;
+        a.tau_post = dt / 2;
+        a.red = gpe::RED_NORM_OUT;
+        a.partial = c->partial;
+      }
+      gpe_status st = launch_pass(c, a);
+      if (st != GPE_OK) return st;
+      if (i == na - 1) {
+        const gpe::PassShape sh = gpe::pass_shape(c->prec, c->n3, ax);
+        HIPCHK(c, gpe::launch_finalize(c->partial, sh.blocks, c->sums + 3 * gpe::kRedSlots,
+                                       c->scale, c->desc.norm_target, c->dV, c->stream),
+               "finalize launch");
+      }
+    }
+    ++s;
+    if (check_every > 0 && s % check_every == 0) {
+      gpe_obs o;
+      gpe_status st = compute_obs(c, c->scale, &o);
+      if (st != GPE_OK) return st;
+      e_last = o.energy;
+      const bool done = std::fabs(o.energy - e_prev) < tol;
+      e_prev = o.energy;
+      if (done) {
+        result = GPE_OK;
+        break;
+      }
+    }
+  }
+  HIPCHK(c, gpe::launch_scale(c->prec, c->psi, c->sites, c->scale, c->stream), "scale launch");
+  HIPCHK(c, hipStreamSynchronize(c->stream), "stream sync");
+  if (steps_done) *steps_done = s;
+  if (energy) *energy = e_last;
+  if (result == GPE_ENOTCONV) return fail(c, GPE_ENOTCONV, "ground state did not converge");
+  return result;
+}
+
+gpe_status gpe_observables(gpe_ctx *c, gpe_obs *out, gpe_spectra *spec) {
+  if (!c) return GPE_EINVAL;
+  if (!out) return fail(c, GPE_EINVAL, "out is NULL");
+  if (spec) return fail(c, GPE_EUNSUPPORTED, "spectra not built yet");
+  return compute_obs(c, nullptr, out);
+}
+
+int32_t gpe_spectra_bins(const gpe_ctx *c) {
+  if (!c) return -1;
+  double dk = 2 * kPi / c->L3[3 - c->dim];
+  for (int j = 3 - c->dim; j < 3; ++j) dk = std::fmin(dk, 2 * kPi / c->L3[j]);
+  double q = 0;
+  for (int j = 3 - c->dim; j < 3; ++j) {
+    const double kn = (double)(c->n3[j] / 2) * (2 * kPi / c->L3[j]) / dk;
+    q += kn * kn;
+  }
+  return (int32_t)std::floor(std::sqrt(q) + 0.5) + 1;
+}
+
+gpe_status gpe_transform(gpe_ctx *c, int32_t axis_mask, int32_t inverse) {
+  if (!c) return GPE_EINVAL;
+  if (axis_mask & ~((1 << c->dim) - 1)) return fail(c, GPE_EINVAL, "axis_mask names a missing axis");
+  for (int j = 0; j < c->dim; ++j) {
+    if (!(axis_mask & (1 << j))) continue;
+    const int ax = view_axis(c, j);
+    gpe::PassArgs a = base_args(c, ax);
+    if (inverse) {
+      void *tab = nullptr;
+      gpe_status st = get_table(c, ax, TB_INVN, 0.0, &tab);
+      if (st != GPE_OK) return st;
+      a.forward = 0;
+      a.mid = gpe::MID_TABLE;
+      a.mtab = tab;
+    } else {
+      a.inverse = 0;
+    }
+    gpe_status st = launch_pass(c, a);
+    if (st != GPE_OK) return st;
+  }
+  return GPE_OK;
+}
+
+gpe_status gpe_synchronize(gpe_ctx *c) {
+  if (!c) return GPE_EINVAL;
+  HIPCHK(c, hipStreamSynchronize(c->stream), "stream sync");
+  return GPE_OK;
+}
+
+gpe_status gpe_timing_enable(gpe_ctx *c, int32_t on) {
+  if (!c) return GPE_EINVAL;
+  gpe_status st = drain_timing(c);
+  if (st != GPE_OK) return st;
+  c->kinds.clear();
+  c->timing = on != 0;
+  return GPE_OK;
+}
+
+gpe_status gpe_timing_read(gpe_ctx *c, gpe_timing *out) {
+  if (!c || !out) return GPE_EINVAL;
+  gpe_status st = drain_timing(c);
+  if (st != GPE_OK) return st;
+  std::memset(out, 0, sizeof(*out));
+  out->count = (int32_t)std::min<size_t>(8, c->kinds.size());
+  for (int i = 0; i < out->count; ++i) {
+    std::snprintf(out->name[i], sizeof(out->name[i]), "%s", c->kinds[i].name.c_str());
+    out->total_ms[i] = c->kinds[i].total_ms;
+    out->launches[i] = c->kinds[i].launches;
+    out->bytes[i] = c->kinds[i].bytes;
+  }
+  return GPE_OK;
+}
+
+uint64_t gpe_device_bytes(const gpe_ctx *c) { return c ? c->dev_bytes : 0; }
+
+const char *gpe_last_error(const gpe_ctx *c) {
+  if (!c) return g_create_error.c_str();
+  return c->err.c_str();
+}
+
+void gpe_destroy(gpe_ctx *c) {
+  if (!c) return;
+  if (c->stream) (void)hipStreamSynchronize(c->stream);
+  for (auto &pe : c->pending) c->event_pool.push_back(pe.second);
+  for (auto &ev : c->event_pool) {
+    (void)hipEventDestroy(ev.first);
+    (void)hipEventDestroy(ev.second);
+  }
+  for (auto &kv : c->tables) (void)hipFree(kv.second);
+  for (int j = 0; j < 3; ++j) {
+    if (c->tw[j]) (void)hipFree(c->tw[j]);
+    if (c->kw[j]) (void)hipFree(c->kw[j]);
+  }
+  if (c->psi) (void)hipFree(c->psi);
+  if (c->V) (void)hipFree(c->V);
+  if (c->partial) (void)hipFree(c->partial);
+  if (c->sums) (void)hipFree(c->sums);
+  if (c->scale) (void)hipFree(c->scale);
+  if (c->own_stream && c->stream) (void)hipStreamDestroy(c->stream);
+  delete c;
+}
+
+}  // extern "C"

@@ -1,0 +1,83 @@
+// Internal interface between the host runtime (gpe.cpp) and the HIP kernels
+// (axis_pass.hip, reduce.hip, spectra.hip).  Not part of the public ABI.
+#pragma once
+
+#include <hip/hip_runtime.h>
+#include <cstdint>
+
+namespace gpe {
+
+// What an axis pass does before its forward transform (pre), between the
+// transforms (mid) and after the inverse transform (post).
+enum PhaseOp : int {
+  PH_NONE = 0,
+  PH_REAL = 1,  // psi <- exp(-i (V + g|psi|^2) tau) psi
+  PH_IMAG = 2,  // psi <- exp(-(V + g|psi|^2) tau) psi   (pre: after psi <- c psi)
+};
+
+enum MidOp : int {
+  MID_NONE = 0,   // forward and inverse with nothing in between (identity)
+  MID_TABLE = 1,  // multiply the spectrum by a per-frequency complex table
+};
+
+// Reduction slots written per workgroup when the matching flag is set.
+enum RedFlag : int {
+  RED_NONE = 0,
+  RED_NORM_OUT = 1,  // sum |psi_out|^2                           (1 value)
+  RED_KIN = 2,       // sum w[f] |psi_hat|^2 after the forward FFT (1 value)
+  RED_REAL = 4,      // sums over the (pre-op) input: |psi|^2, V|psi|^2, |psi|^4,
+                     // x0^2|psi|^2, x1^2|psi|^2, x2^2|psi|^2     (6 values)
+};
+constexpr int kRedSlots = 8;  // partial[wg * kRedSlots + slot]
+constexpr int kSlotNormOut = 0, kSlotKin = 1, kSlotReal = 2;
+
+struct PassArgs {
+  const void *src;  // complex T, whole grid
+  void *dst;        // complex T, whole grid (may equal src)
+  int n[3];         // grid as 3D (2D problems use n[0] = 1)
+  int axis;         // transformed axis (0, 1 or 2)
+  int forward;      // 1: run forward stages on input; 0: input is a spectrum
+  int inverse;      // 1: run inverse stages; 0: store the spectrum (natural order)
+  int store;        // 0: read-only pass (reductions only)
+  int pre, post, mid, red;
+  double tau_pre, tau_post, g;
+  const double *V;    // FP64 potential per site, or null
+  double hv[3];       // analytic V = sum_j hv[j] x_j^2 when V is null
+  double lo[3], h[3]; // coordinates x_j = lo[j] + i h[j] (3D indexing)
+  const void *tw;     // twiddles exp(-2 pi i j / N), j < N, complex T
+  const void *mtab;   // mid table (complex T, N entries) for MID_TABLE
+  const double *kw;   // RED_KIN weights per frequency (N doubles)
+  const double *scale;  // PH_IMAG pre: psi <- (*scale) psi (null: 1)
+  double *partial;      // reductions, kRedSlots doubles per workgroup
+};
+
+struct PassShape {
+  int N;        // axis length
+  bool strided; // axis is not the contiguous one
+  int W;        // lines (contiguous) or columns (strided) per workgroup
+  int threads;  // workgroup size
+  long long blocks;
+};
+
+// Launch geometry the kernels are built for (must match the template choice).
+PassShape pass_shape(int precision, const int n[3], int axis);
+
+// Launch one axis pass; precision 0 = FP64, 1 = FP32.
+hipError_t launch_axis_pass(int precision, const PassArgs &a, hipStream_t s);
+
+// Sum `count` partial blocks of kRedSlots doubles in fixed order into
+// out[kRedSlots] (device), optionally deriving the imaginary-time scale:
+// if scale_out != null: *scale_out = sqrt(norm_target / (dV * sum slot 0)).
+hipError_t launch_finalize(const double *partial, long long count, double *out,
+                           double *scale_out, double norm_target, double dV,
+                           hipStream_t s);
+
+// psi <- c psi (c read from device), precision 0/1; sets *c = 1 afterwards.
+hipError_t launch_scale(int precision, void *psi, long long sites, double *c,
+                        hipStream_t s);
+
+// Precision conversion copies (device to device).
+hipError_t launch_convert(int src_prec, const void *src, int dst_prec, void *dst,
+                          long long sites, hipStream_t s);
+
+}  // namespace gpe

@@ -1,0 +1,108 @@
+// Second-stage reductions and small pointwise kernels.
+//
+// Axis passes leave kRedSlots FP64 partial sums per workgroup.  One
+// workgroup adds them in a fixed order (thread i takes partials i, i + 256,
+// ... in turn, then a fixed tree), so the result does not depend on timing.
+// For the imaginary-time method it also forms the renormalisation factor
+// c = sqrt(norm_target / (dV sum |psi|^2)) on the device, so the step loop
+// never waits on the host.
+#include "gpe_kernels.h"
+
+namespace gpe {
+namespace {
+
+constexpr int kFinThreads = 256;
+
+__global__ void __launch_bounds__(kFinThreads)
+finalize_kernel(const double *__restrict__ partial, long long count,
+                double *__restrict__ out, double *__restrict__ scale_out,
+                double norm_target, double dV) {
+  __shared__ double s[kRedSlots][kFinThreads];
+  const int tid = threadIdx.x;
+  double acc[kRedSlots];
+#pragma unroll
+  for (int k = 0; k < kRedSlots; ++k) acc[k] = 0;
+  for (long long i = tid; i < count; i += kFinThreads) {
+#pragma unroll
+    for (int k = 0; k < kRedSlots; ++k) acc[k] += partial[i * kRedSlots + k];
+  }
+#pragma unroll
+  for (int k = 0; k < kRedSlots; ++k) s[k][tid] = acc[k];
+  __syncthreads();
+  for (int h = kFinThreads / 2; h >= 1; h >>= 1) {
+    if (tid < h) {
+#pragma unroll
+      for (int k = 0; k < kRedSlots; ++k) s[k][tid] += s[k][tid + h];
+    }
+    __syncthreads();
+  }
+  if (tid < kRedSlots) out[tid] = s[tid][0];
+  if (tid == 0 && scale_out) scale_out[0] = sqrt(norm_target / (dV * s[0][0]));
+}
+
+template <typename T>
+__global__ void scale_kernel(T *__restrict__ psi, long long n, const double *__restrict__ c) {
+  const double f = *c;
+  for (long long i = (long long)blockIdx.x * blockDim.x + threadIdx.x; i < n;
+       i += (long long)gridDim.x * blockDim.x)
+    psi[i] = (T)(f * (double)psi[i]);
+}
+
+__global__ void set_one_kernel(double *c) { *c = 1.0; }
+
+template <typename S, typename D>
+__global__ void convert_kernel(const S *__restrict__ src, D *__restrict__ dst, long long n) {
+  for (long long i = (long long)blockIdx.x * blockDim.x + threadIdx.x; i < n;
+       i += (long long)gridDim.x * blockDim.x)
+    dst[i] = (D)src[i];
+}
+
+unsigned grid_for(long long n, int threads) {
+  long long b = (n + threads - 1) / threads;
+  if (b > 65536) b = 65536;
+  return (unsigned)(b < 1 ? 1 : b);
+}
+
+}  // namespace
+
+hipError_t launch_finalize(const double *partial, long long count, double *out,
+                           double *scale_out, double norm_target, double dV,
+                           hipStream_t s) {
+  hipLaunchKernelGGL(finalize_kernel, dim3(1), dim3(kFinThreads), 0, s, partial, count,
+                     out, scale_out, norm_target, dV);
+  return hipGetLastError();
+}
+
+hipError_t launch_scale(int precision, void *psi, long long sites, double *c,
+                        hipStream_t s) {
+  const long long n = 2 * sites;  // real components
+  if (precision == 1)
+    hipLaunchKernelGGL(scale_kernel<float>, dim3(grid_for(n, 256)), dim3(256), 0, s,
+                       static_cast<float *>(psi), n, c);
+  else
+    hipLaunchKernelGGL(scale_kernel<double>, dim3(grid_for(n, 256)), dim3(256), 0, s,
+                       static_cast<double *>(psi), n, c);
+  hipLaunchKernelGGL(set_one_kernel, dim3(1), dim3(1), 0, s, c);
+  return hipGetLastError();
+}
+
+hipError_t launch_convert(int src_prec, const void *src, int dst_prec, void *dst,
+                          long long sites, hipStream_t s) {
+  const long long n = 2 * sites;
+  const dim3 g(grid_for(n, 256)), b(256);
+  if (src_prec == 0 && dst_prec == 1)
+    hipLaunchKernelGGL((convert_kernel<double, float>), g, b, 0, s,
+                       static_cast<const double *>(src), static_cast<float *>(dst), n);
+  else if (src_prec == 1 && dst_prec == 0)
+    hipLaunchKernelGGL((convert_kernel<float, double>), g, b, 0, s,
+                       static_cast<const float *>(src), static_cast<double *>(dst), n);
+  else if (src_prec == 1)
+    hipLaunchKernelGGL((convert_kernel<float, float>), g, b, 0, s,
+                       static_cast<const float *>(src), static_cast<float *>(dst), n);
+  else
+    hipLaunchKernelGGL((convert_kernel<double, double>), g, b, 0, s,
+                       static_cast<const double *>(src), static_cast<double *>(dst), n);
+  return hipGetLastError();
+}
+
+}  // namespace gpe

@@ -1,0 +1,371 @@
+"""Thin ctypes binding over libgpe.so (C ABI in include/gpe.h).
+
+Functions named like the C ABI (gpe_create, gpe_evolve, ...) marshal
+arguments only; every step of the solver runs in the HIP library.  `Context`
+wraps them for numpy / torch callers.  There is no fallback: if the library
+is missing or no HIP device is present the calls fail loudly.
+"""
+import ctypes
+import os
+
+import numpy as np
+
+_HERE = os.path.dirname(os.path.abspath(__file__))
+LIB_PATH = os.path.join(_HERE, "libgpe.so")
+
+GPE_OK = 0
+GPE_EINVAL = -1
+GPE_ENOMEM = -2
+GPE_EDEVICE = -3
+GPE_ENOTCONV = -4
+GPE_ENONFINITE = -5
+GPE_EBUSY = -6
+GPE_EUNSUPPORTED = -7
+STATUS_NAMES = {0: "GPE_OK", -1: "GPE_EINVAL", -2: "GPE_ENOMEM", -3: "GPE_EDEVICE",
+                -4: "GPE_ENOTCONV", -5: "GPE_ENONFINITE", -6: "GPE_EBUSY",
+                -7: "GPE_EUNSUPPORTED"}
+
+GPE_FP64 = 0
+GPE_FP32 = 1
+
+
+class gpe_desc(ctypes.Structure):
+    _fields_ = [("dim", ctypes.c_int32), ("n", ctypes.c_int32 * 3),
+                ("lo", ctypes.c_double * 3), ("hi", ctypes.c_double * 3),
+                ("g", ctypes.c_double), ("precision", ctypes.c_int32),
+                ("norm_target", ctypes.c_double)]
+
+
+class gpe_harmonic(ctypes.Structure):
+    _fields_ = [("w", ctypes.c_double * 3)]
+
+
+class gpe_obs(ctypes.Structure):
+    _fields_ = [("norm", ctypes.c_double), ("energy", ctypes.c_double),
+                ("mu", ctypes.c_double), ("e_kin", ctypes.c_double),
+                ("e_pot", ctypes.c_double), ("e_int", ctypes.c_double),
+                ("sigma", ctypes.c_double * 3), ("r_rms", ctypes.c_double)]
+
+
+class gpe_spectra(ctypes.Structure):
+    _fields_ = [("nbins", ctypes.c_int32), ("dk", ctypes.c_double),
+                ("n_k", ctypes.POINTER(ctypes.c_double)),
+                ("e_comp", ctypes.POINTER(ctypes.c_double)),
+                ("e_incomp", ctypes.POINTER(ctypes.c_double)),
+                ("e_qp", ctypes.POINTER(ctypes.c_double))]
+
+
+class gpe_timing(ctypes.Structure):
+    _fields_ = [("count", ctypes.c_int32), ("name", (ctypes.c_char * 32) * 8),
+                ("total_ms", ctypes.c_double * 8), ("launches", ctypes.c_int64 * 8),
+                ("bytes", ctypes.c_double * 8)]
+
+
+_P = ctypes.c_void_p
+_D = ctypes.c_double
+_I32 = ctypes.c_int32
+_I64 = ctypes.c_int64
+_DP = ctypes.POINTER(ctypes.c_double)
+
+# name -> (restype, argtypes); the C ABI declared in include/gpe.h
+SIGNATURES = {
+    "gpe_create": (_I32, [ctypes.POINTER(gpe_desc), _DP, ctypes.POINTER(gpe_harmonic), _P,
+                          ctypes.POINTER(_P)]),
+    "gpe_set_potential": (_I32, [_P, _DP, ctypes.POINTER(gpe_harmonic)]),
+    "gpe_set_state": (_I32, [_P, _DP]),
+    "gpe_set_state_device": (_I32, [_P, _P, _I32]),
+    "gpe_get_state": (_I32, [_P, _DP]),
+    "gpe_get_state_device": (_I32, [_P, _P, _I32]),
+    "gpe_evolve": (_I32, [_P, _D, _I64]),
+    "gpe_ground_state": (_I32, [_P, _D, _D, _I32, _I64, ctypes.POINTER(_I64), _DP]),
+    "gpe_observables": (_I32, [_P, ctypes.POINTER(gpe_obs), ctypes.POINTER(gpe_spectra)]),
+    "gpe_spectra_bins": (_I32, [_P]),
+    "gpe_transform": (_I32, [_P, _I32, _I32]),
+    "gpe_synchronize": (_I32, [_P]),
+    "gpe_timing_enable": (_I32, [_P, _I32]),
+    "gpe_timing_read": (_I32, [_P, ctypes.POINTER(gpe_timing)]),
+    "gpe_device_bytes": (ctypes.c_uint64, [_P]),
+    "gpe_last_error": (ctypes.c_char_p, [_P]),
+    "gpe_destroy": (None, [_P]),
+}
+
+_lib = None
+
+
+def load_library(path=LIB_PATH):
+    """Load libgpe.so and declare the ABI.  Raises if it is not built."""
+    global _lib
+    if _lib is not None:
+        return _lib
+    if not os.path.exists(path):
+        raise RuntimeError("libgpe.so is not built (%s); run __graft_entry__.build()" % path)
+    lib = ctypes.CDLL(path)
+    for name, (res, args) in SIGNATURES.items():
+        f = getattr(lib, name)
+        f.restype = res
+        f.argtypes = args
+    _lib = lib
+    return lib
+
+
+class GpeError(RuntimeError):
+    def __init__(self, status, msg):
+        self.status = status
+        super().__init__("%s: %s" % (STATUS_NAMES.get(status, status), msg))
+
+
+def _err(ctx):
+    m = load_library().gpe_last_error(ctx)
+    return m.decode() if m else ""
+
+
+def _check(status, ctx=None):
+    if status != GPE_OK:
+        raise GpeError(status, _err(ctx))
+    return status
+
+
+def _dptr(a):
+    return a.ctypes.data_as(_DP) if a is not None else None
+
+
+# ----------------------------------------------------- ABI-named functions ---
+
+def gpe_create(desc, V_host=None, V_an=None, hip_stream=None):
+    lib = load_library()
+    out = _P()
+    st = lib.gpe_create(ctypes.byref(desc), _dptr(V_host),
+                        ctypes.byref(V_an) if V_an is not None else None,
+                        hip_stream, ctypes.byref(out))
+    if st != GPE_OK:
+        raise GpeError(st, _err(None))
+    return out
+
+
+def gpe_set_potential(ctx, V_host=None, V_an=None):
+    return _check(load_library().gpe_set_potential(
+        ctx, _dptr(V_host), ctypes.byref(V_an) if V_an is not None else None), ctx)
+
+
+def gpe_set_state(ctx, psi_host):
+    return _check(load_library().gpe_set_state(ctx, _dptr(psi_host)), ctx)
+
+
+def gpe_set_state_device(ctx, dptr, src):
+    return _check(load_library().gpe_set_state_device(ctx, dptr, src), ctx)
+
+
+def gpe_get_state(ctx, psi_host_out):
+    return _check(load_library().gpe_get_state(ctx, _dptr(psi_host_out)), ctx)
+
+
+def gpe_get_state_device(ctx, dptr, dst):
+    return _check(load_library().gpe_get_state_device(ctx, dptr, dst), ctx)
+
+
+def gpe_evolve(ctx, dt, nsteps):
+    return _check(load_library().gpe_evolve(ctx, float(dt), int(nsteps)), ctx)
+
+
+def gpe_ground_state(ctx, dt, tol, check_every, max_steps):
+    """Returns (status, steps_done, energy); GPE_ENOTCONV is returned, not raised."""
+    steps = _I64(0)
+    energy = _D(0)
+    st = load_library().gpe_ground_state(ctx, float(dt), float(tol), int(check_every),
+                                         int(max_steps), ctypes.byref(steps),
+                                         ctypes.byref(energy))
+    if st not in (GPE_OK, GPE_ENOTCONV):
+        raise GpeError(st, _err(ctx))
+    return st, steps.value, energy.value
+
+
+def gpe_observables(ctx, out, spec=None):
+    return _check(load_library().gpe_observables(
+        ctx, ctypes.byref(out), ctypes.byref(spec) if spec is not None else None), ctx)
+
+
+def gpe_spectra_bins(ctx):
+    return load_library().gpe_spectra_bins(ctx)
+
+
+def gpe_transform(ctx, axis_mask, inverse):
+    return _check(load_library().gpe_transform(ctx, int(axis_mask), int(inverse)), ctx)
+
+
+def gpe_synchronize(ctx):
+    return _check(load_library().gpe_synchronize(ctx), ctx)
+
+
+def gpe_timing_enable(ctx, on):
+    return _check(load_library().gpe_timing_enable(ctx, int(on)), ctx)
+
+
+def gpe_timing_read(ctx):
+    t = gpe_timing()
+    _check(load_library().gpe_timing_read(ctx, ctypes.byref(t)), ctx)
+    return {t.name[i].value.decode(): {"total_ms": t.total_ms[i], "launches": t.launches[i],
+                                       "bytes": t.bytes[i]} for i in range(t.count)}
+
+
+def gpe_device_bytes(ctx):
+    return load_library().gpe_device_bytes(ctx)
+
+
+def gpe_last_error(ctx):
+    return _err(ctx)
+
+
+def gpe_destroy(ctx):
+    load_library().gpe_destroy(ctx)
+
+
+# ------------------------------------------------------------- convenience ---
+
+OBS_KEYS = ("norm", "energy", "mu", "e_kin", "e_pot", "e_int",
+            "sigma_x", "sigma_y", "sigma_z", "r_rms")
+
+
+class Context:
+    """One solver instance on the current HIP device.
+
+    shape: grid points per axis (2 or 3 entries); lo, hi: box; g: interaction;
+    precision: "fp64" or "fp32"; V: FP64 array of `shape` or None; harmonic:
+    trap frequencies per axis (V = 1/2 sum w^2 x^2) or None; stream: a
+    hipStream_t handle (int) such as torch.cuda.current_stream().cuda_stream.
+    """
+
+    def __init__(self, shape, lo, hi, g, precision="fp64", norm_target=1.0,
+                 V=None, harmonic=None, stream=None):
+        dim = len(shape)
+        self.shape = tuple(int(s) for s in shape)
+        self.dim = dim
+        d = gpe_desc()
+        d.dim = dim
+        lo = np.broadcast_to(np.asarray(lo, np.float64), (dim,))
+        hi = np.broadcast_to(np.asarray(hi, np.float64), (dim,))
+        for j in range(dim):
+            d.n[j] = self.shape[j]
+            d.lo[j] = float(lo[j])
+            d.hi[j] = float(hi[j])
+        for j in range(dim, 3):
+            d.n[j] = 1
+        d.g = float(g)
+        d.precision = GPE_FP32 if precision == "fp32" else GPE_FP64
+        d.norm_target = float(norm_target)
+        self.precision = precision
+        self.desc = d
+        Vh = None
+        if V is not None:
+            Vh = np.ascontiguousarray(V, dtype=np.float64)
+            if Vh.shape != self.shape:
+                raise ValueError("V shape %s != %s" % (Vh.shape, self.shape))
+        an = None
+        if harmonic is not None:
+            an = gpe_harmonic()
+            for j in range(dim):
+                an.w[j] = float(harmonic[j])
+        self._ctx = None
+        self._ctx = gpe_create(d, Vh, an, ctypes.c_void_p(stream) if stream else None)
+
+    @property
+    def handle(self):
+        return self._ctx
+
+    def close(self):
+        if self._ctx is not None:
+            gpe_destroy(self._ctx)
+            self._ctx = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+    def __enter__(self):
+        return self
+
+    def __exit__(self, *a):
+        self.close()
+
+    def set_potential(self, V=None, harmonic=None):
+        Vh = np.ascontiguousarray(V, dtype=np.float64) if V is not None else None
+        an = None
+        if harmonic is not None:
+            an = gpe_harmonic()
+            for j in range(self.dim):
+                an.w[j] = float(harmonic[j])
+        gpe_set_potential(self._ctx, Vh, an)
+
+    def set_state(self, psi):
+        p = np.ascontiguousarray(psi, dtype=np.complex128)
+        if p.shape != self.shape:
+            raise ValueError("psi shape %s != %s" % (p.shape, self.shape))
+        gpe_set_state(self._ctx, p.view(np.float64))
+
+    def get_state(self):
+        out = np.empty(self.shape, np.complex128)
+        gpe_get_state(self._ctx, out.view(np.float64))
+        return out
+
+    def set_state_device(self, tensor):
+        """tensor: a contiguous torch complex128/complex64 CUDA tensor."""
+        src = GPE_FP32 if str(tensor.dtype) == "torch.complex64" else GPE_FP64
+        if tuple(tensor.shape) != self.shape or not tensor.is_contiguous():
+            raise ValueError("need a contiguous tensor of shape %s" % (self.shape,))
+        gpe_set_state_device(self._ctx, ctypes.c_void_p(tensor.data_ptr()), src)
+
+    def get_state_device(self, tensor):
+        dst = GPE_FP32 if str(tensor.dtype) == "torch.complex64" else GPE_FP64
+        if tuple(tensor.shape) != self.shape or not tensor.is_contiguous():
+            raise ValueError("need a contiguous tensor of shape %s" % (self.shape,))
+        gpe_get_state_device(self._ctx, ctypes.c_void_p(tensor.data_ptr()), dst)
+
+    def evolve(self, dt, nsteps):
+        gpe_evolve(self._ctx, dt, nsteps)
+
+    def ground_state(self, dt, tol=1e-10, check_every=10, max_steps=1000000):
+        st, steps, energy = gpe_ground_state(self._ctx, dt, tol, check_every, max_steps)
+        return steps, energy, st == GPE_OK
+
+    def imag_steps(self, dt, nsteps):
+        gpe_ground_state(self._ctx, dt, 0.0, 0, nsteps)
+
+    def observables(self):
+        o = gpe_obs()
+        gpe_observables(self._ctx, o, None)
+        vals = [o.norm, o.energy, o.mu, o.e_kin, o.e_pot, o.e_int,
+                o.sigma[0], o.sigma[1], o.sigma[2], o.r_rms]
+        return dict(zip(OBS_KEYS, vals))
+
+    def spectra(self):
+        nb = gpe_spectra_bins(self._ctx)
+        arrs = {k: np.zeros(nb) for k in ("n_k", "e_comp", "e_incomp", "e_qp")}
+        s = gpe_spectra()
+        s.nbins = nb
+        s.n_k = _dptr(arrs["n_k"])
+        s.e_comp = _dptr(arrs["e_comp"])
+        s.e_incomp = _dptr(arrs["e_incomp"])
+        s.e_qp = _dptr(arrs["e_qp"])
+        o = gpe_obs()
+        gpe_observables(self._ctx, o, s)
+        arrs["dk"] = s.dk
+        return arrs
+
+    def transform(self, axes=None, inverse=False):
+        mask = 0
+        for a in (range(self.dim) if axes is None else axes):
+            mask |= 1 << a
+        gpe_transform(self._ctx, mask, int(bool(inverse)))
+
+    def synchronize(self):
+        gpe_synchronize(self._ctx)
+
+    def timing(self, on=None):
+        if on is not None:
+            gpe_timing_enable(self._ctx, on)
+            return None
+        return gpe_timing_read(self._ctx)
+
+    def device_bytes(self):
+        return gpe_device_bytes(self._ctx)

@@ -1,0 +1,46 @@
+"""Host-side checks of the C-ABI library (no GPU needed, no compute calls)."""
+import os
+import re
+
+import pytest
+
+from paper_2301_08275_amd import gpe
+
+ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+
+
+def declared_functions():
+    text = open(os.path.join(ROOT, "include", "gpe.h")).read()
+    text = re.sub(r"/\*.*?\*/", "", text, flags=re.S)
+    names = re.findall(r"\b(gpe_[a-z_]+)\s*\(", text)
+    return sorted(set(names))
+
+
+def test_header_declares_the_boundary():
+    names = declared_functions()
+    for must in ("gpe_create", "gpe_evolve", "gpe_ground_state", "gpe_observables",
+                 "gpe_destroy", "gpe_last_error", "gpe_spectra_bins"):
+        assert must in names
+
+
+def test_library_exports_every_declared_symbol():
+    if not os.path.exists(gpe.LIB_PATH):
+        pytest.fail("libgpe.so is not built; run __graft_entry__.build() first")
+    lib = gpe.load_library()
+    for name in declared_functions():
+        assert hasattr(lib, name), name
+        assert name in gpe.SIGNATURES, name
+
+
+def test_binding_covers_exactly_the_header():
+    assert sorted(gpe.SIGNATURES) == declared_functions()
+
+
+def test_missing_library_fails_loudly(tmp_path):
+    with pytest.raises(RuntimeError):
+        gpe._lib_saved = gpe._lib
+        try:
+            gpe._lib = None
+            gpe.load_library(str(tmp_path / "nope.so"))
+        finally:
+            gpe._lib = gpe._lib_saved
