@@ -1,0 +1,630 @@
+// Fused per-axis TSSP pass for gfx950 (templates shared by the FP64 and FP32
+// translation units).
+//
+// The spectral step of the method (Numerical Scheme section: the kinetic
+// substep exp(-i |k|^2 dt/2) applied between a forward and an inverse DFT)
+// factors over axes because |k|^2 = sum_j k_j^2 and the d-dimensional DFT is
+// the product of one-dimensional DFTs along each axis.  One launch therefore
+// treats one axis completely: each workgroup loads whole lines along that
+// axis from HBM, optionally applies the real-space nonlinear/potential phase
+// (pre), runs the forward DFT of every line through registers and LDS,
+// multiplies by a per-frequency table (kinetic factor with 1/N, a spectral
+// derivative, ...), runs the inverse DFT, optionally applies the phase again
+// (post) and accumulates sums, and stores the lines back.  A 3D real-time step
+// is three such launches: 32 bytes of HBM traffic per site per launch in FP64.
+//
+// FFT: mixed-radix (2/4/8/16) Cooley-Tukey, decimation in frequency for the
+// forward transform (digit-reversed spectrum, never reordered) and the exact
+// reverse for the inverse, so the spectrum is used in place.  Each thread
+// holds E elements of one line; stages exchange through LDS.  Twiddles come
+// from an FP64-accurate table exp(-2 pi i j/N) built on the host per index.
+#pragma once
+
+#include "gpe_kernels.h"
+
+#include <cmath>
+
+// Build-time tuning knobs (the defaults are the measured best on MI355X).
+#ifndef GPE_CONTIG_THREADS
+#define GPE_CONTIG_THREADS 256  // workgroup size for the contiguous axis
+#endif
+#ifndef GPE_TW_POWERS
+#define GPE_TW_POWERS 1  // load w^(2^j), form the other twiddle powers by products
+#endif
+#ifndef GPE_WAVE_SYNC
+#define GPE_WAVE_SYNC 1  // lines held inside one wavefront sync without s_barrier
+#endif
+#ifndef GPE_FAST_SINCOS
+#define GPE_FAST_SINCOS 1  // Cody-Waite reduction + Taylor series for the phase
+#endif
+
+namespace gpe {
+namespace pass {
+
+template <typename T>
+struct alignas(2 * sizeof(T)) cx {
+  T x, y;
+};
+
+template <typename T>
+__device__ __forceinline__ cx<T> cadd(cx<T> a, cx<T> b) { return {a.x + b.x, a.y + b.y}; }
+template <typename T>
+__device__ __forceinline__ cx<T> csub(cx<T> a, cx<T> b) { return {a.x - b.x, a.y - b.y}; }
+template <typename T>
+__device__ __forceinline__ cx<T> cmul(cx<T> a, cx<T> b) {
+  return {a.x * b.x - a.y * b.y, a.x * b.y + a.y * b.x};
+}
+// a * conj(b)
+template <typename T>
+__device__ __forceinline__ cx<T> cmulc(cx<T> a, cx<T> b) {
+  return {a.x * b.x + a.y * b.y, a.y * b.x - a.x * b.y};
+}
+
+// v * exp(SIGN * 2 pi i k / 16); k is a constant once loops are unrolled.
+template <int SIGN, typename T>
+__device__ __forceinline__ cx<T> rot16(cx<T> v, int k) {
+  const T r = T(0.70710678118654752440);
+  const T c1 = T(0.92387953251128675613), s1 = T(0.38268343236508977173);
+  switch (k) {
+    case 0: return v;
+    case 1: return cmul(v, cx<T>{c1, SIGN * s1});
+    case 2: return {r * (v.x - SIGN * v.y), r * (v.y + SIGN * v.x)};
+    case 3: return cmul(v, cx<T>{s1, SIGN * c1});
+    case 4: return {-SIGN * v.y, SIGN * v.x};
+    case 5: return cmul(v, cx<T>{-s1, SIGN * c1});
+    case 6: return {-r * (v.x + SIGN * v.y), r * (SIGN * v.x - v.y)};
+    default: return cmul(v, cx<T>{-c1, SIGN * s1});
+  }
+}
+
+template <int R>
+__host__ __device__ constexpr int bitrev(int i) {
+  int r = 0;
+  for (int b = 1; b < R; b <<= 1) {
+    r = (r << 1) | (i & 1);
+    i >>= 1;
+  }
+  return r;
+}
+
+// In-register DFT of R <= 16 points, natural order in and out:
+// X[k] = sum_n x[n] exp(SIGN 2 pi i n k / R).  Radix-2 decimation in frequency.
+template <int R, int SIGN, typename T>
+__device__ __forceinline__ void dft(cx<T> *v) {
+#pragma unroll
+  for (int h = R / 2; h >= 1; h >>= 1) {
+#pragma unroll
+    for (int b = 0; b < R; b += 2 * h) {
+#pragma unroll
+      for (int j = 0; j < h; ++j) {
+        cx<T> a = v[b + j], c = v[b + j + h];
+        v[b + j] = cadd(a, c);
+        v[b + j + h] = rot16<SIGN>(csub(a, c), j * (16 / (2 * h)));
+      }
+    }
+  }
+  cx<T> t[R];
+#pragma unroll
+  for (int i = 0; i < R; ++i) t[i] = v[i];
+#pragma unroll
+  for (int i = 0; i < R; ++i) v[bitrev<R>(i)] = t[i];
+}
+
+// Plan: N = R0 R1 R2 R3 points per line, E elements per thread, every radix
+// divides E.  Stage s combines the elements whose position digit s differs:
+// positions p = (q mod st) + (q / st) st R + d st, st = N / (P(s) R(s)),
+// for butterfly q in [0, N/R) and digit d in [0, R).
+template <int N_, int E_, int R0, int R1 = 1, int R2 = 1, int R3 = 1>
+struct Plan {
+  static constexpr int N = N_, E = E_, TPL = N_ / E_;
+  static constexpr int M = (R1 == 1 ? 1 : (R2 == 1 ? 2 : (R3 == 1 ? 3 : 4)));
+  __host__ __device__ static constexpr int rad(int s) {
+    return s == 0 ? R0 : s == 1 ? R1 : s == 2 ? R2 : R3;
+  }
+  __host__ __device__ static constexpr int P(int s) {
+    int p = 1;
+    for (int i = 0; i < s; ++i) p *= rad(i);
+    return p;
+  }
+  __host__ __device__ static constexpr int stride(int s) { return N / (P(s) * rad(s)); }
+  __host__ __device__ static constexpr int pos(int s, int q, int d) {
+    return (q % stride(s)) + (q / stride(s)) * stride(s) * rad(s) + d * stride(s);
+  }
+  // Frequency held at position p after all forward stages (digit reversal).
+  __host__ __device__ static constexpr int freq(int p) {
+    int f = 0;
+    for (int s = 0; s < M; ++s) f += ((p / stride(s)) % rad(s)) * P(s);
+    return f;
+  }
+  static_assert(R0 * R1 * R2 * R3 == N_, "radices must multiply to N");
+  static_assert(E_ % R0 == 0 && E_ % R1 == 0 && E_ % R2 == 0 && E_ % R3 == 0,
+                "every radix divides E");
+};
+
+template <int N> struct PlanFor;
+template <> struct PlanFor<8> { using type = Plan<8, 8, 8>; };
+template <> struct PlanFor<16> { using type = Plan<16, 8, 8, 2>; };
+template <> struct PlanFor<32> { using type = Plan<32, 8, 8, 4>; };
+template <> struct PlanFor<64> { using type = Plan<64, 8, 8, 8>; };
+template <> struct PlanFor<128> { using type = Plan<128, 8, 8, 8, 2>; };
+template <> struct PlanFor<256> { using type = Plan<256, 8, 8, 8, 4>; };
+template <> struct PlanFor<512> { using type = Plan<512, 8, 8, 8, 8>; };
+template <> struct PlanFor<1024> { using type = Plan<1024, 16, 16, 8, 8>; };
+
+// LDS layout of a tile of W lines of N points (separate re and im planes).
+// Strided tiles are rows of W columns with one padding row after every eight
+// rows; contiguous lines get one padding slot per eight points.  For the
+// radix-8 exchange patterns these spread a wavefront's accesses over all banks
+// (no conflicts for strided tiles with 32 or 64 four-byte banks, FP64 or FP32).
+template <int N, int W, bool STRIDED>
+struct Lds {
+  static constexpr int line = N + N / 8;
+  static constexpr int size = STRIDED ? W * line : W * line;
+  __device__ static __forceinline__ int idx(int p, int c) {
+    return STRIDED ? W * (p + (p >> 3)) + c : c * line + p + (p >> 3);
+  }
+};
+
+__host__ __device__ constexpr int high_bit(int d) {
+  int h = 1;
+  while (h * 2 <= d) h *= 2;
+  return h;
+}
+
+// u[d] *= w^d (or conj(w^d)) for d = 1 .. R-1, w = exp(-2 pi i tb / N).  The
+// powers w^(2^j) come from the FP64-accurate table; the others are products of
+// at most log2(R) - 1 of them (a few ulp, not a long recurrence).
+template <int R, bool CONJ, typename T>
+__device__ __forceinline__ void twiddle(cx<T> *u, const cx<T> *__restrict__ tw, int tb) {
+#if GPE_TW_POWERS
+  cx<T> w[R];
+#pragma unroll
+  for (int d = 1; d < R; d *= 2) w[d] = tw[tb * d];
+#pragma unroll
+  for (int d = 3; d < R; ++d)
+    if (d & (d - 1)) w[d] = cmul(w[high_bit(d)], w[d - high_bit(d)]);
+#pragma unroll
+  for (int d = 1; d < R; ++d) u[d] = CONJ ? cmulc(u[d], w[d]) : cmul(u[d], w[d]);
+#else
+#pragma unroll
+  for (int d = 1; d < R; ++d) u[d] = CONJ ? cmulc(u[d], tw[tb * d]) : cmul(u[d], tw[tb * d]);
+#endif
+}
+
+// One forward (SIGN = -1: DFT then twiddle) or inverse (SIGN = +1: conjugate
+// twiddle then DFT) stage S on the thread's E registers.
+template <class PL, int S, int SIGN, typename T>
+__device__ __forceinline__ void stage(cx<T> *v, int t, const cx<T> *__restrict__ tw) {
+  constexpr int R = PL::rad(S), B = PL::E / R, ST = PL::stride(S), P = PL::P(S);
+#pragma unroll
+  for (int b = 0; b < B; ++b) {
+    const int q = t + PL::TPL * b;
+    cx<T> *u = v + b * R;
+    const int tb = P * (q % ST);
+    if (SIGN < 0) {
+      dft<R, -1>(u);
+      if (ST > 1) twiddle<R, false>(u, tw, tb);
+    } else {
+      if (ST > 1) twiddle<R, true>(u, tw, tb);
+      dft<R, +1>(u);
+    }
+  }
+}
+
+// Barrier between LDS writes and reads of an exchange.  When every line of the
+// tile lives inside one wavefront (contiguous axis, N/E <= 64 threads per line)
+// the wave's own in-order LDS queue suffices and only compiler ordering is
+// needed; otherwise the whole workgroup waits.
+template <class PL, int W, bool STRIDED>
+__device__ __forceinline__ void lds_sync() {
+  constexpr bool in_wave = GPE_WAVE_SYNC && (STRIDED ? PL::TPL * W <= 64 : PL::TPL <= 64);
+  if constexpr (in_wave) {
+    __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
+    __builtin_amdgcn_wave_barrier();
+    __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
+  } else {
+    __syncthreads();
+  }
+}
+
+// Move the E registers from the stage-A layout to the stage-B layout.
+template <class PL, int W, bool STRIDED, int A, int B, typename T>
+__device__ __forceinline__ void exchange(cx<T> *v, int t, int c, T *lre, T *lim,
+                                         bool first) {
+  using L = Lds<PL::N, W, STRIDED>;
+  constexpr int RA = PL::rad(A), RB = PL::rad(B);
+  if (!first) lds_sync<PL, W, STRIDED>();
+#pragma unroll
+  for (int b = 0; b < PL::E / RA; ++b)
+#pragma unroll
+    for (int d = 0; d < RA; ++d) {
+      const int i = L::idx(PL::pos(A, t + PL::TPL * b, d), c);
+      lre[i] = v[b * RA + d].x;
+      lim[i] = v[b * RA + d].y;
+    }
+  lds_sync<PL, W, STRIDED>();
+#pragma unroll
+  for (int b = 0; b < PL::E / RB; ++b)
+#pragma unroll
+    for (int d = 0; d < RB; ++d) {
+      const int i = L::idx(PL::pos(B, t + PL::TPL * b, d), c);
+      v[b * RB + d].x = lre[i];
+      v[b * RB + d].y = lim[i];
+    }
+}
+
+template <class PL, int W, bool STRIDED, typename T>
+__device__ __forceinline__ void forward_fft(cx<T> *v, int t, int c, T *lre, T *lim,
+                                            const cx<T> *tw) {
+  stage<PL, 0, -1>(v, t, tw);
+  if constexpr (PL::M > 1) {
+    exchange<PL, W, STRIDED, 0, 1>(v, t, c, lre, lim, true);
+    stage<PL, 1, -1>(v, t, tw);
+  }
+  if constexpr (PL::M > 2) {
+    exchange<PL, W, STRIDED, 1, 2>(v, t, c, lre, lim, false);
+    stage<PL, 2, -1>(v, t, tw);
+  }
+  if constexpr (PL::M > 3) {
+    exchange<PL, W, STRIDED, 2, 3>(v, t, c, lre, lim, false);
+    stage<PL, 3, -1>(v, t, tw);
+  }
+}
+
+template <class PL, int W, bool STRIDED, typename T>
+__device__ __forceinline__ void inverse_fft(cx<T> *v, int t, int c, T *lre, T *lim,
+                                            const cx<T> *tw, bool first) {
+  if constexpr (PL::M > 3) {
+    stage<PL, 3, +1>(v, t, tw);
+    exchange<PL, W, STRIDED, 3, 2>(v, t, c, lre, lim, first);
+    first = false;
+  }
+  if constexpr (PL::M > 2) {
+    stage<PL, 2, +1>(v, t, tw);
+    exchange<PL, W, STRIDED, 2, 1>(v, t, c, lre, lim, first);
+    first = false;
+  }
+  if constexpr (PL::M > 1) {
+    stage<PL, 1, +1>(v, t, tw);
+    exchange<PL, W, STRIDED, 1, 0>(v, t, c, lre, lim, first);
+  }
+  stage<PL, 0, +1>(v, t, tw);
+}
+
+__device__ __forceinline__ double site_potential(const PassArgs &a, int j0, int j1, int j2) {
+  if (a.vkind == V_NONE) return 0.0;
+  if (a.vkind == V_ARRAY) return a.V[((long long)j0 * a.n[1] + j1) * a.n[2] + j2];
+  const double x0 = a.lo[0] + j0 * a.h[0], x1 = a.lo[1] + j1 * a.h[1],
+               x2 = a.lo[2] + j2 * a.h[2];
+  return a.hv[0] * x0 * x0 + a.hv[1] * x1 * x1 + a.hv[2] * x2 * x2;
+}
+
+// sin and cos of x in FP64: Cody-Waite reduction x = n pi/2 + r with pi/2 split
+// in three parts (the first two with 33 significant bits, so n * part is exact
+// for |n| < 2^20), then the Taylor series of sin and cos on |r| <= pi/4 up to
+// degree 17 and 18 (truncation below 1e-19).  Arguments beyond 1e6 go to the
+// library routine.
+__device__ __forceinline__ void sincos_phase(double x, double *s, double *c) {
+#if GPE_FAST_SINCOS
+  if (!(fabs(x) < 1.0e6)) {
+    sincos(x, s, c);
+    return;
+  }
+  const double n = rint(x * 0.63661977236758134308);
+  double r = fma(-n, 0x1.921fb54400000p+0, x);
+  r = fma(-n, 0x1.0b4611a600000p-34, r);
+  r = fma(-n, 0x1.3198a2e037073p-69, r);
+  const double r2 = r * r;
+  double ps = 2.8114572543455206e-15;
+  ps = fma(ps, r2, -7.647163731819816e-13);
+  ps = fma(ps, r2, 1.6059043836821613e-10);
+  ps = fma(ps, r2, -2.505210838544172e-08);
+  ps = fma(ps, r2, 2.7557319223985893e-06);
+  ps = fma(ps, r2, -0.0001984126984126984);
+  ps = fma(ps, r2, 0.008333333333333333);
+  ps = fma(ps, r2, -0.16666666666666666);
+  ps = fma(ps * r2, r, r);
+  double pc = -1.5619206968586225e-16;
+  pc = fma(pc, r2, 4.779477332387385e-14);
+  pc = fma(pc, r2, -1.1470745597729725e-11);
+  pc = fma(pc, r2, 2.08767569878681e-09);
+  pc = fma(pc, r2, -2.755731922398589e-07);
+  pc = fma(pc, r2, 2.48015873015873e-05);
+  pc = fma(pc, r2, -0.001388888888888889);
+  pc = fma(pc, r2, 0.041666666666666664);
+  pc = fma(pc, r2, -0.5);
+  pc = fma(pc, r2, 1.0);
+  const int q = ((int)n) & 3;
+  const double ss = (q & 1) ? pc : ps, cc = (q & 1) ? ps : pc;
+  *s = (q & 2) ? -ss : ss;
+  *c = ((q + 1) & 2) ? -cc : cc;
+#else
+  sincos(x, s, c);
+#endif
+}
+
+// Nonlinear/potential phase in FP64 whatever the state precision.
+template <typename T>
+__device__ __forceinline__ cx<T> apply_phase(int op, cx<T> v, double V, double g,
+                                             double tau) {
+  const double re = (double)v.x, im = (double)v.y;
+  const double th = (V + g * (re * re + im * im)) * tau;
+  if (op == PH_REAL) {
+    double s, c;
+    sincos_phase(th, &s, &c);
+    return {(T)(re * c + im * s), (T)(im * c - re * s)};
+  }
+  const double f = exp(-th);
+  return {(T)(re * f), (T)(im * f)};
+}
+
+template <int NV>
+__device__ __forceinline__ void block_reduce_store(double (&acc)[NV], double *out,
+                                                   int slot0) {
+  __shared__ double red[16][NV];
+  const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+  const int nw = (blockDim.x + 63) >> 6;
+#pragma unroll
+  for (int k = 0; k < NV; ++k) {
+    double x = acc[k];
+#pragma unroll
+    for (int o = 32; o >= 1; o >>= 1) x += __shfl_xor(x, o, 64);
+    acc[k] = x;
+  }
+  if (lane == 0) {
+#pragma unroll
+    for (int k = 0; k < NV; ++k) red[wave][k] = acc[k];
+  }
+  __syncthreads();
+  if (threadIdx.x < NV) {
+    double s = 0;
+    for (int w = 0; w < nw; ++w) s += red[w][threadIdx.x];
+    out[(long long)blockIdx.x * kRedSlots + slot0 + threadIdx.x] = s;
+  }
+}
+
+// Compile-time operation sets of the hot passes; MODE_GENERIC reads them from
+// the arguments at run time.
+enum PassMode : int {
+  MODE_GENERIC = 0,
+  MODE_PLAIN = 1,          // forward, table, inverse
+  MODE_PRE_REAL = 2,       // real-time phase, forward, table, inverse
+  MODE_PRE_IMAG = 3,       // scale, imaginary-time phase, forward, table, inverse
+  MODE_POST_IMAG_RED = 4,  // forward, table, inverse, imaginary-time phase, norm sum
+};
+
+template <typename T, class PL, int W, bool STRIDED, int MODE>
+__global__ void __launch_bounds__(PL::TPL * W)
+axis_pass_kernel(const PassArgs a) {
+  constexpr int N = PL::N, E = PL::E, TPL = PL::TPL;
+  using L = Lds<N, W, STRIDED>;
+  __shared__ T lre[PL::M > 1 ? L::size : 1], lim[PL::M > 1 ? L::size : 1];
+
+  constexpr bool G = MODE == MODE_GENERIC;
+  const int forward = G ? a.forward : 1;
+  const int inverse = G ? a.inverse : 1;
+  const int store = G ? a.store : 1;
+  const int pre = G ? a.pre
+                    : (MODE == MODE_PRE_REAL ? PH_REAL : MODE == MODE_PRE_IMAG ? PH_IMAG : PH_NONE);
+  const int post = G ? a.post : (MODE == MODE_POST_IMAG_RED ? PH_IMAG : PH_NONE);
+  const int mid = G ? a.mid : MID_TABLE;
+  const int red = G ? a.red : (MODE == MODE_POST_IMAG_RED ? RED_NORM_OUT : RED_NONE);
+  const bool has_scale = G ? a.scale != nullptr : MODE == MODE_PRE_IMAG;
+
+  const int tid = threadIdx.x;
+  const int c = STRIDED ? (tid % W) : (tid / TPL);
+  const int t = STRIDED ? (tid / W) : (tid % TPL);
+  const int n1 = a.n[1], n2 = a.n[2];
+
+  // Line geometry: element p of this thread's line sits at base + p * S; its
+  // site coordinates are (j0, j1, j2) with the axis coordinate replaced by p.
+  long long base, S;
+  int j0 = 0, j1 = 0, j2 = 0;
+  bool valid = true;
+  if (!STRIDED) {
+    const long long line = (long long)blockIdx.x * W + c;
+    valid = !G || line < (long long)a.n[0] * n1;
+    j0 = (int)(line / n1);
+    j1 = (int)(line % n1);
+    base = line * N;
+    S = 1;
+  } else {
+    const int ct = n2 / W;
+    const int outer = blockIdx.x / ct;
+    j2 = (blockIdx.x % ct) * W + c;
+    if (a.axis == 1) {
+      j0 = outer;
+      base = (long long)outer * n1 * n2 + j2;
+      S = n2;
+    } else {
+      j1 = outer;
+      base = (long long)outer * n2 + j2;
+      S = (long long)n1 * n2;
+    }
+  }
+  const int axis = STRIDED ? a.axis : 2;
+
+  const cx<T> *__restrict__ src = static_cast<const cx<T> *>(a.src);
+  cx<T> *__restrict__ dst = static_cast<cx<T> *>(a.dst);
+  const cx<T> *__restrict__ tw = static_cast<const cx<T> *>(a.tw);
+  const cx<T> *__restrict__ mtab = static_cast<const cx<T> *>(a.mtab);
+  constexpr int R0 = PL::rad(0), RL = PL::rad(PL::M - 1);
+
+  double acc[kRedSlots];
+#pragma unroll
+  for (int k = 0; k < kRedSlots; ++k) acc[k] = 0;
+
+  cx<T> v[E];
+  if (forward) {
+#pragma unroll
+    for (int b = 0; b < E / R0; ++b)
+#pragma unroll
+      for (int d = 0; d < R0; ++d) {
+        const int p = PL::pos(0, t + TPL * b, d);
+        v[b * R0 + d] = valid ? src[base + p * S] : cx<T>{0, 0};
+      }
+    if (has_scale || pre != PH_NONE || (red & RED_REAL)) {
+      const double sc = has_scale ? *a.scale : 1.0;
+#pragma unroll
+      for (int b = 0; b < E / R0; ++b)
+#pragma unroll
+        for (int d = 0; d < R0; ++d) {
+          const int p = PL::pos(0, t + TPL * b, d);
+          const int k0 = axis == 0 ? p : j0, k1 = axis == 1 ? p : j1, k2 = axis == 2 ? p : j2;
+          cx<T> u = v[b * R0 + d];
+          if (has_scale) u = {(T)(sc * (double)u.x), (T)(sc * (double)u.y)};
+          const double V = (pre != PH_NONE || (red & RED_REAL)) && valid
+                               ? site_potential(a, k0, k1, k2) : 0.0;
+          if (red & RED_REAL) {
+            const double rho = (double)u.x * u.x + (double)u.y * u.y;
+            const double x0 = a.lo[0] + k0 * a.h[0], x1 = a.lo[1] + k1 * a.h[1],
+                         x2 = a.lo[2] + k2 * a.h[2];
+            acc[kSlotReal + 0] += rho;
+            acc[kSlotReal + 1] += V * rho;
+            acc[kSlotReal + 2] += rho * rho;
+            acc[kSlotReal + 3] += x0 * x0 * rho;
+            acc[kSlotReal + 4] += x1 * x1 * rho;
+            acc[kSlotReal + 5] += x2 * x2 * rho;
+          }
+          if (pre != PH_NONE) u = apply_phase(pre, u, V, a.g, a.tau_pre);
+          v[b * R0 + d] = u;
+        }
+    }
+    forward_fft<PL, W, STRIDED>(v, t, c, lre, lim, tw);
+  } else {
+    // Input is a spectrum in natural order: load it in the digit-reversed
+    // layout the inverse stages start from.
+#pragma unroll
+    for (int b = 0; b < E / RL; ++b)
+#pragma unroll
+      for (int d = 0; d < RL; ++d) {
+        const int p = PL::pos(PL::M - 1, t + TPL * b, d);
+        v[b * RL + d] = valid ? src[base + PL::freq(p) * S] : cx<T>{0, 0};
+      }
+  }
+
+  // Spectrum of this line: element (b, d) holds frequency freq(pos(M-1, q, d)).
+  if ((red & RED_KIN) || mid == MID_TABLE || !inverse) {
+#pragma unroll
+    for (int b = 0; b < E / RL; ++b)
+#pragma unroll
+      for (int d = 0; d < RL; ++d) {
+        const int f = PL::freq(PL::pos(PL::M - 1, t + TPL * b, d));
+        cx<T> u = v[b * RL + d];
+        if (red & RED_KIN) acc[kSlotKin] += a.kw[f] * ((double)u.x * u.x + (double)u.y * u.y);
+        if (mid == MID_TABLE) u = cmul(u, mtab[f]);
+        v[b * RL + d] = u;
+        if (!inverse && store && valid) dst[base + f * S] = u;
+      }
+  }
+
+  if (inverse) {
+    inverse_fft<PL, W, STRIDED>(v, t, c, lre, lim, tw, !forward);
+    if (post != PH_NONE || (red & RED_NORM_OUT)) {
+#pragma unroll
+      for (int b = 0; b < E / R0; ++b)
+#pragma unroll
+        for (int d = 0; d < R0; ++d) {
+          const int p = PL::pos(0, t + TPL * b, d);
+          cx<T> u = v[b * R0 + d];
+          if (post != PH_NONE) {
+            const int k0 = axis == 0 ? p : j0, k1 = axis == 1 ? p : j1, k2 = axis == 2 ? p : j2;
+            const double V = valid ? site_potential(a, k0, k1, k2) : 0.0;
+            u = apply_phase(post, u, V, a.g, a.tau_post);
+          }
+          if (red & RED_NORM_OUT) acc[kSlotNormOut] += (double)u.x * u.x + (double)u.y * u.y;
+          v[b * R0 + d] = u;
+        }
+    }
+    if (store && valid) {
+#pragma unroll
+      for (int b = 0; b < E / R0; ++b)
+#pragma unroll
+        for (int d = 0; d < R0; ++d) {
+          const int p = PL::pos(0, t + TPL * b, d);
+          dst[base + p * S] = v[b * R0 + d];
+        }
+    }
+  }
+
+  if (red) {
+    if (!valid) {
+#pragma unroll
+      for (int k = 0; k < kRedSlots; ++k) acc[k] = 0;
+    }
+    block_reduce_store(acc, a.partial, 0);
+  }
+}
+
+template <int N>
+constexpr int contig_lines() {
+  return PlanFor<N>::type::TPL >= GPE_CONTIG_THREADS ? 1
+                                                     : GPE_CONTIG_THREADS / PlanFor<N>::type::TPL;
+}
+
+// Columns per workgroup for a strided axis: the requested width, halved until
+// the N x W tile (two planes plus padding) fits the 160 KiB of LDS and the
+// workgroup has at most 1024 threads.
+__host__ __device__ constexpr int fit_w(int N, int esize, int W) {
+  const int tpl = N <= 512 ? N / 8 : N / 16;
+  while (W > 8 && (W * (N + N / 8) * esize > 160 * 1024 || tpl * W > 1024)) W /= 2;
+  return W;
+}
+
+template <typename T, class PL, int W, bool STRIDED>
+void launch_mode(const PassArgs &a, int mode, dim3 grid, dim3 block, hipStream_t s) {
+  switch (mode) {
+    case MODE_PLAIN:
+      hipLaunchKernelGGL((axis_pass_kernel<T, PL, W, STRIDED, MODE_PLAIN>), grid, block, 0, s, a);
+      break;
+    case MODE_PRE_REAL:
+      hipLaunchKernelGGL((axis_pass_kernel<T, PL, W, STRIDED, MODE_PRE_REAL>), grid, block, 0, s, a);
+      break;
+    case MODE_PRE_IMAG:
+      hipLaunchKernelGGL((axis_pass_kernel<T, PL, W, STRIDED, MODE_PRE_IMAG>), grid, block, 0, s, a);
+      break;
+    case MODE_POST_IMAG_RED:
+      hipLaunchKernelGGL((axis_pass_kernel<T, PL, W, STRIDED, MODE_POST_IMAG_RED>), grid, block, 0,
+                         s, a);
+      break;
+    default:
+      hipLaunchKernelGGL((axis_pass_kernel<T, PL, W, STRIDED, MODE_GENERIC>), grid, block, 0, s, a);
+  }
+}
+
+template <typename T, int N>
+hipError_t launch_n(const PassArgs &a, const PassShape &sh, int mode, hipStream_t s) {
+  using PL = typename PlanFor<N>::type;
+  const dim3 grid((unsigned)sh.blocks), block((unsigned)sh.threads);
+  constexpr int W16 = fit_w(N, (int)(2 * sizeof(T)), 16);
+  if (!sh.strided) {
+    launch_mode<T, PL, contig_lines<N>(), false>(a, mode, grid, block, s);
+  } else if (sh.W == 8) {
+    launch_mode<T, PL, 8, true>(a, mode, grid, block, s);
+  } else if (sh.W == 16 && W16 == 16) {
+    launch_mode<T, PL, (W16 == 16 ? 16 : 8), true>(a, mode, grid, block, s);
+  } else {
+    return hipErrorInvalidValue;
+  }
+  return hipGetLastError();
+}
+
+template <typename T>
+hipError_t launch_t(const PassArgs &a, const PassShape &sh, int mode, hipStream_t s) {
+  switch (sh.N) {
+    case 8: return launch_n<T, 8>(a, sh, mode, s);
+    case 16: return launch_n<T, 16>(a, sh, mode, s);
+    case 32: return launch_n<T, 32>(a, sh, mode, s);
+    case 64: return launch_n<T, 64>(a, sh, mode, s);
+    case 128: return launch_n<T, 128>(a, sh, mode, s);
+    case 256: return launch_n<T, 256>(a, sh, mode, s);
+    case 512: return launch_n<T, 512>(a, sh, mode, s);
+    case 1024: return launch_n<T, 1024>(a, sh, mode, s);
+    default: return hipErrorInvalidValue;
+  }
+}
+
+int tpl_of(int N);
+
+}  // namespace pass
+}  // namespace gpe

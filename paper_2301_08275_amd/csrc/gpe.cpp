@@ -70,6 +70,11 @@ struct gpe_ctx {
 
   std::string err;
   int pass_order[3] = {2, 1, 0};
+  // Strided columns per workgroup, per view axis (axis 2 is contiguous).  The
+  // slowest axis prefers 256-byte rows in both precisions; the middle axis is
+  // fastest with 128-byte rows in FP64 and 64-byte rows of 16 columns in FP32
+  // (measured at 512^3 on MI355X).
+  int wreq[3] = {16, 8, 8};
 };
 
 namespace {
@@ -210,6 +215,10 @@ gpe::PassArgs base_args(gpe_ctx *c, int vaxis) {
     a.h[j] = c->h3[j];
   }
   a.axis = vaxis;
+  a.wreq = c->wreq[vaxis];
+  a.vkind = c->V ? gpe::V_ARRAY
+                 : ((c->hv[0] != 0 || c->hv[1] != 0 || c->hv[2] != 0) ? gpe::V_HARMONIC
+                                                                      : gpe::V_NONE);
   a.forward = 1;
   a.inverse = 1;
   a.store = 1;
@@ -263,7 +272,7 @@ gpe_status launch_pass(gpe_ctx *c, const gpe::PassArgs &a) {
       HIPCHK(c, hipEventSynchronize(c->pending.back().second.second), "event sync");
       for (auto &pe : c->pending) {
         float ms = 0;
-        hipEventElapsedTime(&ms, pe.second.first, pe.second.second);
+        (void)hipEventElapsedTime(&ms, pe.second.first, pe.second.second);
         c->kinds[pe.first].total_ms += ms;
         c->kinds[pe.first].launches += 1;
         c->event_pool.push_back(pe.second);
@@ -279,7 +288,7 @@ gpe_status drain_timing(gpe_ctx *c) {
   HIPCHK(c, hipEventSynchronize(c->pending.back().second.second), "event sync");
   for (auto &pe : c->pending) {
     float ms = 0;
-    hipEventElapsedTime(&ms, pe.second.first, pe.second.second);
+    (void)hipEventElapsedTime(&ms, pe.second.first, pe.second.second);
     c->kinds[pe.first].total_ms += ms;
     c->kinds[pe.first].launches += 1;
     c->event_pool.push_back(pe.second);
@@ -373,7 +382,7 @@ gpe_status observe_sums(gpe_ctx *c, const double *scale, double host[3][gpe::kRe
     a.partial = c->partial + i * c->partial_region;
     gpe_status st = launch_pass(c, a);
     if (st != GPE_OK) return st;
-    const gpe::PassShape sh = gpe::pass_shape(c->prec, c->n3, ax);
+    const gpe::PassShape sh = gpe::pass_shape(c->prec, c->n3, ax, c->wreq[ax]);
     HIPCHK(c, gpe::launch_finalize(a.partial, sh.blocks, c->sums + i * gpe::kRedSlots,
                                    nullptr, 0, 1, c->stream), "finalize launch");
   }
@@ -435,6 +444,7 @@ gpe_status gpe_create(const gpe_desc *desc, const double *V_host, const gpe_harm
   c->dim = desc->dim;
   c->prec = desc->precision;
   c->esize = c->prec == GPE_FP32 ? 8 : 16;
+  if (c->prec == GPE_FP32) c->wreq[1] = 16;
   const int off = 3 - c->dim;
   c->sites = 1;
   c->dV = 1;
@@ -475,9 +485,12 @@ gpe_status gpe_create(const gpe_desc *desc, const double *V_host, const gpe_harm
   if ((st = dalloc(c, &c->psi, c->sites * c->esize, "state allocation")) != GPE_OK) return bail(st);
   if (hipMemset(c->psi, 0, c->sites * c->esize) != hipSuccess)
     return bail(fail(c, GPE_EDEVICE, "state clear"));
+  // Tuning overrides for experiments: strided workgroup widths per axis.
+  if (const char *w = std::getenv("GPE_TUNE_WX")) c->wreq[0] = std::atoi(w);
+  if (const char *w = std::getenv("GPE_TUNE_WY")) c->wreq[1] = std::atoi(w);
   long long maxb = 1;
   for (int ax = 3 - c->dim; ax < 3; ++ax) {
-    const gpe::PassShape sh = gpe::pass_shape(c->prec, c->n3, ax);
+    const gpe::PassShape sh = gpe::pass_shape(c->prec, c->n3, ax, c->wreq[ax]);
     if (sh.blocks > maxb) maxb = sh.blocks;
   }
   c->partial_region = maxb * gpe::kRedSlots;
@@ -639,7 +652,7 @@ gpe_status gpe_ground_state(gpe_ctx *c, double dt, double tol, int32_t check_eve
       gpe_status st = launch_pass(c, a);
       if (st != GPE_OK) return st;
       if (i == na - 1) {
-        const gpe::PassShape sh = gpe::pass_shape(c->prec, c->n3, ax);
+        const gpe::PassShape sh = gpe::pass_shape(c->prec, c->n3, ax, c->wreq[ax]);
         HIPCHK(c, gpe::launch_finalize(c->partial, sh.blocks, c->sums + 3 * gpe::kRedSlots,
                                        c->scale, c->desc.norm_target, c->dV, c->stream),
                "finalize launch");

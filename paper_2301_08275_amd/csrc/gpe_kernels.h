@@ -31,6 +31,8 @@ enum RedFlag : int {
 constexpr int kRedSlots = 8;  // partial[wg * kRedSlots + slot]
 constexpr int kSlotNormOut = 0, kSlotKin = 1, kSlotReal = 2;
 
+enum VKind : int { V_NONE = 0, V_ARRAY = 1, V_HARMONIC = 2 };
+
 struct PassArgs {
   const void *src;  // complex T, whole grid
   void *dst;        // complex T, whole grid (may equal src)
@@ -41,6 +43,8 @@ struct PassArgs {
   int store;        // 0: read-only pass (reductions only)
   int pre, post, mid, red;
   double tau_pre, tau_post, g;
+  int vkind;          // V_NONE, V_ARRAY (V below) or V_HARMONIC (hv below)
+  int wreq;           // columns per workgroup requested for a strided axis (8 or 16)
   const double *V;    // FP64 potential per site, or null
   double hv[3];       // analytic V = sum_j hv[j] x_j^2 when V is null
   double lo[3], h[3]; // coordinates x_j = lo[j] + i h[j] (3D indexing)
@@ -60,7 +64,7 @@ struct PassShape {
 };
 
 // Launch geometry the kernels are built for (must match the template choice).
-PassShape pass_shape(int precision, const int n[3], int axis);
+PassShape pass_shape(int precision, const int n[3], int axis, int wreq);
 
 // Launch one axis pass; precision 0 = FP64, 1 = FP32.
 hipError_t launch_axis_pass(int precision, const PassArgs &a, hipStream_t s);
