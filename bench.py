@@ -1,18 +1,27 @@
 #!/usr/bin/env python3
-"""Throughput of the TSSP step on one MI355X.
+"""Throughput of the TSSP solver on one MI355X.
 
-Workload (default): 3D quantum-turbulence grid, 512^3 sites on the periodic
-box [0, 2 pi)^3, V = 0, g = 1, psi = exp(i theta) with theta a seeded
-band-limited random phase (|m| <= 8, per-mode variance ~ |m|^-2), dt = 5e-4,
-FP64 state.  One step = one real-time TSSP step (three fused axis passes).
-The FP32 form of the same workload is timed in the same run.
+Workload (default): 3D quantum turbulence, 512^3 sites on the periodic box
+[0, 2 pi)^3, V = 0, g = 1, psi = exp(i theta) with theta a seeded
+band-limited random phase (integer modes 1 <= |m| <= 8, per-mode variance
+~ |m|^-2, rms |grad theta| = 1), dt = 5e-4, FP64 state.  A step is one
+real-time TSSP step (three fused axis passes); the particle-number,
+compressible, incompressible and quantum-pressure |k|-shell spectra are
+evaluated every 100 steps inside the timed region, as the workload asks.  The
+FP32 form of the same workload is timed in the same run.
 
 Prints ONE JSON line.  Inputs are resident in HBM before timing starts; the
-timed region is bracketed by device synchronisation and measured with HIP
-events on the library's stream.  The dominant kernel's average duration comes
-from per-launch HIP events inside the timed region.
+timed region is bracketed by device synchronisation and timed with HIP events
+recorded on the stream the library launches on.  The dominant kernel's
+average duration comes from per-launch HIP events inside the timed region.
+HBM traffic is taken from the committed rocprofv3 counter summary when it was
+made from the current kernel sources, else reported as null.
+
+--copy-calibration times a plain device copy of 2 GiB (the reference kernel
+for scaling the FETCH_SIZE / WRITE_SIZE counters) and exits.
 """
 import argparse
+import hashlib
 import json
 import os
 import sys
@@ -22,36 +31,99 @@ ROOT = os.path.dirname(os.path.abspath(__file__))
 sys.path.insert(0, ROOT)
 
 HBM_PEAK_GBS = 8000.0
+TRAFFIC_FILE = os.path.join(ROOT, "profiles", "traffic_step_512.json")
+KERNEL_SOURCES = ["axis_pass.h", "axis_pass.hip", "axis_pass_f64.hip", "axis_pass_f32.hip",
+                  "gpe_kernels.h"]
 
 
 def log(*a):
     print(*a, file=sys.stderr, flush=True)
 
 
-def time_run(ctx, torch, steps, warmup, dt):
+def kernel_hash():
+    h = hashlib.sha256()
+    for name in KERNEL_SOURCES:
+        with open(os.path.join(ROOT, "paper_2301_08275_amd", "csrc", name), "rb") as f:
+            h.update(f.read())
+    return h.hexdigest()[:16]
+
+
+def copy_calibration():
+    import torch
+
+    n = 1 << 27  # 2 GiB of FP64 complex
+    x = torch.zeros(2 * n, dtype=torch.float64, device="cuda")
+    y = torch.empty_like(x)
+    for _ in range(3):
+        y.copy_(x)
+    torch.cuda.synchronize()
+    e0 = torch.cuda.Event(enable_timing=True)
+    e1 = torch.cuda.Event(enable_timing=True)
+    e0.record()
+    reps = 10
+    for _ in range(reps):
+        y.copy_(x)
+    e1.record()
+    torch.cuda.synchronize()
+    ms = e0.elapsed_time(e1) / reps
+    nbytes = x.numel() * 8
+    print(json.dumps({"copy_bytes_read": nbytes, "copy_bytes_written": nbytes,
+                      "ms": ms, "GBps_read_plus_write": 2 * nbytes / ms / 1e6}), flush=True)
+
+
+def run_workload(ctx, torch, steps, warmup, dt, every, spectra):
     stream = torch.cuda.current_stream()
     ctx.evolve(dt, warmup)
+    if spectra:
+        ctx.spectra()
     torch.cuda.synchronize()
     ctx.timing(True)
     e0 = torch.cuda.Event(enable_timing=True)
     e1 = torch.cuda.Event(enable_timing=True)
     torch.cuda.synchronize()
     e0.record(stream)
-    ctx.evolve(dt, steps)
+    done, nspec = 0, 0
+    while done < steps:
+        chunk = min(every - done % every, steps - done)
+        ctx.evolve(dt, chunk)
+        done += chunk
+        if spectra and done % every == 0:
+            ctx.observables()
+            ctx.spectra()
+            nspec += 1
     e1.record(stream)
     torch.cuda.synchronize()
     ms = e0.elapsed_time(e1)
     kinds = ctx.timing()
     ctx.timing(False)
-    return ms, kinds
+    return ms, kinds, nspec
+
+
+def kernel_table(kinds):
+    out = {}
+    for k, v in kinds.items():
+        avg = v["total_ms"] / max(1, v["launches"])
+        out[k] = {"launches": v["launches"], "avg_ms": avg, "bytes": v["bytes"],
+                  "GBps": v["bytes"] / (avg * 1e-3) / 1e9}
+    return out
 
 
 def dominant(kinds):
     name = max(kinds, key=lambda k: kinds[k]["total_ms"])
     k = kinds[name]
     avg_ms = k["total_ms"] / max(1, k["launches"])
-    achieved = k["bytes"] / (avg_ms * 1e-3) / 1e9
-    return name, avg_ms, achieved, k["bytes"]
+    return name, avg_ms, k["bytes"] / (avg_ms * 1e-3) / 1e9, k["bytes"]
+
+
+def traffic_for(kernel):
+    if not os.path.exists(TRAFFIC_FILE):
+        return None
+    with open(TRAFFIC_FILE) as f:
+        t = json.load(f)
+    if t.get("kernel_hash") != kernel_hash():
+        return None
+    k = t.get("kernels", {}).get(kernel)
+    return k["hbm_bytes_per_launch"] if k else None
 
 
 def cpu_baseline(n, seed, steps=1):
@@ -66,8 +138,8 @@ def cpu_baseline(n, seed, steps=1):
     t = time.perf_counter() - t0
     return {"value": n ** 3 * steps / t, "unit": "site-steps/s", "cores": oracle.get_threads(),
             "kind": "oracle",
-            "sample": "%d real-time step(s) of the %d^3 FP64 workload (plain radix-2 oracle, "
-                      "%.1f s)" % (steps, n, t)}
+            "sample": "%d real-time TSSP step(s) of the %d^3 FP64 turbulence workload, no "
+                      "spectra (plain radix-2 C++ oracle, %.1f s)" % (steps, n, t)}
 
 
 def main():
@@ -76,31 +148,39 @@ def main():
     ap.add_argument("--steps", type=int, default=200)
     ap.add_argument("--warmup", type=int, default=20)
     ap.add_argument("--n", type=int, default=512)
+    ap.add_argument("--spectra-every", type=int, default=100)
+    ap.add_argument("--no-spectra", action="store_true")
     ap.add_argument("--no-cpu", action="store_true")
     ap.add_argument("--no-fp32", action="store_true")
+    ap.add_argument("--copy-calibration", action="store_true")
     args = ap.parse_args()
     if args.gpus != 1:
-        print("bench.py measures one GPU only: this build has no multi-GPU path "
+        print("bench.py measures one GPU: this build has no multi-GPU path "
               "(run with --gpus 1)", file=sys.stderr)
         sys.exit(2)
 
     import torch
 
+    torch.cuda.set_device(0)
+    if args.copy_calibration:
+        copy_calibration()
+        return
+    # a dedicated stream at default priority: the library enqueues on it and
+    # the timing events are recorded on it
+    torch.cuda.set_stream(torch.cuda.Stream())
+
     from paper_2301_08275_amd import gpe
     from paper_2301_08275_amd import inputs as I
 
-    torch.cuda.set_device(0)
-    # a dedicated stream (default priority): the library enqueues on it and the
-    # timing events are recorded on it
-    torch.cuda.set_stream(torch.cuda.Stream())
     n, seed, dt, g = args.n, 2, 5e-4, 1.0
     lo, hi = (0.0,) * 3, (2 * 3.141592653589793,) * 3
-    log("generating %d^3 phase field" % n)
+    log("generating the %d^3 phase field" % n)
     psi0 = I.phase_field(n, seed)
     dev = torch.from_numpy(psi0).to("cuda")
     del psi0
     stream = torch.cuda.current_stream().cuda_stream
     sites = n ** 3
+    spectra = not args.no_spectra
 
     results = {}
     for prec in (["fp64"] if args.no_fp32 else ["fp64", "fp32"]):
@@ -108,9 +188,9 @@ def main():
         ctx = gpe.Context((n, n, n), lo, hi, g, precision=prec,
                           norm_target=(2 * 3.141592653589793) ** 3, stream=stream)
         ctx.set_state_device(dev)
-        ms, kinds = time_run(ctx, torch, args.steps, args.warmup, dt)
-        name, avg_ms, achieved, bytes_per = dominant(kinds)
-        results[prec] = dict(ms=ms, kinds=kinds, dom=(name, avg_ms, achieved, bytes_per))
+        ms, kinds, nspec = run_workload(ctx, torch, args.steps, args.warmup, dt,
+                                        args.spectra_every, spectra)
+        results[prec] = dict(ms=ms, kinds=kinds, nspec=nspec, dom=dominant(kinds))
         ctx.close()
         torch.cuda.synchronize()
     del dev
@@ -120,6 +200,8 @@ def main():
     ms_step = r64["ms"] / args.steps
     value = sites * args.steps / (r64["ms"] * 1e-3)
     name, avg_ms, achieved, bytes_per = r64["dom"]
+    step_kinds = {k: v for k, v in r64["kinds"].items() if k.startswith("step_")}
+    step_ms = sum(v["total_ms"] for v in step_kinds.values()) / args.steps
     out = {
         "metric": "TSSP site-steps/s at 512^3 FP64 vs FP32; % HBM roofline; p50/p99 solve latency",
         "value": value,
@@ -134,27 +216,30 @@ def main():
         "dtype": "f64",
         "data": "synthetic",
         "config": {"workload": "3D quantum turbulence, %d^3 periodic box [0,2pi)^3, V=0, g=1, "
-                               "psi=exp(i theta) seeded random phase (|m|<=8, ~k^-2), dt=5e-4, "
-                               "real-time TSSP" % n,
+                               "psi=exp(i theta), seeded random phase |m|<=8 ~|m|^-2, dt=5e-4, "
+                               "real-time TSSP, shell spectra every %d steps"
+                               % (n, args.spectra_every),
                    "grid": [n, n, n], "sites": sites, "dt": dt, "g": g,
-                   "passes_per_step": 3},
+                   "spectra_evaluations": r64["nspec"], "passes_per_step": 3},
         "roofline": {"bound": "hbm", "achieved": achieved, "peak": HBM_PEAK_GBS, "unit": "GB/s",
-                     "frac": achieved / HBM_PEAK_GBS, "traffic": None,
+                     "frac": achieved / HBM_PEAK_GBS, "traffic": traffic_for(name),
                      "kernel": name, "avg_launch_ms": avg_ms, "bytes_per_launch": bytes_per},
-        "kernels": {k: {"avg_ms": v["total_ms"] / max(1, v["launches"]),
-                        "GBps": v["bytes"] / (v["total_ms"] / max(1, v["launches"]) * 1e-3) / 1e9}
-                    for k, v in r64["kinds"].items()},
+        "stepping_only": {"ms_per_step": step_ms, "site_steps_per_s": sites / (step_ms * 1e-3),
+                          "hbm_GBps_at_96B_per_site_step":
+                              96.0 * sites / (step_ms * 1e-3) / 1e9},
+        "kernels": kernel_table(r64["kinds"]),
     }
-    step_bytes = sum(v["bytes"] for v in r64["kinds"].values())
-    out["step_hbm_frac"] = step_bytes / (ms_step * 1e-3) / 1e9 / HBM_PEAK_GBS
     if "fp32" in results:
         r32 = results["fp32"]
         v32 = sites * args.steps / (r32["ms"] * 1e-3)
         n32, a32, ach32, b32 = r32["dom"]
+        s32 = sum(v["total_ms"] for k, v in r32["kinds"].items() if k.startswith("step_"))
         out["fp32"] = {"value": v32, "ms_per_step": r32["ms"] / args.steps,
                        "speedup_vs_fp64": v32 / value,
+                       "stepping_only_ms_per_step": s32 / args.steps,
                        "dominant_kernel": n32, "achieved_GBps": ach32,
-                       "frac": ach32 / HBM_PEAK_GBS}
+                       "frac": ach32 / HBM_PEAK_GBS,
+                       "kernels": kernel_table(r32["kinds"])}
     if not args.no_cpu:
         log("timing the CPU oracle")
         out["cpu_baseline"] = cpu_baseline(n, seed)

@@ -98,13 +98,17 @@ typedef struct {
   double *n_k, *e_comp, *e_incomp, *e_qp;
 } gpe_spectra;
 
-/* Per-kernel-kind timing collected with HIP events while enabled. */
+/* Per-kernel-kind timing collected with HIP events while enabled.  A kind is
+ * an operation on one axis ("step_x_fp64": fused TSSP pass along x; "fft_",
+ * "obs_", "deriv_", "ifft_": the forward, read-only, derivative and inverse
+ * passes used by observables, spectra and transforms). */
+#define GPE_TIMING_KINDS 16
 typedef struct {
-  int32_t count;          /* number of kinds reported */
-  char name[8][32];       /* kind names, e.g. "pass_x_fp64" */
-  double total_ms[8];     /* summed event time */
-  int64_t launches[8];    /* launches timed */
-  double bytes[8];        /* algorithmic HBM bytes per launch */
+  int32_t count;                       /* number of kinds reported */
+  char name[GPE_TIMING_KINDS][32];     /* kind names */
+  double total_ms[GPE_TIMING_KINDS];   /* summed event time */
+  int64_t launches[GPE_TIMING_KINDS];  /* launches timed */
+  double bytes[GPE_TIMING_KINDS];      /* algorithmic HBM bytes per launch */
 } gpe_timing;
 
 /* Create a context: validates desc, allocates the state and work buffers on

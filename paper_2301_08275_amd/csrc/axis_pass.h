@@ -34,6 +34,12 @@
 #ifndef GPE_WAVE_SYNC
 #define GPE_WAVE_SYNC 1  // lines held inside one wavefront sync without s_barrier
 #endif
+#ifndef GPE_FP32_TW_HILO
+#define GPE_FP32_TW_HILO 1  // FP32 twiddles applied as hi + lo pairs (else hi, powers by products)
+#endif
+#ifndef GPE_FP32_K_HILO
+#define GPE_FP32_K_HILO 1  // FP32 per-frequency factors applied as hi + lo pairs
+#endif
 #ifndef GPE_FAST_SINCOS
 #define GPE_FAST_SINCOS 1  // Cody-Waite reduction + Taylor series for the phase
 #endif
@@ -45,6 +51,16 @@ template <typename T>
 struct alignas(2 * sizeof(T)) cx {
   T x, y;
 };
+
+// Table entries: FP64 tables hold the complex factor.  FP32 tables hold it as
+// a hi + lo pair of FP32 complex numbers (x, y = hi; z, w = lo), and the
+// product is formed by one chain of FMAs before a single rounding, so every
+// twiddle and kinetic factor is unit-modulus to ~1e-14: a plainly rounded
+// FP32 factor is off by up to 6e-8 in modulus, the same way every step, and
+// the norm would drift linearly.
+template <typename T> struct TabOf { using type = cx<T>; };
+template <> struct TabOf<float> { using type = float4; };
+template <typename T> using tab_t = typename TabOf<T>::type;
 
 template <typename T>
 __device__ __forceinline__ cx<T> cadd(cx<T> a, cx<T> b) { return {a.x + b.x, a.y + b.y}; }
@@ -60,20 +76,66 @@ __device__ __forceinline__ cx<T> cmulc(cx<T> a, cx<T> b) {
   return {a.x * b.x + a.y * b.y, a.y * b.x - a.x * b.y};
 }
 
-// v * exp(SIGN * 2 pi i k / 16); k is a constant once loops are unrolled.
+// u * w (or u * conj(w)) with w = (e.x + e.z) + i (e.y + e.w) given as an FP32
+// hi + lo pair; the lo products are added first, then the hi products, each
+// component rounded once at the end of its FMA chain.
+template <bool CONJ>
+__device__ __forceinline__ cx<float> cmul_hl(cx<float> u, const float4 &e) {
+  if (CONJ) {
+    const float re = fmaf(u.x, e.x, fmaf(u.y, e.y, fmaf(u.x, e.z, u.y * e.w)));
+    const float im = fmaf(u.y, e.x, fmaf(-u.x, e.y, fmaf(u.y, e.z, -u.x * e.w)));
+    return {re, im};
+  }
+  const float re = fmaf(u.x, e.x, fmaf(-u.y, e.y, fmaf(u.x, e.z, -u.y * e.w)));
+  const float im = fmaf(u.x, e.y, fmaf(u.y, e.x, fmaf(u.x, e.w, u.y * e.z)));
+  return {re, im};
+}
+
+// v * exp(SIGN * 2 pi i k / 16); k is a constant once loops are unrolled.  In
+// FP32 the irrational constants are applied as hi + lo pairs, so the rotation
+// has unit modulus to well below FP32 rounding (a plain FP32 sqrt(1/2) has
+// 2 r^2 = 1 - 3.4e-8, a bias that would accumulate step after step).
 template <int SIGN, typename T>
 __device__ __forceinline__ cx<T> rot16(cx<T> v, int k) {
-  const T r = T(0.70710678118654752440);
-  const T c1 = T(0.92387953251128675613), s1 = T(0.38268343236508977173);
-  switch (k) {
-    case 0: return v;
-    case 1: return cmul(v, cx<T>{c1, SIGN * s1});
-    case 2: return {r * (v.x - SIGN * v.y), r * (v.y + SIGN * v.x)};
-    case 3: return cmul(v, cx<T>{s1, SIGN * c1});
-    case 4: return {-SIGN * v.y, SIGN * v.x};
-    case 5: return cmul(v, cx<T>{-s1, SIGN * c1});
-    case 6: return {-r * (v.x + SIGN * v.y), r * (SIGN * v.x - v.y)};
-    default: return cmul(v, cx<T>{-c1, SIGN * s1});
+  if constexpr (sizeof(T) == 8) {
+    const T r = T(0.70710678118654752440);
+    const T c1 = T(0.92387953251128675613), s1 = T(0.38268343236508977173);
+    switch (k) {
+      case 0: return v;
+      case 1: return cmul(v, cx<T>{c1, SIGN * s1});
+      case 2: return {r * (v.x - SIGN * v.y), r * (v.y + SIGN * v.x)};
+      case 3: return cmul(v, cx<T>{s1, SIGN * c1});
+      case 4: return {-SIGN * v.y, SIGN * v.x};
+      case 5: return cmul(v, cx<T>{-s1, SIGN * c1});
+      case 6: return {-r * (v.x + SIGN * v.y), r * (SIGN * v.x - v.y)};
+      default: return cmul(v, cx<T>{-c1, SIGN * s1});
+    }
+  } else {
+    const float rh = 0x1.6a09e6p-1f, rl = 1.2101617485882343e-08f;
+    const float ch = 0x1.d906bcp-1f, cl = 2.830748968563057e-08f;
+    const float sh = 0x1.87de2ap-2f, sl = 6.2233507236442165e-09f;
+    auto cm2 = [](cx<float> a, float xh, float xl, float yh, float yl) {
+      // a * ((xh + xl) + i (yh + yl))
+      const float re = fmaf(a.x, xh, fmaf(a.x, xl, -fmaf(a.y, yh, a.y * yl)));
+      const float im = fmaf(a.x, yh, fmaf(a.x, yl, fmaf(a.y, xh, a.y * xl)));
+      return cx<float>{re, im};
+    };
+    switch (k) {
+      case 0: return v;
+      case 1: return cm2(v, ch, cl, SIGN * sh, SIGN * sl);
+      case 2: {
+        const float a = v.x - SIGN * v.y, b = v.y + SIGN * v.x;
+        return {fmaf(rh, a, rl * a), fmaf(rh, b, rl * b)};
+      }
+      case 3: return cm2(v, sh, sl, SIGN * ch, SIGN * cl);
+      case 4: return {-SIGN * v.y, SIGN * v.x};
+      case 5: return cm2(v, -sh, -sl, SIGN * ch, SIGN * cl);
+      case 6: {
+        const float a = -(v.x + SIGN * v.y), b = SIGN * v.x - v.y;
+        return {fmaf(rh, a, rl * a), fmaf(rh, b, rl * b)};
+      }
+      default: return cm2(v, -ch, -cl, SIGN * sh, SIGN * sl);
+    }
   }
 }
 
@@ -171,30 +233,58 @@ __host__ __device__ constexpr int high_bit(int d) {
   return h;
 }
 
-// u[d] *= w^d (or conj(w^d)) for d = 1 .. R-1, w = exp(-2 pi i tb / N).  The
-// powers w^(2^j) come from the FP64-accurate table; the others are products of
-// at most log2(R) - 1 of them (a few ulp, not a long recurrence).
+// The leading (hi) part of a table entry.
+template <typename T>
+__device__ __forceinline__ cx<T> tab_hi(const tab_t<T> &e) {
+  if constexpr (sizeof(T) == 4) return cx<T>{e.x, e.y};
+  else return e;
+}
+
+// u[d] *= w^d (or conj(w^d)) for d = 1 .. R-1, w = exp(-2 pi i tb / N).  FP64:
+// the powers w^(2^j) come from the FP64-accurate table and the others are
+// products of at most log2(R) - 1 of them (a few ulp, not a long recurrence).
+// FP32: every power is read from the hi + lo table.
 template <int R, bool CONJ, typename T>
-__device__ __forceinline__ void twiddle(cx<T> *u, const cx<T> *__restrict__ tw, int tb) {
+__device__ __forceinline__ void twiddle(cx<T> *u, const tab_t<T> *__restrict__ tw, int tb) {
+  if constexpr (sizeof(T) == 4 && GPE_FP32_TW_HILO) {
+#pragma unroll
+    for (int d = 1; d < R; ++d) {
+      u[d] = cmul_hl<CONJ>(u[d], tw[tb * d]);
+    }
+  } else {
 #if GPE_TW_POWERS
-  cx<T> w[R];
+    cx<T> w[R];
 #pragma unroll
-  for (int d = 1; d < R; d *= 2) w[d] = tw[tb * d];
+    for (int d = 1; d < R; d *= 2) w[d] = tab_hi<T>(tw[tb * d]);
 #pragma unroll
-  for (int d = 3; d < R; ++d)
-    if (d & (d - 1)) w[d] = cmul(w[high_bit(d)], w[d - high_bit(d)]);
+    for (int d = 3; d < R; ++d)
+      if (d & (d - 1)) w[d] = cmul(w[high_bit(d)], w[d - high_bit(d)]);
 #pragma unroll
-  for (int d = 1; d < R; ++d) u[d] = CONJ ? cmulc(u[d], w[d]) : cmul(u[d], w[d]);
+    for (int d = 1; d < R; ++d) u[d] = CONJ ? cmulc(u[d], w[d]) : cmul(u[d], w[d]);
 #else
 #pragma unroll
-  for (int d = 1; d < R; ++d) u[d] = CONJ ? cmulc(u[d], tw[tb * d]) : cmul(u[d], tw[tb * d]);
+    for (int d = 1; d < R; ++d)
+      u[d] = CONJ ? cmulc(u[d], tab_hi<T>(tw[tb * d])) : cmul(u[d], tab_hi<T>(tw[tb * d]));
 #endif
+  }
+}
+
+// Multiply by a per-frequency table entry.
+template <typename T>
+__device__ __forceinline__ cx<T> table_mul(cx<T> u, const tab_t<T> &e) {
+  if constexpr (sizeof(T) == 4 && GPE_FP32_K_HILO) {
+    return cmul_hl<false>(u, e);
+  } else if constexpr (sizeof(T) == 4) {
+    return cmul(u, cx<T>{e.x, e.y});
+  } else {
+    return cmul(u, e);
+  }
 }
 
 // One forward (SIGN = -1: DFT then twiddle) or inverse (SIGN = +1: conjugate
 // twiddle then DFT) stage S on the thread's E registers.
 template <class PL, int S, int SIGN, typename T>
-__device__ __forceinline__ void stage(cx<T> *v, int t, const cx<T> *__restrict__ tw) {
+__device__ __forceinline__ void stage(cx<T> *v, int t, const tab_t<T> *__restrict__ tw) {
   constexpr int R = PL::rad(S), B = PL::E / R, ST = PL::stride(S), P = PL::P(S);
 #pragma unroll
   for (int b = 0; b < B; ++b) {
@@ -255,7 +345,7 @@ __device__ __forceinline__ void exchange(cx<T> *v, int t, int c, T *lre, T *lim,
 
 template <class PL, int W, bool STRIDED, typename T>
 __device__ __forceinline__ void forward_fft(cx<T> *v, int t, int c, T *lre, T *lim,
-                                            const cx<T> *tw) {
+                                            const tab_t<T> *tw) {
   stage<PL, 0, -1>(v, t, tw);
   if constexpr (PL::M > 1) {
     exchange<PL, W, STRIDED, 0, 1>(v, t, c, lre, lim, true);
@@ -273,7 +363,7 @@ __device__ __forceinline__ void forward_fft(cx<T> *v, int t, int c, T *lre, T *l
 
 template <class PL, int W, bool STRIDED, typename T>
 __device__ __forceinline__ void inverse_fft(cx<T> *v, int t, int c, T *lre, T *lim,
-                                            const cx<T> *tw, bool first) {
+                                            const tab_t<T> *tw, bool first) {
   if constexpr (PL::M > 3) {
     stage<PL, 3, +1>(v, t, tw);
     exchange<PL, W, STRIDED, 3, 2>(v, t, c, lre, lim, first);
@@ -430,8 +520,13 @@ axis_pass_kernel(const PassArgs a) {
     S = 1;
   } else {
     const int ct = n2 / W;
-    const int outer = blockIdx.x / ct;
-    j2 = (blockIdx.x % ct) * W + c;
+    // Workgroups are dealt to the 8 XCDs round-robin; with xcd_remap each XCD
+    // takes a contiguous run of tiles instead (same tiles, other order).
+    int tile = blockIdx.x;
+    if (a.xcd_remap && (gridDim.x & 7) == 0)
+      tile = (blockIdx.x & 7) * (gridDim.x >> 3) + (blockIdx.x >> 3);
+    const int outer = tile / ct;
+    j2 = (tile % ct) * W + c;
     if (a.axis == 1) {
       j0 = outer;
       base = (long long)outer * n1 * n2 + j2;
@@ -446,8 +541,8 @@ axis_pass_kernel(const PassArgs a) {
 
   const cx<T> *__restrict__ src = static_cast<const cx<T> *>(a.src);
   cx<T> *__restrict__ dst = static_cast<cx<T> *>(a.dst);
-  const cx<T> *__restrict__ tw = static_cast<const cx<T> *>(a.tw);
-  const cx<T> *__restrict__ mtab = static_cast<const cx<T> *>(a.mtab);
+  const tab_t<T> *__restrict__ tw = static_cast<const tab_t<T> *>(a.tw);
+  const tab_t<T> *__restrict__ mtab = static_cast<const tab_t<T> *>(a.mtab);
   constexpr int R0 = PL::rad(0), RL = PL::rad(PL::M - 1);
 
   double acc[kRedSlots];
@@ -512,7 +607,7 @@ axis_pass_kernel(const PassArgs a) {
         const int f = PL::freq(PL::pos(PL::M - 1, t + TPL * b, d));
         cx<T> u = v[b * RL + d];
         if (red & RED_KIN) acc[kSlotKin] += a.kw[f] * ((double)u.x * u.x + (double)u.y * u.y);
-        if (mid == MID_TABLE) u = cmul(u, mtab[f]);
+        if (mid == MID_TABLE) u = table_mul(u, mtab[f]);
         v[b * RL + d] = u;
         if (!inverse && store && valid) dst[base + f * S] = u;
       }
@@ -527,7 +622,14 @@ axis_pass_kernel(const PassArgs a) {
         for (int d = 0; d < R0; ++d) {
           const int p = PL::pos(0, t + TPL * b, d);
           cx<T> u = v[b * R0 + d];
-          if (post != PH_NONE) {
+          if (post == PH_DERIV) {
+            // combine the derivative with the state at this site (re-read)
+            const cx<T> q = valid ? src[base + p * S] : cx<T>{0, 0};
+            const double qr = q.x, qi = q.y, dr = u.x, di = u.y;
+            const double mag = sqrt(qr * qr + qi * qi);
+            const double zr = qr * dr + qi * di, zi = qr * di - qi * dr;  // conj(q) d
+            u = mag > 0 ? cx<T>{(T)(zi / mag), (T)(zr / mag)} : cx<T>{0, 0};
+          } else if (post != PH_NONE) {
             const int k0 = axis == 0 ? p : j0, k1 = axis == 1 ? p : j1, k2 = axis == 2 ? p : j2;
             const double V = valid ? site_potential(a, k0, k1, k2) : 0.0;
             u = apply_phase(post, u, V, a.g, a.tau_post);

@@ -52,6 +52,9 @@ struct gpe_ctx {
   int device = 0;
 
   void *psi = nullptr;
+  void *work[3] = {nullptr, nullptr, nullptr};  // spectra work fields (allocated on demand)
+  double *hist_partial = nullptr;  // shell histograms per workgroup
+  double *hist = nullptr;          // 8 x nbins finalized shell sums
   double *V = nullptr;         // FP64 potential array (device) or null
   double hv[3] = {0, 0, 0};    // analytic V coefficients (3D view)
   double *partial = nullptr;   // per-workgroup partials, 3 regions
@@ -75,6 +78,9 @@ struct gpe_ctx {
   // fastest with 128-byte rows in FP64 and 64-byte rows of 16 columns in FP32
   // (measured at 512^3 on MI355X).
   int wreq[3] = {16, 8, 8};
+  // Strided passes hand each XCD a contiguous run of tiles (measured: a few
+  // percent faster at 512^3 than the default round-robin order).
+  int xcd_remap[3] = {1, 1, 0};
 };
 
 namespace {
@@ -116,22 +122,27 @@ double wavenumber(const gpe_ctx *c, int vaxis, long i) {
   return 2 * kPi * (double)signed_mode(i, c->n3[vaxis]) / c->L3[vaxis];
 }
 
-// Host FP64 tables, rounded to the state precision on upload.
+// Host FP64 tables uploaded in the state precision, 16 bytes per entry either
+// way: FP64 (re, im), or FP32 (re_hi, im_hi, re_lo, im_lo) with hi the FP32
+// rounding of the FP64 value and lo the FP32 rounding of the remainder.
 gpe_status upload_complex(gpe_ctx *c, void **dst, const std::vector<double> &re,
                           const std::vector<double> &im) {
   const size_t n = re.size();
   std::vector<double> d(2 * n);
-  std::vector<float> f(2 * n);
+  std::vector<float> f(4 * n);
   for (size_t i = 0; i < n; ++i) {
     d[2 * i] = re[i];
     d[2 * i + 1] = im[i];
-    f[2 * i] = (float)re[i];
-    f[2 * i + 1] = (float)im[i];
+    const float rh = (float)re[i], ih = (float)im[i];
+    f[4 * i] = rh;
+    f[4 * i + 1] = ih;
+    f[4 * i + 2] = (float)(re[i] - (double)rh);
+    f[4 * i + 3] = (float)(im[i] - (double)ih);
   }
-  gpe_status st = dalloc(c, dst, n * c->esize, "table allocation");
+  gpe_status st = dalloc(c, dst, n * 16, "table allocation");
   if (st != GPE_OK) return st;
-  HIPCHK(c, hipMemcpy(*dst, c->prec == 1 ? (void *)f.data() : (void *)d.data(),
-                      n * c->esize, hipMemcpyHostToDevice), "table upload");
+  HIPCHK(c, hipMemcpy(*dst, c->prec == 1 ? (void *)f.data() : (void *)d.data(), n * 16,
+                      hipMemcpyHostToDevice), "table upload");
   return GPE_OK;
 }
 
@@ -216,6 +227,7 @@ gpe::PassArgs base_args(gpe_ctx *c, int vaxis) {
   }
   a.axis = vaxis;
   a.wreq = c->wreq[vaxis];
+  a.xcd_remap = (vaxis != 2 && c->xcd_remap[vaxis]) ? 1 : 0;
   a.vkind = c->V ? gpe::V_ARRAY
                  : ((c->hv[0] != 0 || c->hv[1] != 0 || c->hv[2] != 0) ? gpe::V_HARMONIC
                                                                       : gpe::V_NONE);
@@ -228,10 +240,15 @@ gpe::PassArgs base_args(gpe_ctx *c, int vaxis) {
   return a;
 }
 
-const char *kind_name(int prec, int vaxis) {
-  static const char *names[2][3] = {{"pass_x_fp64", "pass_y_fp64", "pass_z_fp64"},
-                                    {"pass_x_fp32", "pass_y_fp32", "pass_z_fp32"}};
-  return names[prec][vaxis];
+// Timing kind: operation, axis of the 3D view, precision.
+std::string kind_name(int prec, const gpe::PassArgs &a) {
+  const char *op = "step";
+  if (!a.forward) op = "ifft";
+  else if (!a.store) op = "obs";
+  else if (!a.inverse) op = "fft";
+  else if (a.post == gpe::PH_DERIV) op = "deriv";
+  static const char ax[3] = {'x', 'y', 'z'};
+  return std::string(op) + "_" + ax[a.axis] + (prec == 1 ? "_fp32" : "_fp64");
 }
 
 gpe_status launch_pass(gpe_ctx *c, const gpe::PassArgs &a) {
@@ -239,7 +256,7 @@ gpe_status launch_pass(gpe_ctx *c, const gpe::PassArgs &a) {
   hipEvent_t e0 = nullptr, e1 = nullptr;
   if (c->timing) {
     // kinds: one per axis of the 3D view; bytes = algorithmic HBM traffic
-    const char *nm = kind_name(c->prec, a.axis);
+    const std::string nm = kind_name(c->prec, a);
     for (size_t i = 0; i < c->kinds.size(); ++i)
       if (c->kinds[i].name == nm) kind = (int)i;
     if (kind < 0) {
@@ -250,6 +267,7 @@ gpe_status launch_pass(gpe_ctx *c, const gpe::PassArgs &a) {
     }
     double bytes = (double)c->sites * c->esize;  // every pass reads the state once
     bytes += a.store ? (double)c->sites * c->esize : 0;
+    if (a.post == gpe::PH_DERIV) bytes += (double)c->sites * c->esize;  // re-reads psi
     if (c->V && (a.pre != gpe::PH_NONE || a.post != gpe::PH_NONE)) bytes += 8.0 * c->sites;
     c->kinds[kind].bytes = bytes;
     if (!c->event_pool.empty()) {
@@ -426,6 +444,120 @@ gpe_status compute_obs(gpe_ctx *c, const double *scale, gpe_obs *o) {
   return GPE_OK;
 }
 
+bool equal_lengths(const gpe_ctx *c) {
+  const int off = 3 - c->dim;
+  for (int j = off + 1; j < 3; ++j)
+    if (std::fabs(c->L3[j] - c->L3[off]) > 1e-12 * c->L3[off]) return false;
+  return true;
+}
+
+double shell_width(const gpe_ctx *c) {
+  double dk = 2 * kPi / c->L3[3 - c->dim];
+  for (int j = 3 - c->dim; j < 3; ++j) dk = std::fmin(dk, 2 * kPi / c->L3[j]);
+  return dk;
+}
+
+int shell_count(const gpe_ctx *c) {
+  const double dk = shell_width(c);
+  double q = 0;
+  for (int j = 3 - c->dim; j < 3; ++j) {
+    const double kn = (double)(c->n3[j] / 2) * (2 * kPi / c->L3[j]) / dk;
+    q += kn * kn;
+  }
+  return (int)std::floor(std::sqrt(q) + 0.5) + 1;
+}
+
+// Forward transform along every axis, src -> dst (then in place on dst).
+gpe_status forward_all(gpe_ctx *c, const void *src, void *dst) {
+  bool first = true;
+  for (int i = 0; i < n_axes(c); ++i) {
+    const int ax = order_axis(c, i);
+    gpe::PassArgs a = base_args(c, ax);
+    a.src = first ? src : dst;
+    a.dst = dst;
+    a.inverse = 0;
+    gpe_status st = launch_pass(c, a);
+    if (st != GPE_OK) return st;
+    first = false;
+  }
+  return GPE_OK;
+}
+
+// Shell spectra of the current state (see gpe_spectra).
+gpe_status compute_spectra(gpe_ctx *c, gpe_spectra *spec) {
+  const int nb = shell_count(c);
+  if (spec->nbins != nb) return fail(c, GPE_EINVAL, "spec->nbins must equal gpe_spectra_bins()");
+  for (int j = 0; j < c->dim; ++j) {
+    if (!c->work[j]) {
+      gpe_status st = dalloc(c, &c->work[j], c->sites * c->esize, "spectra work allocation");
+      if (st != GPE_OK) return st;
+    }
+  }
+  const int blocks = gpe::shell_blocks(c->sites);
+  if (!c->hist_partial) {
+    gpe_status st = dalloc(c, (void **)&c->hist_partial, (size_t)blocks * 4 * nb * sizeof(double),
+                           "histogram allocation");
+    if (st != GPE_OK) return st;
+    st = dalloc(c, (void **)&c->hist, 8 * (size_t)nb * sizeof(double), "histogram allocation");
+    if (st != GPE_OK) return st;
+  }
+  gpe::ShellArgs sa{};
+  for (int j = 0; j < 3; ++j) {
+    sa.n[j] = c->n3[j];
+    sa.kscale[j] = j >= 3 - c->dim ? 2 * kPi / c->L3[j] : 0.0;
+  }
+  sa.dk = shell_width(c);
+  sa.integer_shells = equal_lengths(c) ? 1 : 0;
+  sa.nbins = nb;
+  sa.w = c->dV / (double)c->sites;
+  sa.partial = c->hist_partial;
+  // particle-number spectrum from the transform of psi
+  gpe_status st = forward_all(c, c->psi, c->work[0]);
+  if (st != GPE_OK) return st;
+  sa.kind = 0;
+  sa.f[0] = c->work[0];
+  HIPCHK(c, gpe::launch_shells(c->prec, sa, c->stream), "shell launch");
+  HIPCHK(c, gpe::launch_sum_columns(c->hist_partial, blocks, 4 * nb, c->hist, c->stream),
+         "histogram sum");
+  // Z_j = u_j + i w_j from the spectral derivative along each axis, transformed
+  void *deriv_tab[3] = {nullptr, nullptr, nullptr};
+  for (int j = 0; j < c->dim; ++j) {
+    const int ax = view_axis(c, j);
+    st = get_table(c, ax, TB_DERIV, 0.0, &deriv_tab[ax]);
+    if (st != GPE_OK) return st;
+    gpe::PassArgs a = base_args(c, ax);
+    a.src = c->psi;
+    a.dst = c->work[j];
+    a.mid = gpe::MID_TABLE;
+    a.mtab = deriv_tab[ax];
+    a.post = gpe::PH_DERIV;
+    st = launch_pass(c, a);
+    if (st != GPE_OK) return st;
+    st = forward_all(c, c->work[j], c->work[j]);
+    if (st != GPE_OK) return st;
+  }
+  sa.kind = 1;
+  for (int j = 0; j < 3; ++j) sa.f[j] = nullptr;
+  for (int j = 0; j < c->dim; ++j) sa.f[view_axis(c, j)] = c->work[j];
+  HIPCHK(c, gpe::launch_shells(c->prec, sa, c->stream), "shell launch");
+  HIPCHK(c, gpe::launch_sum_columns(c->hist_partial, blocks, 4 * nb, c->hist + 4 * nb, c->stream),
+         "histogram sum");
+  std::vector<double> h(8 * (size_t)nb);
+  HIPCHK(c, hipMemcpyAsync(h.data(), c->hist, h.size() * sizeof(double), hipMemcpyDeviceToHost,
+                           c->stream), "histogram download");
+  HIPCHK(c, hipStreamSynchronize(c->stream), "stream sync");
+  for (int b = 0; b < nb; ++b) {
+    if (spec->n_k) spec->n_k[b] = h[b];
+    if (spec->e_comp) spec->e_comp[b] = h[4 * nb + nb + b];
+    if (spec->e_incomp) spec->e_incomp[b] = h[4 * nb + 2 * nb + b];
+    if (spec->e_qp) spec->e_qp[b] = h[4 * nb + 3 * nb + b];
+  }
+  spec->dk = shell_width(c);
+  for (double x : h)
+    if (!std::isfinite(x)) return fail(c, GPE_ENONFINITE, "spectra are not finite");
+  return GPE_OK;
+}
+
 }  // namespace
 
 extern "C" {
@@ -488,6 +620,7 @@ gpe_status gpe_create(const gpe_desc *desc, const double *V_host, const gpe_harm
   // Tuning overrides for experiments: strided workgroup widths per axis.
   if (const char *w = std::getenv("GPE_TUNE_WX")) c->wreq[0] = std::atoi(w);
   if (const char *w = std::getenv("GPE_TUNE_WY")) c->wreq[1] = std::atoi(w);
+  if (const char *w = std::getenv("GPE_TUNE_XCD")) c->xcd_remap[0] = c->xcd_remap[1] = std::atoi(w);
   long long maxb = 1;
   for (int ax = 3 - c->dim; ax < 3; ++ax) {
     const gpe::PassShape sh = gpe::pass_shape(c->prec, c->n3, ax, c->wreq[ax]);
@@ -683,20 +816,14 @@ gpe_status gpe_ground_state(gpe_ctx *c, double dt, double tol, int32_t check_eve
 gpe_status gpe_observables(gpe_ctx *c, gpe_obs *out, gpe_spectra *spec) {
   if (!c) return GPE_EINVAL;
   if (!out) return fail(c, GPE_EINVAL, "out is NULL");
-  if (spec) return fail(c, GPE_EUNSUPPORTED, "spectra not built yet");
-  return compute_obs(c, nullptr, out);
+  gpe_status st = compute_obs(c, nullptr, out);
+  if (st != GPE_OK || !spec) return st;
+  return compute_spectra(c, spec);
 }
 
 int32_t gpe_spectra_bins(const gpe_ctx *c) {
   if (!c) return -1;
-  double dk = 2 * kPi / c->L3[3 - c->dim];
-  for (int j = 3 - c->dim; j < 3; ++j) dk = std::fmin(dk, 2 * kPi / c->L3[j]);
-  double q = 0;
-  for (int j = 3 - c->dim; j < 3; ++j) {
-    const double kn = (double)(c->n3[j] / 2) * (2 * kPi / c->L3[j]) / dk;
-    q += kn * kn;
-  }
-  return (int32_t)std::floor(std::sqrt(q) + 0.5) + 1;
+  return shell_count(c);
 }
 
 gpe_status gpe_transform(gpe_ctx *c, int32_t axis_mask, int32_t inverse) {
@@ -742,7 +869,7 @@ gpe_status gpe_timing_read(gpe_ctx *c, gpe_timing *out) {
   gpe_status st = drain_timing(c);
   if (st != GPE_OK) return st;
   std::memset(out, 0, sizeof(*out));
-  out->count = (int32_t)std::min<size_t>(8, c->kinds.size());
+  out->count = (int32_t)std::min<size_t>(GPE_TIMING_KINDS, c->kinds.size());
   for (int i = 0; i < out->count; ++i) {
     std::snprintf(out->name[i], sizeof(out->name[i]), "%s", c->kinds[i].name.c_str());
     out->total_ms[i] = c->kinds[i].total_ms;
@@ -773,6 +900,10 @@ void gpe_destroy(gpe_ctx *c) {
     if (c->kw[j]) (void)hipFree(c->kw[j]);
   }
   if (c->psi) (void)hipFree(c->psi);
+  for (int j = 0; j < 3; ++j)
+    if (c->work[j]) (void)hipFree(c->work[j]);
+  if (c->hist_partial) (void)hipFree(c->hist_partial);
+  if (c->hist) (void)hipFree(c->hist);
   if (c->V) (void)hipFree(c->V);
   if (c->partial) (void)hipFree(c->partial);
   if (c->sums) (void)hipFree(c->sums);

@@ -13,6 +13,8 @@ enum PhaseOp : int {
   PH_NONE = 0,
   PH_REAL = 1,  // psi <- exp(-i (V + g|psi|^2) tau) psi
   PH_IMAG = 2,  // psi <- exp(-(V + g|psi|^2) tau) psi   (pre: after psi <- c psi)
+  PH_DERIV = 3, // post only: d = result, p = src at the site:
+                //   out = (Im(conj(p) d) + i Re(conj(p) d)) / |p|  (0 where p = 0)
 };
 
 enum MidOp : int {
@@ -45,6 +47,7 @@ struct PassArgs {
   double tau_pre, tau_post, g;
   int vkind;          // V_NONE, V_ARRAY (V below) or V_HARMONIC (hv below)
   int wreq;           // columns per workgroup requested for a strided axis (8 or 16)
+  int xcd_remap;      // strided axes: give each XCD a contiguous run of tiles
   const double *V;    // FP64 potential per site, or null
   double hv[3];       // analytic V = sum_j hv[j] x_j^2 when V is null
   double lo[3], h[3]; // coordinates x_j = lo[j] + i h[j] (3D indexing)
@@ -79,6 +82,26 @@ hipError_t launch_finalize(const double *partial, long long count, double *out,
 // psi <- c psi (c read from device), precision 0/1; sets *c = 1 afterwards.
 hipError_t launch_scale(int precision, void *psi, long long sites, double *c,
                         hipStream_t s);
+
+// |k|-shell sums.  kind 0: n_k from the spectrum f[0]; kind 1: compressible,
+// incompressible and quantum-pressure energies from the spectra f[j] of
+// Z_j = u_j + i w_j.  Partial histograms of 4 x nbins doubles per workgroup.
+struct ShellArgs {
+  int kind;
+  const void *f[3];  // complex T fields on the 3D view grid
+  int n[3];          // 3D view (2D: n[0] = 1)
+  double kscale[3];  // 2 pi / L_j per view axis (0 for a missing axis)
+  double dk;         // shell width
+  int integer_shells;  // equal box lengths: shells from the integer sum of m_j^2
+  int nbins;
+  double w;          // dV / N_tot
+  double *partial;   // [gridDim][4][nbins]
+};
+int shell_blocks(long long sites);
+hipError_t launch_shells(int precision, const ShellArgs &a, hipStream_t s);
+// out[i] = sum_b partial[b * len + i] for i < len, b < count, fixed order.
+hipError_t launch_sum_columns(const double *partial, long long count, int len, double *out,
+                              hipStream_t s);
 
 // Precision conversion copies (device to device).
 hipError_t launch_convert(int src_prec, const void *src, int dst_prec, void *dst,

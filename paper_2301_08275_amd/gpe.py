@@ -4,6 +4,10 @@ Functions named like the C ABI (gpe_create, gpe_evolve, ...) marshal
 arguments only; every step of the solver runs in the HIP library.  `Context`
 wraps them for numpy / torch callers.  There is no fallback: if the library
 is missing or no HIP device is present the calls fail loudly.
+
+PyTorch ships its own HIP runtime with the same soname as the system one.
+When torch shares the process, import torch (and touch its device) before the
+first call here, so that libgpe.so binds to the runtime torch already loaded.
 """
 import ctypes
 import os
@@ -55,10 +59,14 @@ class gpe_spectra(ctypes.Structure):
                 ("e_qp", ctypes.POINTER(ctypes.c_double))]
 
 
+GPE_TIMING_KINDS = 16
+
+
 class gpe_timing(ctypes.Structure):
-    _fields_ = [("count", ctypes.c_int32), ("name", (ctypes.c_char * 32) * 8),
-                ("total_ms", ctypes.c_double * 8), ("launches", ctypes.c_int64 * 8),
-                ("bytes", ctypes.c_double * 8)]
+    _fields_ = [("count", ctypes.c_int32), ("name", (ctypes.c_char * 32) * GPE_TIMING_KINDS),
+                ("total_ms", ctypes.c_double * GPE_TIMING_KINDS),
+                ("launches", ctypes.c_int64 * GPE_TIMING_KINDS),
+                ("bytes", ctypes.c_double * GPE_TIMING_KINDS)]
 
 
 _P = ctypes.c_void_p
