@@ -46,7 +46,8 @@ typedef enum {
   GPE_ENOTCONV = -4,     /* ground state not converged within max_steps */
   GPE_ENONFINITE = -5,   /* a reduction met a NaN or Inf */
   GPE_EBUSY = -6,        /* result not ready */
-  GPE_EUNSUPPORTED = -7  /* valid request outside what is built (e.g. n = 2048) */
+  GPE_EUNSUPPORTED = -7, /* valid request outside what is built (e.g. n = 2048) */
+  GPE_ECANCELED = -8     /* request cancelled before it finished */
 } gpe_status;
 
 typedef enum { GPE_FP64 = 0, GPE_FP32 = 1 } gpe_precision;
@@ -190,6 +191,76 @@ uint64_t gpe_device_bytes(const gpe_ctx *ctx);
 const char *gpe_last_error(const gpe_ctx *ctx);
 
 void gpe_destroy(gpe_ctx *ctx);
+
+/* ------------------------------------------------------------------------
+ * Serving: a request scheduler over one GPU (no counterpart in the paper,
+ * which solves one problem per run).  Independent solves of the problems
+ * above are submitted from any host thread; a scheduler thread admits them in
+ * arrival order while the HBM budget allows and a slot of their shape class
+ * (dim, n, precision, box, dt) is free, runs every active slot of a class in
+ * the same batched launches (chunks of steps replayed from a HIP graph), and
+ * frees the slot as soon as the request has finished.  Requests of any size
+ * mix; each one's arithmetic does not depend on what else runs.
+ * ---------------------------------------------------------------------- */
+typedef struct gpe_server gpe_server; /* opaque, library-owned */
+
+typedef struct {
+  gpe_desc desc;          /* grid, box, g, precision, norm_target */
+  gpe_harmonic trap;      /* analytic harmonic potential (all zero: V = 0) */
+  const double *psi0;     /* initial state, host FP64 (copied at submit) */
+  int32_t mode;           /* 0: real-time evolution, 1: imaginary time */
+  double dt;              /* > 0 */
+  int64_t nsteps;         /* steps to run (imaginary time: fixed count, renormalised each step) */
+  int32_t keep_state;     /* 1: keep the final state for gpe_server_poll */
+} gpe_request;
+
+typedef struct {
+  gpe_status status;      /* GPE_OK, GPE_ENONFINITE, GPE_ECANCELED, GPE_ENOMEM, ... */
+  gpe_obs obs;            /* observables of the final state */
+  double t_submit, t_start, t_done;  /* seconds on the server's clock */
+  int64_t steps_done;
+} gpe_result;
+
+typedef struct {
+  int64_t submitted, completed, running, queued;
+  double busy_seconds;            /* wall time with at least one request running */
+  double site_steps;              /* sum over completed requests of sites x steps */
+  uint64_t bytes_in_use;          /* HBM held for admitted requests */
+} gpe_server_stats;
+
+/* Create a server on the current HIP device.  hbm_budget_bytes caps the
+ * device memory of admitted requests (0: the device's free memory);
+ * max_slots is the slot count of each shape class (>= 1); max_active caps the
+ * requests running at once over all classes (0: no cap; 1: one at a time);
+ * chunk_steps is the number of steps between completion checks (>= 1). */
+gpe_status gpe_server_create(uint64_t hbm_budget_bytes, int32_t max_slots, int32_t max_active,
+                             int32_t chunk_steps, gpe_server **out);
+
+/* Queue a request (validated now; GPE_EINVAL etc. on bad input, GPE_ENOMEM if
+ * it could never fit the budget).  The initial state is copied.  *id names it. */
+gpe_status gpe_server_submit(gpe_server *srv, const gpe_request *req, uint64_t *id);
+
+/* GPE_EBUSY while the request is queued or running; otherwise fills *out and,
+ * if psi_out is not NULL and the request kept its state, copies the final
+ * state (host FP64).  A finished request can be polled any number of times. */
+gpe_status gpe_server_poll(gpe_server *srv, uint64_t id, gpe_result *out, double *psi_out);
+
+/* Cancel a queued or running request (finishes with GPE_ECANCELED). */
+gpe_status gpe_server_cancel(gpe_server *srv, uint64_t id);
+
+/* Block until no request is queued or running. */
+gpe_status gpe_server_wait_idle(gpe_server *srv);
+
+gpe_status gpe_server_stats_read(gpe_server *srv, gpe_server_stats *out);
+
+/* Device bytes the server charges against its budget for a request of this
+ * shape: *class_b once per shape class (server created with max_slots), and
+ * *slot_b per running request (its state, partials and tables). */
+gpe_status gpe_request_bytes(const gpe_desc *desc, int32_t max_slots, uint64_t *class_b,
+                             uint64_t *slot_b);
+
+/* Stop the scheduler (requests still queued or running are cancelled). */
+void gpe_server_destroy(gpe_server *srv);
 
 #ifdef __cplusplus
 }

@@ -381,12 +381,13 @@ __device__ __forceinline__ void inverse_fft(cx<T> *v, int t, int c, T *lre, T *l
   stage<PL, 0, +1>(v, t, tw);
 }
 
-__device__ __forceinline__ double site_potential(const PassArgs &a, int j0, int j1, int j2) {
-  if (a.vkind == V_NONE) return 0.0;
-  if (a.vkind == V_ARRAY) return a.V[((long long)j0 * a.n[1] + j1) * a.n[2] + j2];
+__device__ __forceinline__ double site_potential(const PassArgs &a, int vkind, const double *hv,
+                                                 int j0, int j1, int j2) {
+  if (vkind == V_NONE) return 0.0;
+  if (vkind == V_ARRAY) return a.V[((long long)j0 * a.n[1] + j1) * a.n[2] + j2];
   const double x0 = a.lo[0] + j0 * a.h[0], x1 = a.lo[1] + j1 * a.h[1],
                x2 = a.lo[2] + j2 * a.h[2];
-  return a.hv[0] * x0 * x0 + a.hv[1] * x1 * x1 + a.hv[2] * x2 * x2;
+  return hv[0] * x0 * x0 + hv[1] * x1 * x1 + hv[2] * x2 * x2;
 }
 
 // sin and cos of x in FP64: Cody-Waite reduction x = n pi/2 + r with pi/2 split
@@ -481,6 +482,7 @@ enum PassMode : int {
   MODE_PRE_REAL = 2,       // real-time phase, forward, table, inverse
   MODE_PRE_IMAG = 3,       // scale, imaginary-time phase, forward, table, inverse
   MODE_POST_IMAG_RED = 4,  // forward, table, inverse, imaginary-time phase, norm sum
+  MODE_SLOTS = 5,          // batched shape class: operations from each block's slot
 };
 
 template <typename T, class PL, int W, bool STRIDED, int MODE>
@@ -491,15 +493,47 @@ axis_pass_kernel(const PassArgs a) {
   __shared__ T lre[PL::M > 1 ? L::size : 1], lim[PL::M > 1 ? L::size : 1];
 
   constexpr bool G = MODE == MODE_GENERIC;
+  constexpr bool SL = MODE == MODE_SLOTS;
   const int forward = G ? a.forward : 1;
   const int inverse = G ? a.inverse : 1;
   const int store = G ? a.store : 1;
-  const int pre = G ? a.pre
-                    : (MODE == MODE_PRE_REAL ? PH_REAL : MODE == MODE_PRE_IMAG ? PH_IMAG : PH_NONE);
-  const int post = G ? a.post : (MODE == MODE_POST_IMAG_RED ? PH_IMAG : PH_NONE);
+  int pre = G ? a.pre
+              : (MODE == MODE_PRE_REAL ? PH_REAL : MODE == MODE_PRE_IMAG ? PH_IMAG : PH_NONE);
+  int post = G ? a.post : (MODE == MODE_POST_IMAG_RED ? PH_IMAG : PH_NONE);
   const int mid = G ? a.mid : MID_TABLE;
-  const int red = G ? a.red : (MODE == MODE_POST_IMAG_RED ? RED_NORM_OUT : RED_NONE);
-  const bool has_scale = G ? a.scale != nullptr : MODE == MODE_PRE_IMAG;
+  int red = G ? a.red : (MODE == MODE_POST_IMAG_RED ? RED_NORM_OUT : RED_NONE);
+  bool has_scale = G ? a.scale != nullptr : MODE == MODE_PRE_IMAG;
+  // Per-block parameters: from the arguments, or (batched) from this block's slot.
+  const void *psrc = a.src;
+  void *pdst = a.dst;
+  const void *ptab = a.mtab;
+  const double *pscale = a.scale;
+  const double *hv = a.hv;
+  int vkind = a.vkind;
+  double g = a.g, tau_pre = a.tau_pre, tau_post = a.tau_post;
+  double *partial = a.partial;
+  if constexpr (SL) {
+    const Slot &sl = a.slots[blockIdx.y];
+    if (sl.mode == SLOT_FREE || sl.steps_done >= sl.steps_total) return;
+    const bool im = sl.mode == SLOT_IMAG;
+    const bool first = a.slot_pass & SLOT_PASS_FIRST, last = a.slot_pass & SLOT_PASS_LAST;
+    psrc = sl.psi;
+    pdst = sl.psi;
+    ptab = im ? a.mtab_imag : a.mtab;
+    g = sl.g;
+    hv = sl.hv;
+    vkind = (hv[0] != 0 || hv[1] != 0 || hv[2] != 0) ? V_HARMONIC : V_NONE;
+    pre = first ? (im ? PH_IMAG : PH_REAL) : PH_NONE;
+    tau_pre = (im || sl.steps_done == 0) ? 0.5 * a.dt : a.dt;
+    has_scale = first && im;
+    pscale = &sl.scale;
+    post = last ? ((im || sl.steps_done == sl.steps_total - 1) ? (im ? PH_IMAG : PH_REAL)
+                                                               : PH_NONE)
+                : PH_NONE;
+    tau_post = 0.5 * a.dt;
+    red = (last && im) ? RED_NORM_OUT : RED_NONE;
+    partial = a.partial + (long long)blockIdx.y * gridDim.x * kRedSlots;
+  }
 
   const int tid = threadIdx.x;
   const int c = STRIDED ? (tid % W) : (tid / TPL);
@@ -513,7 +547,7 @@ axis_pass_kernel(const PassArgs a) {
   bool valid = true;
   if (!STRIDED) {
     const long long line = (long long)blockIdx.x * W + c;
-    valid = !G || line < (long long)a.n[0] * n1;
+    valid = (!G && !SL) || line < (long long)a.n[0] * n1;
     j0 = (int)(line / n1);
     j1 = (int)(line % n1);
     base = line * N;
@@ -539,10 +573,10 @@ axis_pass_kernel(const PassArgs a) {
   }
   const int axis = STRIDED ? a.axis : 2;
 
-  const cx<T> *__restrict__ src = static_cast<const cx<T> *>(a.src);
-  cx<T> *__restrict__ dst = static_cast<cx<T> *>(a.dst);
+  const cx<T> *__restrict__ src = static_cast<const cx<T> *>(psrc);
+  cx<T> *__restrict__ dst = static_cast<cx<T> *>(pdst);
   const tab_t<T> *__restrict__ tw = static_cast<const tab_t<T> *>(a.tw);
-  const tab_t<T> *__restrict__ mtab = static_cast<const tab_t<T> *>(a.mtab);
+  const tab_t<T> *__restrict__ mtab = static_cast<const tab_t<T> *>(ptab);
   constexpr int R0 = PL::rad(0), RL = PL::rad(PL::M - 1);
 
   double acc[kRedSlots];
@@ -559,7 +593,7 @@ axis_pass_kernel(const PassArgs a) {
         v[b * R0 + d] = valid ? src[base + p * S] : cx<T>{0, 0};
       }
     if (has_scale || pre != PH_NONE || (red & RED_REAL)) {
-      const double sc = has_scale ? *a.scale : 1.0;
+      const double sc = has_scale ? *pscale : 1.0;
 #pragma unroll
       for (int b = 0; b < E / R0; ++b)
 #pragma unroll
@@ -569,7 +603,7 @@ axis_pass_kernel(const PassArgs a) {
           cx<T> u = v[b * R0 + d];
           if (has_scale) u = {(T)(sc * (double)u.x), (T)(sc * (double)u.y)};
           const double V = (pre != PH_NONE || (red & RED_REAL)) && valid
-                               ? site_potential(a, k0, k1, k2) : 0.0;
+                               ? site_potential(a, vkind, hv, k0, k1, k2) : 0.0;
           if (red & RED_REAL) {
             const double rho = (double)u.x * u.x + (double)u.y * u.y;
             const double x0 = a.lo[0] + k0 * a.h[0], x1 = a.lo[1] + k1 * a.h[1],
@@ -581,7 +615,7 @@ axis_pass_kernel(const PassArgs a) {
             acc[kSlotReal + 4] += x1 * x1 * rho;
             acc[kSlotReal + 5] += x2 * x2 * rho;
           }
-          if (pre != PH_NONE) u = apply_phase(pre, u, V, a.g, a.tau_pre);
+          if (pre != PH_NONE) u = apply_phase(pre, u, V, g, tau_pre);
           v[b * R0 + d] = u;
         }
     }
@@ -631,8 +665,8 @@ axis_pass_kernel(const PassArgs a) {
             u = mag > 0 ? cx<T>{(T)(zi / mag), (T)(zr / mag)} : cx<T>{0, 0};
           } else if (post != PH_NONE) {
             const int k0 = axis == 0 ? p : j0, k1 = axis == 1 ? p : j1, k2 = axis == 2 ? p : j2;
-            const double V = valid ? site_potential(a, k0, k1, k2) : 0.0;
-            u = apply_phase(post, u, V, a.g, a.tau_post);
+            const double V = valid ? site_potential(a, vkind, hv, k0, k1, k2) : 0.0;
+            u = apply_phase(post, u, V, g, tau_post);
           }
           if (red & RED_NORM_OUT) acc[kSlotNormOut] += (double)u.x * u.x + (double)u.y * u.y;
           v[b * R0 + d] = u;
@@ -654,7 +688,7 @@ axis_pass_kernel(const PassArgs a) {
 #pragma unroll
       for (int k = 0; k < kRedSlots; ++k) acc[k] = 0;
     }
-    block_reduce_store(acc, a.partial, 0);
+    block_reduce_store(acc, partial, 0);
   }
 }
 
@@ -689,6 +723,9 @@ void launch_mode(const PassArgs &a, int mode, dim3 grid, dim3 block, hipStream_t
       hipLaunchKernelGGL((axis_pass_kernel<T, PL, W, STRIDED, MODE_POST_IMAG_RED>), grid, block, 0,
                          s, a);
       break;
+    case MODE_SLOTS:
+      hipLaunchKernelGGL((axis_pass_kernel<T, PL, W, STRIDED, MODE_SLOTS>), grid, block, 0, s, a);
+      break;
     default:
       hipLaunchKernelGGL((axis_pass_kernel<T, PL, W, STRIDED, MODE_GENERIC>), grid, block, 0, s, a);
   }
@@ -697,7 +734,7 @@ void launch_mode(const PassArgs &a, int mode, dim3 grid, dim3 block, hipStream_t
 template <typename T, int N>
 hipError_t launch_n(const PassArgs &a, const PassShape &sh, int mode, hipStream_t s) {
   using PL = typename PlanFor<N>::type;
-  const dim3 grid((unsigned)sh.blocks), block((unsigned)sh.threads);
+  const dim3 grid((unsigned)sh.blocks, (unsigned)(a.slots ? a.nslots : 1)), block((unsigned)sh.threads);
   constexpr int W16 = fit_w(N, (int)(2 * sizeof(T)), 16);
   if (!sh.strided) {
     launch_mode<T, PL, contig_lines<N>(), false>(a, mode, grid, block, s);

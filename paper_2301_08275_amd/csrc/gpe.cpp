@@ -13,77 +13,14 @@
 #include <string>
 #include <vector>
 
+#include "gpe_ctx.h"
 #include "gpe_kernels.h"
 
 namespace {
-
-const double kPi = 3.14159265358979323846264338327950288;
 thread_local std::string g_create_error;
-
-struct DevBuf {
-  void *p = nullptr;
-  size_t bytes = 0;
-};
-
-// Kinds of per-frequency tables along one axis.
-enum TableKind { TB_KREAL = 0, TB_KIMAG = 1, TB_DERIV = 2, TB_INVN = 3 };
-
-struct TimedKind {
-  std::string name;
-  double total_ms = 0;
-  long long launches = 0;
-  double bytes = 0;
-};
-
 }  // namespace
 
-struct gpe_ctx {
-  gpe_desc desc{};
-  int dim = 0;
-  int n3[3] = {1, 1, 1};     // 3D view (2D problems: n3[0] = 1)
-  double lo3[3] = {0, 0, 0}, h3[3] = {0, 0, 0}, L3[3] = {1, 1, 1};
-  long long sites = 0;
-  int prec = 0;
-  size_t esize = 16;  // bytes per complex site
-  double dV = 1;
-
-  hipStream_t stream = nullptr;
-  bool own_stream = false;
-  int device = 0;
-
-  void *psi = nullptr;
-  void *work[3] = {nullptr, nullptr, nullptr};  // spectra work fields (allocated on demand)
-  double *hist_partial = nullptr;  // shell histograms per workgroup
-  double *hist = nullptr;          // 8 x nbins finalized shell sums
-  double *V = nullptr;         // FP64 potential array (device) or null
-  double hv[3] = {0, 0, 0};    // analytic V coefficients (3D view)
-  double *partial = nullptr;   // per-workgroup partials, 3 regions
-  long long partial_region = 0;  // doubles per region
-  double *sums = nullptr;      // finalized sums, 4 x kRedSlots
-  double *scale = nullptr;     // imaginary-time c
-  void *tw[3] = {nullptr, nullptr, nullptr};  // per axis (3D view) twiddles
-  double *kw[3] = {nullptr, nullptr, nullptr};  // k^2/N weights per axis
-  std::map<std::pair<int, std::pair<int, double>>, void *> tables;  // (axis,(kind,dt))
-  size_t dev_bytes = 0;
-
-  bool timing = false;
-  std::vector<TimedKind> kinds;
-  std::vector<std::pair<int, std::pair<hipEvent_t, hipEvent_t>>> pending;
-  std::vector<std::pair<hipEvent_t, hipEvent_t>> event_pool;
-
-  std::string err;
-  int pass_order[3] = {2, 1, 0};
-  // Strided columns per workgroup, per view axis (axis 2 is contiguous).  The
-  // slowest axis prefers 256-byte rows in both precisions; the middle axis is
-  // fastest with 128-byte rows in FP64 and 64-byte rows of 16 columns in FP32
-  // (measured at 512^3 on MI355X).
-  int wreq[3] = {16, 8, 8};
-  // Strided passes hand each XCD a contiguous run of tiles (measured: a few
-  // percent faster at 512^3 than the default round-robin order).
-  int xcd_remap[3] = {1, 1, 0};
-};
-
-namespace {
+namespace gpe_host {
 
 gpe_status fail(gpe_ctx *c, gpe_status st, const std::string &msg) {
   if (c) c->err = msg; else g_create_error = msg;
@@ -558,7 +495,32 @@ gpe_status compute_spectra(gpe_ctx *c, gpe_spectra *spec) {
   return GPE_OK;
 }
 
-}  // namespace
+// Device bytes gpe_create allocates for desc (state, partials, sums, scale,
+// twiddles and E_kin weights per axis); must follow gpe_create.
+uint64_t context_bytes(const gpe_desc &d) {
+  int n3[3] = {1, 1, 1};
+  const int off = 3 - d.dim;
+  long long sites = 1;
+  for (int j = 0; j < d.dim; ++j) {
+    n3[j + off] = d.n[j];
+    sites *= d.n[j];
+  }
+  const uint64_t es = d.precision == GPE_FP32 ? 8 : 16;
+  const int wdef[3] = {16, d.precision == GPE_FP32 ? 16 : 8, 8};
+  long long maxb = 1;
+  uint64_t tables = 0;
+  for (int ax = off; ax < 3; ++ax) {
+    const gpe::PassShape sh = gpe::pass_shape(d.precision, n3, ax, wdef[ax]);
+    if (sh.blocks > maxb) maxb = sh.blocks;
+    tables += (uint64_t)n3[ax] * (16 + sizeof(double));
+  }
+  return (uint64_t)sites * es + 3 * (uint64_t)maxb * gpe::kRedSlots * sizeof(double) +
+         4 * gpe::kRedSlots * sizeof(double) + sizeof(double) + tables;
+}
+
+}  // namespace gpe_host
+
+using namespace gpe_host;
 
 extern "C" {
 

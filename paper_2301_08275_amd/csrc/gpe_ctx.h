@@ -1,0 +1,91 @@
+// Internal: the context behind the opaque gpe_ctx handle and the host helpers
+// shared by the C ABI (gpe.cpp) and the serving scheduler (server.cpp).
+#pragma once
+
+#include <hip/hip_runtime.h>
+
+#include <map>
+#include <string>
+#include <vector>
+
+#include "gpe.h"
+#include "gpe_kernels.h"
+
+namespace gpe_host {
+
+constexpr double kPi = 3.14159265358979323846264338327950288;
+
+// Kinds of per-frequency tables along one axis.
+enum TableKind { TB_KREAL = 0, TB_KIMAG = 1, TB_DERIV = 2, TB_INVN = 3 };
+
+struct TimedKind {
+  std::string name;
+  double total_ms = 0;
+  long long launches = 0;
+  double bytes = 0;
+};
+
+}  // namespace gpe_host
+
+struct gpe_ctx {
+  gpe_desc desc{};
+  int dim = 0;
+  int n3[3] = {1, 1, 1};     // 3D view (2D problems: n3[0] = 1)
+  double lo3[3] = {0, 0, 0}, h3[3] = {0, 0, 0}, L3[3] = {1, 1, 1};
+  long long sites = 0;
+  int prec = 0;
+  size_t esize = 16;  // bytes per complex site
+  double dV = 1;
+
+  hipStream_t stream = nullptr;
+  bool own_stream = false;
+  int device = 0;
+
+  void *psi = nullptr;
+  void *work[3] = {nullptr, nullptr, nullptr};  // spectra work fields (allocated on demand)
+  double *hist_partial = nullptr;  // shell histograms per workgroup
+  double *hist = nullptr;          // 8 x nbins finalized shell sums
+  double *V = nullptr;         // FP64 potential array (device) or null
+  double hv[3] = {0, 0, 0};    // analytic V coefficients (3D view)
+  double *partial = nullptr;   // per-workgroup partials, 3 regions
+  long long partial_region = 0;  // doubles per region
+  double *sums = nullptr;      // finalized sums, 4 x kRedSlots
+  double *scale = nullptr;     // imaginary-time c
+  void *tw[3] = {nullptr, nullptr, nullptr};  // per axis (3D view) twiddles
+  double *kw[3] = {nullptr, nullptr, nullptr};  // k^2/N weights per axis
+  std::map<std::pair<int, std::pair<int, double>>, void *> tables;  // (axis,(kind,dt))
+  size_t dev_bytes = 0;
+
+  bool timing = false;
+  std::vector<gpe_host::TimedKind> kinds;
+  std::vector<std::pair<int, std::pair<hipEvent_t, hipEvent_t>>> pending;
+  std::vector<std::pair<hipEvent_t, hipEvent_t>> event_pool;
+
+  std::string err;
+  int pass_order[3] = {2, 1, 0};
+  // Strided columns per workgroup, per view axis (axis 2 is contiguous).  The
+  // slowest axis prefers 256-byte rows in both precisions; the middle axis is
+  // fastest with 128-byte rows in FP64 and 64-byte rows of 16 columns in FP32
+  // (measured at 512^3 on MI355X).
+  int wreq[3] = {16, 8, 8};
+  // Strided passes hand each XCD a contiguous run of tiles (measured: a few
+  // percent faster at 512^3 than the default round-robin order).
+  int xcd_remap[3] = {1, 1, 0};
+};
+
+
+namespace gpe_host {
+
+gpe_status fail(gpe_ctx *c, gpe_status st, const std::string &msg);
+gpe_status hipfail(gpe_ctx *c, hipError_t e, const char *what);
+gpe_status get_table(gpe_ctx *c, int vaxis, int kind, double dt, void **out);
+gpe::PassArgs base_args(gpe_ctx *c, int vaxis);
+gpe_status launch_pass(gpe_ctx *c, const gpe::PassArgs &a);
+gpe_status set_potential(gpe_ctx *c, const double *V_host, const gpe_harmonic *V_an);
+gpe_status compute_obs(gpe_ctx *c, const double *scale, gpe_obs *o);
+int n_axes(const gpe_ctx *c);
+int order_axis(const gpe_ctx *c, int i);
+int view_axis(const gpe_ctx *c, int user_axis);
+uint64_t context_bytes(const gpe_desc &d);
+
+}  // namespace gpe_host

@@ -35,6 +35,25 @@ constexpr int kSlotNormOut = 0, kSlotKin = 1, kSlotReal = 2;
 
 enum VKind : int { V_NONE = 0, V_ARRAY = 1, V_HARMONIC = 2 };
 
+// One request of a batched shape class (device-resident).  Batched passes
+// launch one grid row (blockIdx.y) per slot; a slot whose mode is SLOT_FREE or
+// whose steps are done costs its blocks an early return, so slots can be
+// filled and emptied without changing the launch.
+enum SlotMode : int { SLOT_FREE = 0, SLOT_REAL = 1, SLOT_IMAG = 2 };
+struct Slot {
+  void *psi;          // state (class precision)
+  double g;
+  double hv[3];       // analytic potential V = sum_j hv[j] x_j^2 (3D view)
+  int mode;           // SlotMode
+  int steps_total;
+  int steps_done;     // advanced once per step by the slot update kernel
+  int pad;
+  double scale;       // imaginary time: renormalisation factor for the next step
+  double norm_target;
+};
+// slot_pass bits for batched passes: first pass of a step, last pass of a step.
+constexpr int SLOT_PASS_FIRST = 1, SLOT_PASS_LAST = 2;
+
 struct PassArgs {
   const void *src;  // complex T, whole grid
   void *dst;        // complex T, whole grid (may equal src)
@@ -56,6 +75,12 @@ struct PassArgs {
   const double *kw;   // RED_KIN weights per frequency (N doubles)
   const double *scale;  // PH_IMAG pre: psi <- (*scale) psi (null: 1)
   double *partial;      // reductions, kRedSlots doubles per workgroup
+  // batched shape class (MODE_SLOTS): per-slot state and operations
+  Slot *slots;
+  int nslots;           // grid rows (blockIdx.y) of a batched launch
+  int slot_pass;        // SLOT_PASS_FIRST | SLOT_PASS_LAST bits
+  double dt;
+  const void *mtab_imag;  // imaginary-time kinetic table of the class
 };
 
 struct PassShape {
@@ -102,6 +127,11 @@ hipError_t launch_shells(int precision, const ShellArgs &a, hipStream_t s);
 // out[i] = sum_b partial[b * len + i] for i < len, b < count, fixed order.
 hipError_t launch_sum_columns(const double *partial, long long count, int len, double *out,
                               hipStream_t s);
+
+// After the last pass of a batched step: per slot, form the imaginary-time
+// factor from its norm partials (fixed order) and advance steps_done.
+hipError_t launch_slot_update(Slot *slots, int nslots, const double *partial,
+                              long long blocks_per_grid, double dV, hipStream_t s);
 
 // Precision conversion copies (device to device).
 hipError_t launch_convert(int src_prec, const void *src, int dst_prec, void *dst,

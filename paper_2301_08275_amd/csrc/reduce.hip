@@ -50,6 +50,30 @@ __global__ void scale_kernel(T *__restrict__ psi, long long n, const double *__r
 
 __global__ void set_one_kernel(double *c) { *c = 1.0; }
 
+// One workgroup per slot: fixed-order sum of the slot's norm partials into the
+// imaginary-time factor, then steps_done += 1.
+__global__ void __launch_bounds__(kFinThreads)
+slot_update_kernel(Slot *__restrict__ slots, const double *__restrict__ partial,
+                   long long blocks_per_grid, double dV) {
+  Slot &sl = slots[blockIdx.x];
+  if (sl.mode == SLOT_FREE || sl.steps_done >= sl.steps_total) return;
+  __shared__ double s[kFinThreads];
+  const int tid = threadIdx.x;
+  if (sl.mode == SLOT_IMAG) {
+    const double *p = partial + (long long)blockIdx.x * blocks_per_grid * kRedSlots;
+    double acc = 0;
+    for (long long i = tid; i < blocks_per_grid; i += kFinThreads) acc += p[i * kRedSlots];
+    s[tid] = acc;
+    __syncthreads();
+    for (int h = kFinThreads / 2; h >= 1; h >>= 1) {
+      if (tid < h) s[tid] += s[tid + h];
+      __syncthreads();
+    }
+    if (tid == 0) sl.scale = sqrt(sl.norm_target / (dV * s[0]));
+  }
+  if (tid == 0) sl.steps_done += 1;
+}
+
 template <typename S, typename D>
 __global__ void convert_kernel(const S *__restrict__ src, D *__restrict__ dst, long long n) {
   for (long long i = (long long)blockIdx.x * blockDim.x + threadIdx.x; i < n;
@@ -70,6 +94,13 @@ hipError_t launch_finalize(const double *partial, long long count, double *out,
                            hipStream_t s) {
   hipLaunchKernelGGL(finalize_kernel, dim3(1), dim3(kFinThreads), 0, s, partial, count,
                      out, scale_out, norm_target, dV);
+  return hipGetLastError();
+}
+
+hipError_t launch_slot_update(Slot *slots, int nslots, const double *partial,
+                              long long blocks_per_grid, double dV, hipStream_t s) {
+  hipLaunchKernelGGL(slot_update_kernel, dim3(nslots), dim3(kFinThreads), 0, s, slots, partial,
+                     blocks_per_grid, dV);
   return hipGetLastError();
 }
 

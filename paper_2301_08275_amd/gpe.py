@@ -25,9 +25,10 @@ GPE_ENOTCONV = -4
 GPE_ENONFINITE = -5
 GPE_EBUSY = -6
 GPE_EUNSUPPORTED = -7
+GPE_ECANCELED = -8
 STATUS_NAMES = {0: "GPE_OK", -1: "GPE_EINVAL", -2: "GPE_ENOMEM", -3: "GPE_EDEVICE",
                 -4: "GPE_ENOTCONV", -5: "GPE_ENONFINITE", -6: "GPE_EBUSY",
-                -7: "GPE_EUNSUPPORTED"}
+                -7: "GPE_EUNSUPPORTED", -8: "GPE_ECANCELED"}
 
 GPE_FP64 = 0
 GPE_FP32 = 1
@@ -69,6 +70,26 @@ class gpe_timing(ctypes.Structure):
                 ("bytes", ctypes.c_double * GPE_TIMING_KINDS)]
 
 
+class gpe_request(ctypes.Structure):
+    _fields_ = [("desc", gpe_desc), ("trap", gpe_harmonic),
+                ("psi0", ctypes.POINTER(ctypes.c_double)), ("mode", ctypes.c_int32),
+                ("dt", ctypes.c_double), ("nsteps", ctypes.c_int64),
+                ("keep_state", ctypes.c_int32)]
+
+
+class gpe_result(ctypes.Structure):
+    _fields_ = [("status", ctypes.c_int32), ("obs", gpe_obs), ("t_submit", ctypes.c_double),
+                ("t_start", ctypes.c_double), ("t_done", ctypes.c_double),
+                ("steps_done", ctypes.c_int64)]
+
+
+class gpe_server_stats(ctypes.Structure):
+    _fields_ = [("submitted", ctypes.c_int64), ("completed", ctypes.c_int64),
+                ("running", ctypes.c_int64), ("queued", ctypes.c_int64),
+                ("busy_seconds", ctypes.c_double), ("site_steps", ctypes.c_double),
+                ("bytes_in_use", ctypes.c_uint64)]
+
+
 _P = ctypes.c_void_p
 _D = ctypes.c_double
 _I32 = ctypes.c_int32
@@ -95,6 +116,15 @@ SIGNATURES = {
     "gpe_device_bytes": (ctypes.c_uint64, [_P]),
     "gpe_last_error": (ctypes.c_char_p, [_P]),
     "gpe_destroy": (None, [_P]),
+    "gpe_server_create": (_I32, [ctypes.c_uint64, _I32, _I32, _I32, ctypes.POINTER(_P)]),
+    "gpe_server_submit": (_I32, [_P, ctypes.POINTER(gpe_request), ctypes.POINTER(ctypes.c_uint64)]),
+    "gpe_server_poll": (_I32, [_P, ctypes.c_uint64, ctypes.POINTER(gpe_result), _DP]),
+    "gpe_server_cancel": (_I32, [_P, ctypes.c_uint64]),
+    "gpe_server_wait_idle": (_I32, [_P]),
+    "gpe_server_stats_read": (_I32, [_P, ctypes.POINTER(gpe_server_stats)]),
+    "gpe_server_destroy": (None, [_P]),
+    "gpe_request_bytes": (_I32, [ctypes.POINTER(gpe_desc), _I32, ctypes.POINTER(ctypes.c_uint64),
+                                 ctypes.POINTER(ctypes.c_uint64)]),
 }
 
 _lib = None
@@ -225,6 +255,56 @@ def gpe_last_error(ctx):
 
 def gpe_destroy(ctx):
     load_library().gpe_destroy(ctx)
+
+
+def gpe_server_create(hbm_budget_bytes, max_slots, max_active, chunk_steps):
+    out = _P()
+    st = load_library().gpe_server_create(int(hbm_budget_bytes), int(max_slots),
+                                          int(max_active), int(chunk_steps), ctypes.byref(out))
+    if st != GPE_OK:
+        raise GpeError(st, "gpe_server_create")
+    return out
+
+
+def gpe_server_submit(srv, req):
+    rid = ctypes.c_uint64(0)
+    st = load_library().gpe_server_submit(srv, ctypes.byref(req), ctypes.byref(rid))
+    if st != GPE_OK:
+        raise GpeError(st, "gpe_server_submit")
+    return rid.value
+
+
+def gpe_server_poll(srv, rid, out, psi_out=None):
+    """Returns the status of the call (GPE_EBUSY while pending)."""
+    return load_library().gpe_server_poll(srv, int(rid), ctypes.byref(out), _dptr(psi_out))
+
+
+def gpe_server_cancel(srv, rid):
+    return load_library().gpe_server_cancel(srv, int(rid))
+
+
+def gpe_server_wait_idle(srv):
+    return load_library().gpe_server_wait_idle(srv)
+
+
+def gpe_server_stats_read(srv):
+    st = gpe_server_stats()
+    load_library().gpe_server_stats_read(srv, ctypes.byref(st))
+    return {k: getattr(st, k) for k, _ in gpe_server_stats._fields_}
+
+
+def gpe_server_destroy(srv):
+    load_library().gpe_server_destroy(srv)
+
+
+def gpe_request_bytes(desc, max_slots):
+    """(bytes per shape class, bytes per running request) the server charges."""
+    cb, sb = ctypes.c_uint64(0), ctypes.c_uint64(0)
+    st = load_library().gpe_request_bytes(ctypes.byref(desc), int(max_slots), ctypes.byref(cb),
+                                          ctypes.byref(sb))
+    if st != GPE_OK:
+        raise GpeError(st, "gpe_request_bytes")
+    return cb.value, sb.value
 
 
 # ------------------------------------------------------------- convenience ---
@@ -377,3 +457,101 @@ class Context:
 
     def device_bytes(self):
         return gpe_device_bytes(self._ctx)
+
+
+def make_desc(shape, lo, hi, g, precision="fp64", norm_target=1.0):
+    dim = len(shape)
+    d = gpe_desc()
+    d.dim = dim
+    lo = np.broadcast_to(np.asarray(lo, np.float64), (dim,))
+    hi = np.broadcast_to(np.asarray(hi, np.float64), (dim,))
+    for j in range(dim):
+        d.n[j] = int(shape[j])
+        d.lo[j] = float(lo[j])
+        d.hi[j] = float(hi[j])
+    for j in range(dim, 3):
+        d.n[j] = 1
+    d.g = float(g)
+    d.precision = GPE_FP32 if precision == "fp32" else GPE_FP64
+    d.norm_target = float(norm_target)
+    return d
+
+
+class Server:
+    """Request scheduler on the current HIP device (gpe_server_* calls).
+
+    budget: HBM bytes for admitted requests (0: the device's free memory);
+    max_slots: slots per shape class; max_active: requests running at once
+    (0: no cap, 1: one at a time); chunk_steps: steps between completion checks.
+    """
+
+    def __init__(self, budget=0, max_slots=16, max_active=0, chunk_steps=16):
+        self._srv = gpe_server_create(budget, max_slots, max_active, chunk_steps)
+        self._keep = {}
+        self._shapes = {}
+
+    def submit(self, shape, lo, hi, g, psi0, mode="real", dt=1e-3, nsteps=100,
+               precision="fp64", trap=None, norm_target=1.0, keep_state=False):
+        r = gpe_request()
+        r.desc = make_desc(shape, lo, hi, g, precision, norm_target)
+        if trap is not None:
+            for j, w in enumerate(trap):
+                r.trap.w[j] = float(w)
+        p = np.ascontiguousarray(psi0, dtype=np.complex128)
+        if p.shape != tuple(shape):
+            raise ValueError("psi0 shape %s != %s" % (p.shape, tuple(shape)))
+        r.psi0 = p.view(np.float64).ctypes.data_as(_DP)
+        r.mode = 1 if mode in ("imag", "ground", 1) else 0
+        r.dt = float(dt)
+        r.nsteps = int(nsteps)
+        r.keep_state = 1 if keep_state else 0
+        rid = gpe_server_submit(self._srv, r)
+        self._keep[rid] = keep_state
+        self._shapes[rid] = tuple(shape)
+        return rid
+
+    def poll(self, rid):
+        """None while pending; else a dict with status, obs, times, state."""
+        out = gpe_result()
+        st = gpe_server_poll(self._srv, rid, out, None)
+        if st == GPE_EBUSY:
+            return None
+        if st != GPE_OK:
+            raise GpeError(st, "gpe_server_poll")
+        res = {"status": out.status, "steps_done": out.steps_done,
+               "t_submit": out.t_submit, "t_start": out.t_start, "t_done": out.t_done,
+               "obs": dict(zip(OBS_KEYS, [out.obs.norm, out.obs.energy, out.obs.mu,
+                                          out.obs.e_kin, out.obs.e_pot, out.obs.e_int,
+                                          out.obs.sigma[0], out.obs.sigma[1],
+                                          out.obs.sigma[2], out.obs.r_rms]))}
+        if self._keep.get(rid):
+            psi = np.empty(self._shapes[rid], np.complex128)
+            st = gpe_server_poll(self._srv, rid, out, psi.view(np.float64))
+            res["psi"] = psi if st == GPE_OK else None
+        return res
+
+    def cancel(self, rid):
+        return gpe_server_cancel(self._srv, rid)
+
+    def wait_idle(self):
+        gpe_server_wait_idle(self._srv)
+
+    def stats(self):
+        return gpe_server_stats_read(self._srv)
+
+    def close(self):
+        if self._srv is not None:
+            gpe_server_destroy(self._srv)
+            self._srv = None
+
+    def __enter__(self):
+        return self
+
+    def __exit__(self, *a):
+        self.close()
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass

@@ -1,0 +1,180 @@
+"""GPU tests of the serving scheduler (gpe_server_* calls).
+
+Every request's result must match the single-context path and the oracle, be
+bitwise identical whether it ran alone or in a mix, and the scheduler must
+respect the HBM budget, cancellation and per-request failure isolation.
+"""
+import sys
+import time
+
+import numpy as np
+import pytest
+
+import oracle
+from paper_2301_08275_amd import gpe
+from paper_2301_08275_amd import inputs as I
+
+pytestmark = pytest.mark.gpu
+
+BOX = 8.0
+
+
+def rel(a, b):
+    return float(np.linalg.norm(np.ravel(a - b)) / np.linalg.norm(np.ravel(b)))
+
+
+def say(*a):
+    print(*a, flush=True)
+    sys.stdout.flush()
+
+
+def make_req(i, shape, mode, prec="fp64", nsteps=None):
+    """A request of the serving mix: trap anisotropy, g and noise seeded by i."""
+    dim = len(shape)
+    u = I.uniform(1000 + i, 3)
+    a = 1.0 + 7.0 * u[0]
+    g = 100.0 * u[1]
+    trap = [1.0, a] if dim == 2 else [1.0, 1.0, a]
+    lo, hi = (-BOX,) * dim, (BOX,) * dim
+    psi0 = I.noisy_gaussian(shape, lo, hi, seed=5000 + i, amp=0.05)
+    steps = nsteps if nsteps is not None else 20 + int(60 * u[2])
+    return dict(shape=shape, lo=lo, hi=hi, g=g, psi0=psi0, mode=mode, dt=1e-3, nsteps=steps,
+                precision=prec, trap=trap, keep_state=True)
+
+
+def solve_alone_ctx(req):
+    """The same request through the single-context API."""
+    with gpe.Context(req["shape"], req["lo"], req["hi"], req["g"], precision=req["precision"],
+                     harmonic=req["trap"]) as ctx:
+        ctx.set_state(req["psi0"])
+        if req["mode"] == "real":
+            ctx.evolve(req["dt"], req["nsteps"])
+        else:
+            ctx.imag_steps(req["dt"], req["nsteps"])
+        return ctx.get_state()
+
+
+def run_all(srv, reqs, timeout=120):
+    ids = [srv.submit(**r) for r in reqs]
+    t0 = time.time()
+    out = {}
+    while len(out) < len(ids):
+        for rid in ids:
+            if rid not in out:
+                res = srv.poll(rid)
+                if res is not None:
+                    out[rid] = res
+        assert time.time() - t0 < timeout, "server did not finish"
+        time.sleep(0.002)
+    return [out[i] for i in ids]
+
+
+def mix():
+    shapes2 = [(64, 64), (128, 128), (64, 128)]
+    shapes3 = [(32, 32, 32), (64, 32, 16)]
+    reqs = []
+    for i in range(18):
+        shape = shapes2[i % 3] if i % 5 != 4 else shapes3[(i // 5) % 2]
+        mode = "real" if i % 2 == 0 else "imag"
+        prec = "fp32" if i % 7 == 3 else "fp64"
+        reqs.append(make_req(i, shape, mode, prec))
+    return reqs
+
+
+def test_server_results_match_single_context_and_oracle():
+    reqs = mix()
+    say("server mix of", len(reqs))
+    with gpe.Server(max_slots=8, chunk_steps=8) as srv:
+        res = run_all(srv, reqs)
+        st = srv.stats()
+    assert st["completed"] == len(reqs)
+    for r, out in zip(reqs, res):
+        assert out["status"] == gpe.GPE_OK, out
+        assert out["steps_done"] == r["nsteps"]
+        ref = solve_alone_ctx(r)
+        tol = 1e-12 if r["precision"] == "fp64" else 1e-5
+        assert rel(out["psi"], ref) < tol, (r["shape"], r["mode"], r["precision"])
+    # one of each mode against the oracle
+    for r, out in zip(reqs[:2], res[:2]):
+        V = I.harmonic(r["shape"], r["lo"], r["hi"], r["trap"])
+        if r["mode"] == "real":
+            ref = oracle.tssp_real(r["psi0"], r["lo"], r["hi"], V, r["g"], r["dt"], r["nsteps"])
+        else:
+            ref = oracle.tssp_imag(r["psi0"], r["lo"], r["hi"], V, r["g"], r["dt"], r["nsteps"])
+        assert rel(out["psi"], ref) < 1e-10
+        o = oracle.observables(ref, r["lo"], r["hi"], V, r["g"])
+        assert abs(out["obs"]["energy"] - o["energy"]) < 1e-9 * abs(o["energy"])
+
+
+def test_result_is_identical_alone_and_in_the_mix():
+    reqs = mix()
+    probe = [reqs[1], reqs[4], reqs[3]]
+    with gpe.Server(max_slots=8, chunk_steps=8) as srv:
+        alone = [run_all(srv, [p])[0] for p in probe]
+    with gpe.Server(max_slots=8, chunk_steps=8) as srv:
+        mixed = run_all(srv, reqs)
+    for p, a in zip(probe, alone):
+        m = mixed[reqs.index(p)]
+        assert np.array_equal(a["psi"], m["psi"])
+        assert a["obs"]["energy"] == m["obs"]["energy"]
+
+
+def max_overlap(res):
+    """Largest number of requests running at the same instant."""
+    ev = sorted([(r["t_start"], 1) for r in res] + [(r["t_done"], -1) for r in res],
+                key=lambda e: (e[0], e[1]))
+    cur = best = 0
+    for _, d in ev:
+        cur += d
+        best = max(best, cur)
+    return best
+
+
+@pytest.mark.parametrize("fit", [1, 2])
+def test_admission_respects_budget(fit):
+    """A budget with room for the class and `fit` running requests: every
+    request still finishes, never more than `fit` run at once, and the bytes
+    held stay within the budget."""
+    reqs = [make_req(i, (128, 128), "real", nsteps=40) for i in range(6)]
+    cls_b, slot_b = gpe.gpe_request_bytes(gpe.make_desc((128, 128), -BOX, BOX, 1.0), 8)
+    budget = cls_b + fit * slot_b + slot_b // 2
+    with gpe.Server(budget=budget, max_slots=8, chunk_steps=4) as srv:
+        res = run_all(srv, reqs)
+        assert srv.stats()["bytes_in_use"] <= budget
+    assert all(r["status"] == gpe.GPE_OK for r in res)
+    assert max_overlap(res) <= fit
+
+
+def test_max_active_one_is_one_at_a_time():
+    reqs = [make_req(i, (64, 64), "real", nsteps=30) for i in range(5)]
+    with gpe.Server(max_slots=8, max_active=1, chunk_steps=4) as srv:
+        res = run_all(srv, reqs)
+    assert max_overlap(res) == 1
+    assert [r["t_start"] for r in res] == sorted(r["t_start"] for r in res)
+
+
+def test_cancel_and_failure_isolation():
+    good = make_req(1, (64, 64), "real", nsteps=50)
+    bad = make_req(2, (64, 64), "real", nsteps=50)
+    bad["psi0"] = bad["psi0"].copy()
+    bad["psi0"][3, 5] = np.nan
+    long = make_req(3, (128, 128), "real", nsteps=200000)
+    with gpe.Server(max_slots=8, chunk_steps=8) as srv:
+        lid = srv.submit(**long)
+        ids = [srv.submit(**good), srv.submit(**bad)]
+        time.sleep(0.05)
+        srv.cancel(lid)
+        srv.wait_idle()
+        rl = srv.poll(lid)
+        rg, rb = srv.poll(ids[0]), srv.poll(ids[1])
+    assert rl["status"] == gpe.GPE_ECANCELED
+    assert rb["status"] == gpe.GPE_ENONFINITE
+    assert rg["status"] == gpe.GPE_OK
+    assert rel(rg["psi"], solve_alone_ctx(good)) < 1e-12
+
+
+def test_oversized_request_is_refused():
+    with gpe.Server(budget=1 << 20, max_slots=2) as srv:
+        with pytest.raises(gpe.GpeError) as e:
+            srv.submit(**make_req(0, (256, 256), "real"))
+        assert e.value.status == gpe.GPE_ENOMEM
