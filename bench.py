@@ -8,7 +8,9 @@ band-limited random phase (integer modes 1 <= |m| <= 8, per-mode variance
 real-time TSSP step (three fused axis passes); the particle-number,
 compressible, incompressible and quantum-pressure |k|-shell spectra are
 evaluated every 100 steps inside the timed region, as the workload asks.  The
-FP32 form of the same workload is timed in the same run.
+FP32 form of the same workload is timed in the same run.  The serving mix
+(a seeded Poisson stream of independent 2D/3D solves, FP32 or FP64) is then
+run through the request server and, for comparison, one request at a time.
 
 Prints ONE JSON line.  Inputs are resident in HBM before timing starts; the
 timed region is bracketed by device synchronisation and timed with HIP events
@@ -142,6 +144,74 @@ def cpu_baseline(n, seed, steps=1):
                       "spectra (plain radix-2 C++ oracle, %.1f s)" % (steps, n, t)}
 
 
+def percentile(xs, q):
+    xs = sorted(xs)
+    if not xs:
+        return None
+    k = (len(xs) - 1) * q
+    lo = int(k)
+    hi = min(lo + 1, len(xs) - 1)
+    return xs[lo] + (xs[hi] - xs[lo]) * (k - lo)
+
+
+def serving_bench(nreq, max_slots, chunk):
+    """The serving mix: requests arrive on a seeded Poisson stream (mean
+    200/s); continuous batching through the request server against the same
+    requests solved one at a time in arrival order with the single-context
+    calls.  Latency = done - arrival."""
+    import numpy as np
+
+    from paper_2301_08275_amd import gpe
+    from paper_2301_08275_amd import inputs as I
+
+    trace = I.serving_trace(nreq)
+    psis = [I.psi0_of(r) for r in trace]
+    work = sum(float(np.prod(r["shape"])) * r["nsteps"] for r in trace)
+
+    def submit_args(r, p):
+        return dict(shape=r["shape"], lo=r["lo"], hi=r["hi"], g=r["g"], psi0=p, mode=r["mode"],
+                    dt=r["dt"], nsteps=r["nsteps"], precision=r["precision"], trap=r["trap"])
+
+    srv = gpe.Server(max_slots=max_slots, chunk_steps=chunk)
+    t0 = time.perf_counter()
+    ids = []
+    for r, p in zip(trace, psis):
+        delay = t0 + r["arrival"] - time.perf_counter()
+        if delay > 0:
+            time.sleep(delay)
+        ids.append(srv.submit(**submit_args(r, p)))
+    srv.wait_idle()
+    res = [srv.poll(i) for i in ids]
+    srv.close()
+    ok = sum(1 for x in res if x["status"] == gpe.GPE_OK)
+    lat = [x["t_done"] - x["t_submit"] for x in res]
+    span = max(x["t_done"] for x in res) - min(x["t_submit"] for x in res)
+
+    # one at a time, same arrivals, single-context calls
+    clock, lat1 = 0.0, []
+    for r, p in zip(trace, psis):
+        start = max(clock, r["arrival"])
+        ts = time.perf_counter()
+        with gpe.Context(r["shape"], r["lo"], r["hi"], r["g"], precision=r["precision"],
+                         harmonic=r["trap"]) as ctx:
+            ctx.set_state(p)
+            if r["mode"] == "real":
+                ctx.evolve(r["dt"], r["nsteps"])
+            else:
+                ctx.imag_steps(r["dt"], r["nsteps"])
+            ctx.observables()
+        clock = start + (time.perf_counter() - ts)
+        lat1.append(clock - r["arrival"])
+    span1 = clock - trace[0]["arrival"]
+    return {"requests": nreq, "completed_ok": ok, "offered_rate_per_s": 200.0,
+            "offered_site_steps": work, "max_slots": max_slots, "chunk_steps": chunk,
+            "p50_latency_s": percentile(lat, 0.5), "p99_latency_s": percentile(lat, 0.99),
+            "makespan_s": span, "site_steps_per_s": work / span,
+            "one_at_a_time": {"p50_latency_s": percentile(lat1, 0.5),
+                              "p99_latency_s": percentile(lat1, 0.99),
+                              "makespan_s": span1, "site_steps_per_s": work / span1}}
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -153,6 +223,10 @@ def main():
     ap.add_argument("--no-cpu", action="store_true")
     ap.add_argument("--no-fp32", action="store_true")
     ap.add_argument("--copy-calibration", action="store_true")
+    ap.add_argument("--serving", type=int, default=64,
+                    help="requests of the serving mix to run (0: skip)")
+    ap.add_argument("--serving-slots", type=int, default=16)
+    ap.add_argument("--serving-chunk", type=int, default=16)
     args = ap.parse_args()
     if args.gpus != 1:
         print("bench.py measures one GPU: this build has no multi-GPU path "
@@ -240,6 +314,9 @@ def main():
                        "dominant_kernel": n32, "achieved_GBps": ach32,
                        "frac": ach32 / HBM_PEAK_GBS,
                        "kernels": kernel_table(r32["kinds"])}
+    if args.serving > 0:
+        log("serving mix: %d requests" % args.serving)
+        out["serving"] = serving_bench(args.serving, args.serving_slots, args.serving_chunk)
     if not args.no_cpu:
         log("timing the CPU oracle")
         out["cpu_baseline"] = cpu_baseline(n, seed)

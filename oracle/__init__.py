@@ -20,7 +20,7 @@ _lib = None
 
 def build(force=True):
     """Compile the oracle library with g++ (plain -O2, no fast-math)."""
-    from .build import build_oracle
+    from .buildlib import build_oracle
 
     build_oracle(force=force)
 

@@ -381,7 +381,7 @@ __device__ __forceinline__ void inverse_fft(cx<T> *v, int t, int c, T *lre, T *l
   stage<PL, 0, +1>(v, t, tw);
 }
 
-__device__ __forceinline__ double site_potential(const PassArgs &a, int vkind, const double *hv,
+__device__ __forceinline__ double site_potential(const PassArgs &a, int vkind, const double (&hv)[3],
                                                  int j0, int j1, int j2) {
   if (vkind == V_NONE) return 0.0;
   if (vkind == V_ARRAY) return a.V[((long long)j0 * a.n[1] + j1) * a.n[2] + j2];
@@ -508,12 +508,15 @@ axis_pass_kernel(const PassArgs a) {
   void *pdst = a.dst;
   const void *ptab = a.mtab;
   const double *pscale = a.scale;
-  const double *hv = a.hv;
+  // (copied by value: a pointer that may point into the kernel arguments
+  // would force them into private memory)
+  double hv[3] = {a.hv[0], a.hv[1], a.hv[2]};
   int vkind = a.vkind;
   double g = a.g, tau_pre = a.tau_pre, tau_post = a.tau_post;
   double *partial = a.partial;
   if constexpr (SL) {
-    const Slot &sl = a.slots[blockIdx.y];
+    const int si = a.slot_map ? a.slot_map[blockIdx.y] : (int)blockIdx.y;
+    const Slot &sl = a.slots[si];
     if (sl.mode == SLOT_FREE || sl.steps_done >= sl.steps_total) return;
     const bool im = sl.mode == SLOT_IMAG;
     const bool first = a.slot_pass & SLOT_PASS_FIRST, last = a.slot_pass & SLOT_PASS_LAST;
@@ -521,7 +524,9 @@ axis_pass_kernel(const PassArgs a) {
     pdst = sl.psi;
     ptab = im ? a.mtab_imag : a.mtab;
     g = sl.g;
-    hv = sl.hv;
+    hv[0] = sl.hv[0];
+    hv[1] = sl.hv[1];
+    hv[2] = sl.hv[2];
     vkind = (hv[0] != 0 || hv[1] != 0 || hv[2] != 0) ? V_HARMONIC : V_NONE;
     pre = first ? (im ? PH_IMAG : PH_REAL) : PH_NONE;
     tau_pre = (im || sl.steps_done == 0) ? 0.5 * a.dt : a.dt;
@@ -532,7 +537,7 @@ axis_pass_kernel(const PassArgs a) {
                 : PH_NONE;
     tau_post = 0.5 * a.dt;
     red = (last && im) ? RED_NORM_OUT : RED_NONE;
-    partial = a.partial + (long long)blockIdx.y * gridDim.x * kRedSlots;
+    partial = a.partial + (long long)si * gridDim.x * kRedSlots;
   }
 
   const int tid = threadIdx.x;

@@ -77,6 +77,7 @@ struct PassArgs {
   double *partial;      // reductions, kRedSlots doubles per workgroup
   // batched shape class (MODE_SLOTS): per-slot state and operations
   Slot *slots;
+  const int *slot_map;  // grid row -> slot index (null: row = slot)
   int nslots;           // grid rows (blockIdx.y) of a batched launch
   int slot_pass;        // SLOT_PASS_FIRST | SLOT_PASS_LAST bits
   double dt;

@@ -81,6 +81,10 @@ struct ShapeClass {
   long long bpg_last = 0;
   void *kreal[3] = {nullptr, nullptr, nullptr}, *kimag[3] = {nullptr, nullptr, nullptr};
   hipGraphExec_t graph = nullptr;
+  bool use_graph = false;             // small grids: replay chunks from a graph over all slots
+  int *d_map = nullptr;               // large grids: launch rows for the active slots only
+  std::vector<int> h_map;
+  bool map_dirty = true;
   int active = 0;
   bool failed = false;                // a chunk failed to launch this round
   uint64_t fixed_bytes = 0;           // proto context + slot table + partials
@@ -93,6 +97,7 @@ void destroy_class(ShapeClass *c) {
   if (c->proto) gpe_destroy(c->proto);
   if (c->d) (void)hipFree(c->d);
   if (c->partial) (void)hipFree(c->partial);
+  if (c->d_map) (void)hipFree(c->d_map);
   delete c;
 }
 
@@ -144,7 +149,7 @@ uint64_t class_bytes(const gpe_desc &d, int max_slots) {
   const long long bpg =
       gpe::pass_shape(d.precision, n3, last, last == 0 ? wlast : (d.precision == GPE_FP32 ? 16 : 8))
           .blocks;
-  return context_bytes(d) + ktabs + (uint64_t)max_slots * sizeof(gpe::Slot) +
+  return context_bytes(d) + ktabs + (uint64_t)max_slots * (sizeof(gpe::Slot) + sizeof(int)) +
          (uint64_t)max_slots * bpg * gpe::kRedSlots * sizeof(double);
 }
 
@@ -154,16 +159,21 @@ ShapeClass *find_class(gpe_server *s, const ClassKey &k) {
   return nullptr;
 }
 
-// Enqueue one batched step of class c on the server stream.
+// Enqueue one batched step of class c on the server stream: graph classes
+// launch a row per slot (free or finished rows return at once); the others a
+// row per active slot through the slot map.
 gpe_status enqueue_step(gpe_server *s, ShapeClass *c) {
   gpe_ctx *p = c->proto;
   const int na = n_axes(p);
+  const int rows = c->use_graph ? c->S : (int)c->h_map.size();
+  if (rows == 0) return GPE_OK;
   for (int i = 0; i < na; ++i) {
     const int ax = order_axis(p, i);
     gpe::PassArgs a = base_args(p, ax);
     a.mid = gpe::MID_TABLE;
     a.slots = c->d;
-    a.nslots = c->S;
+    a.slot_map = c->use_graph ? nullptr : c->d_map;
+    a.nslots = rows;
     a.slot_pass = (i == 0 ? gpe::SLOT_PASS_FIRST : 0) | (i == na - 1 ? gpe::SLOT_PASS_LAST : 0);
     a.dt = c->key.dt;
     a.mtab = c->kreal[ax];
@@ -179,7 +189,17 @@ gpe_status enqueue_step(gpe_server *s, ShapeClass *c) {
 }
 
 gpe_status run_chunk(gpe_server *s, ShapeClass *c) {
-  if (!s->use_graph) {
+  if (!c->use_graph) {
+    if (c->map_dirty) {
+      c->h_map.clear();
+      for (int i = 0; i < c->S; ++i)
+        if (c->owner[i]) c->h_map.push_back(i);
+      if (!c->h_map.empty() &&
+          hipMemcpyAsync(c->d_map, c->h_map.data(), c->h_map.size() * sizeof(int),
+                         hipMemcpyHostToDevice, s->stream) != hipSuccess)
+        return GPE_EDEVICE;
+      c->map_dirty = false;
+    }
     for (int k = 0; k < s->chunk; ++k) {
       gpe_status st = enqueue_step(s, c);
       if (st != GPE_OK) return st;
@@ -227,18 +247,23 @@ gpe_status create_class(gpe_server *s, const gpe_request &r, ShapeClass **out) {
   }
   const int last = order_axis(p, n_axes(p) - 1);
   c->bpg_last = gpe::pass_shape(p->prec, p->n3, last, p->wreq[last]).blocks;
+  // Graph replay over all slots pays for the empty rows' dispatch, which is
+  // negligible for small grids (where launch latency dominates) and not for
+  // large ones.
+  c->use_graph = s->use_graph && p->sites * c->S <= (1LL << 22);
   c->h.assign(c->S, gpe::Slot{});
   c->owner.assign(c->S, 0);
   c->ctx.assign(c->S, nullptr);
   const size_t pbytes = (size_t)c->S * c->bpg_last * gpe::kRedSlots * sizeof(double);
   if (hipMalloc(&c->d, c->S * sizeof(gpe::Slot)) != hipSuccess ||
       hipMalloc(&c->partial, pbytes) != hipSuccess ||
+      hipMalloc(&c->d_map, c->S * sizeof(int)) != hipSuccess ||
       hipMemcpyAsync(c->d, c->h.data(), c->S * sizeof(gpe::Slot), hipMemcpyHostToDevice,
                      s->stream) != hipSuccess) {
     destroy_class(c);
     return GPE_ENOMEM;
   }
-  c->fixed_bytes = p->dev_bytes + c->S * sizeof(gpe::Slot) + pbytes;  // tables included
+  c->fixed_bytes = p->dev_bytes + c->S * (sizeof(gpe::Slot) + sizeof(int)) + pbytes;
   s->used += c->fixed_bytes;
   s->classes.push_back(c);
   *out = c;
@@ -315,6 +340,7 @@ gpe_status admit(gpe_server *s, Req *r) {
     return GPE_EDEVICE;
   c->owner[i] = r->id;
   ++c->active;
+  c->map_dirty = true;
   r->cls = (int)(std::find(s->classes.begin(), s->classes.end(), c) - s->classes.begin());
   r->slot = i;
   return GPE_OK;
@@ -342,6 +368,7 @@ void complete(gpe_server *s, ShapeClass *c, int i, Req *r, bool cancelled) {
   (void)hipMemcpyAsync(c->d + i, &c->h[i], sizeof(gpe::Slot), hipMemcpyHostToDevice, s->stream);
   c->owner[i] = 0;
   --c->active;
+  c->map_dirty = true;
   {
     std::lock_guard<std::mutex> lk(s->mu);
     --s->running;
@@ -425,6 +452,7 @@ void scheduler(gpe_server *s) {
         if (c->failed) {
           c->owner[i] = 0;
           --c->active;
+          c->map_dirty = true;
           c->h[i].mode = gpe::SLOT_FREE;
           (void)hipMemcpyAsync(c->d + i, &c->h[i], sizeof(gpe::Slot), hipMemcpyHostToDevice,
                                s->stream);

@@ -165,3 +165,39 @@ def bao_initial(shape, lo, hi, gamma_y=2.0, gamma_z=4.0, eps1=0.25):
     """Dynamics-validation initial state: exp(-(x^2 + gy y^2 + gz z^2)/(2 eps1)),
     normalised numerically to 1."""
     return gaussian(shape, lo, hi, widths=[1.0, gamma_y, gamma_z][: len(shape)], eps=eps1)
+
+
+def serving_trace(nreq, seed=4, rate=200.0, box=8.0):
+    """The serving mix: a seeded Poisson stream of independent solves.
+
+    Request i draws (in this order, from stream `seed`, 8 uniforms each):
+    inter-arrival time (exponential, mean 1/rate), 2D (60 %) or 3D (40 %),
+    grid size uniform over {64, 128, 256, 512}^2 or {64, 128, 256}^3, trap
+    anisotropy a ~ U[1, 8] (V = (x^2 + a^2 y^2)/2 in 2D, (x^2 + y^2 + a^2 z^2)/2
+    in 3D), g ~ U[0, 100], ground state or real time (half each; both a fixed
+    step count), steps ~ U{200..2000}, FP32 or FP64 (half each).  The box is
+    [-box, box)^d and dt = 1e-3.  The initial state (psi0_of) is a Gaussian with
+    1 % noise seeded by the request index.
+    """
+    u = uniform(seed, 8 * nreq).reshape(nreq, 8)
+    t = 0.0
+    out = []
+    for i in range(nreq):
+        t += -math.log(1.0 - u[i, 0]) / rate
+        dim = 2 if u[i, 1] < 0.6 else 3
+        sizes = (64, 128, 256, 512) if dim == 2 else (64, 128, 256)
+        n = sizes[min(len(sizes) - 1, int(u[i, 2] * len(sizes)))]
+        a = 1.0 + 7.0 * u[i, 3]
+        g = 100.0 * u[i, 4]
+        mode = "imag" if u[i, 5] < 0.5 else "real"
+        steps = 200 + min(1800, int(u[i, 6] * 1801))
+        prec = "fp32" if u[i, 7] < 0.5 else "fp64"
+        trap = [1.0, a] if dim == 2 else [1.0, 1.0, a]
+        out.append(dict(index=i, arrival=t, shape=(n,) * dim, lo=(-box,) * dim, hi=(box,) * dim,
+                        g=g, trap=trap, mode=mode, nsteps=steps, dt=1e-3, precision=prec))
+    return out
+
+
+def psi0_of(req, seed_base=40000):
+    """Initial state of a serving request (see serving_trace)."""
+    return noisy_gaussian(req["shape"], req["lo"], req["hi"], seed=seed_base + req["index"])
