@@ -197,10 +197,13 @@ void gpe_destroy(gpe_ctx *ctx);
  * which solves one problem per run).  Independent solves of the problems
  * above are submitted from any host thread; a scheduler thread admits them in
  * arrival order while the HBM budget allows and a slot of their shape class
- * (dim, n, precision, box, dt) is free, runs every active slot of a class in
- * the same batched launches (chunks of steps replayed from a HIP graph), and
- * frees the slot as soon as the request has finished.  Requests of any size
- * mix; each one's arithmetic does not depend on what else runs.
+ * (dim, n, precision, box, dt) is free, and runs in rounds: each round gives
+ * every shape class with running requests one chunk of batched steps (all its
+ * slots in the same launches), sized so that each running request receives
+ * about the same GPU time per round (1 ms), and finishes the requests that
+ * the previous round completed while the GPU runs the current one.  Requests
+ * of any size mix; each one's arithmetic does not depend on what else runs,
+ * nor on how its steps are cut into chunks.
  * ---------------------------------------------------------------------- */
 typedef struct gpe_server gpe_server; /* opaque, library-owned */
 
@@ -230,9 +233,10 @@ typedef struct {
 
 /* Create a server on the current HIP device.  hbm_budget_bytes caps the
  * device memory of admitted requests (0: the device's free memory);
- * max_slots is the slot count of each shape class (>= 1); max_active caps the
- * requests running at once over all classes (0: no cap; 1: one at a time);
- * chunk_steps is the number of steps between completion checks (>= 1). */
+ * max_slots is the slot count of each shape class (1..256, else
+ * GPE_EUNSUPPORTED); max_active caps the requests running at once over all
+ * classes (0: no cap; 1: one at a time); chunk_steps (>= 1) is the length of
+ * the step graph replayed for small grids, whose chunks are whole replays. */
 gpe_status gpe_server_create(uint64_t hbm_budget_bytes, int32_t max_slots, int32_t max_active,
                              int32_t chunk_steps, gpe_server **out);
 
@@ -245,7 +249,8 @@ gpe_status gpe_server_submit(gpe_server *srv, const gpe_request *req, uint64_t *
  * state (host FP64).  A finished request can be polled any number of times. */
 gpe_status gpe_server_poll(gpe_server *srv, uint64_t id, gpe_result *out, double *psi_out);
 
-/* Cancel a queued or running request (finishes with GPE_ECANCELED). */
+/* Cancel a queued or running request (finishes with GPE_ECANCELED, without
+ * observables or final state). */
 gpe_status gpe_server_cancel(gpe_server *srv, uint64_t id);
 
 /* Block until no request is queued or running. */

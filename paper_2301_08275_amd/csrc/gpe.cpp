@@ -497,7 +497,7 @@ gpe_status compute_spectra(gpe_ctx *c, gpe_spectra *spec) {
 
 // Device bytes gpe_create allocates for desc (state, partials, sums, scale,
 // twiddles and E_kin weights per axis); must follow gpe_create.
-uint64_t context_bytes(const gpe_desc &d) {
+uint64_t context_bytes(const gpe_desc &d, bool with_state) {
   int n3[3] = {1, 1, 1};
   const int off = 3 - d.dim;
   long long sites = 1;
@@ -514,7 +514,7 @@ uint64_t context_bytes(const gpe_desc &d) {
     if (sh.blocks > maxb) maxb = sh.blocks;
     tables += (uint64_t)n3[ax] * (16 + sizeof(double));
   }
-  return (uint64_t)sites * es + 3 * (uint64_t)maxb * gpe::kRedSlots * sizeof(double) +
+  return (with_state ? (uint64_t)sites * es : 0) + 3 * (uint64_t)maxb * gpe::kRedSlots * sizeof(double) +
          4 * gpe::kRedSlots * sizeof(double) + sizeof(double) + tables;
 }
 
@@ -526,6 +526,15 @@ extern "C" {
 
 gpe_status gpe_create(const gpe_desc *desc, const double *V_host, const gpe_harmonic *V_an,
                       void *hip_stream, gpe_ctx **out) {
+  return create_context(desc, V_host, V_an, hip_stream, true, out);
+}
+
+}  // extern "C"
+
+namespace gpe_host {
+
+gpe_status create_context(const gpe_desc *desc, const double *V_host, const gpe_harmonic *V_an,
+                          void *hip_stream, bool with_state, gpe_ctx **out) {
   if (!out) return fail(nullptr, GPE_EINVAL, "out is NULL");
   *out = nullptr;
   std::string msg;
@@ -576,9 +585,12 @@ gpe_status gpe_create(const gpe_desc *desc, const double *V_host, const gpe_harm
     gpe_destroy(c);
     return s;
   };
-  if ((st = dalloc(c, &c->psi, c->sites * c->esize, "state allocation")) != GPE_OK) return bail(st);
-  if (hipMemset(c->psi, 0, c->sites * c->esize) != hipSuccess)
-    return bail(fail(c, GPE_EDEVICE, "state clear"));
+  if (with_state) {
+    if ((st = dalloc(c, &c->psi, c->sites * c->esize, "state allocation")) != GPE_OK)
+      return bail(st);
+    if (hipMemset(c->psi, 0, c->sites * c->esize) != hipSuccess)
+      return bail(fail(c, GPE_EDEVICE, "state clear"));
+  }
   // Tuning overrides for experiments: strided workgroup widths per axis.
   if (const char *w = std::getenv("GPE_TUNE_WX")) c->wreq[0] = std::atoi(w);
   if (const char *w = std::getenv("GPE_TUNE_WY")) c->wreq[1] = std::atoi(w);
@@ -611,6 +623,10 @@ gpe_status gpe_create(const gpe_desc *desc, const double *V_host, const gpe_harm
   *out = c;
   return GPE_OK;
 }
+
+}  // namespace gpe_host
+
+extern "C" {
 
 gpe_status gpe_set_potential(gpe_ctx *c, const double *V_host, const gpe_harmonic *V_an) {
   if (!c) return GPE_EINVAL;

@@ -86,6 +86,11 @@ gpe_status compute_obs(gpe_ctx *c, const double *scale, gpe_obs *o);
 int n_axes(const gpe_ctx *c);
 int order_axis(const gpe_ctx *c, int i);
 int view_axis(const gpe_ctx *c, int user_axis);
-uint64_t context_bytes(const gpe_desc &d);
+// Device bytes of a context (with_state: including the state array).
+uint64_t context_bytes(const gpe_desc &d, bool with_state = true);
+// gpe_create, optionally without the state array (a holder of the tables of
+// a shape class, used only for its geometry, twiddles and weights).
+gpe_status create_context(const gpe_desc *desc, const double *V_host, const gpe_harmonic *V_an,
+                          void *hip_stream, bool with_state, gpe_ctx **out);
 
 }  // namespace gpe_host

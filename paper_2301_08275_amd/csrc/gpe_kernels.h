@@ -134,6 +134,19 @@ hipError_t launch_sum_columns(const double *partial, long long count, int len, d
 hipError_t launch_slot_update(Slot *slots, int nslots, const double *partial,
                               long long blocks_per_grid, double dV, hipStream_t s);
 
+// Most slots a shape class holds (the active-slot map travels as a kernel
+// argument).
+constexpr int kMaxSlots = 256;
+struct SlotMap {
+  int n;
+  int idx[kMaxSlots];
+};
+// Stream-ordered writes of one slot-table entry and of the active-slot map.
+// The values travel as kernel arguments, so no host buffer has to outlive the
+// call.
+hipError_t launch_slot_write(Slot *dst, const Slot &value, hipStream_t s);
+hipError_t launch_map_write(int *dst, const SlotMap &m, hipStream_t s);
+
 // Precision conversion copies (device to device).
 hipError_t launch_convert(int src_prec, const void *src, int dst_prec, void *dst,
                           long long sites, hipStream_t s);

@@ -74,6 +74,12 @@ slot_update_kernel(Slot *__restrict__ slots, const double *__restrict__ partial,
   if (tid == 0) sl.steps_done += 1;
 }
 
+__global__ void slot_write_kernel(Slot *dst, Slot value) { *dst = value; }
+
+__global__ void map_write_kernel(int *dst, SlotMap m) {
+  for (int i = threadIdx.x; i < m.n; i += blockDim.x) dst[i] = m.idx[i];
+}
+
 template <typename S, typename D>
 __global__ void convert_kernel(const S *__restrict__ src, D *__restrict__ dst, long long n) {
   for (long long i = (long long)blockIdx.x * blockDim.x + threadIdx.x; i < n;
@@ -101,6 +107,17 @@ hipError_t launch_slot_update(Slot *slots, int nslots, const double *partial,
                               long long blocks_per_grid, double dV, hipStream_t s) {
   hipLaunchKernelGGL(slot_update_kernel, dim3(nslots), dim3(kFinThreads), 0, s, slots, partial,
                      blocks_per_grid, dV);
+  return hipGetLastError();
+}
+
+hipError_t launch_slot_write(Slot *dst, const Slot &value, hipStream_t s) {
+  hipLaunchKernelGGL(slot_write_kernel, dim3(1), dim3(1), 0, s, dst, value);
+  return hipGetLastError();
+}
+
+hipError_t launch_map_write(int *dst, const SlotMap &m, hipStream_t s) {
+  if (m.n < 1 || m.n > kMaxSlots) return hipErrorInvalidValue;
+  hipLaunchKernelGGL(map_write_kernel, dim3(1), dim3(256), 0, s, dst, m);
   return hipGetLastError();
 }
 

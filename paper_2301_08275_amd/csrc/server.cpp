@@ -1,21 +1,31 @@
 // Serving scheduler behind the gpe_server_* calls of include/gpe.h.
 //
-// One scheduler thread owns every GPU call.  Requests wait in arrival order;
-// the head is admitted while the HBM budget allows and a slot of its shape
-// class (dim, n, precision, box, dt) is free.  Every class keeps a
-// device-resident slot table; one chunk of steps runs all active slots of a
-// class in the same batched launches (the fused axis passes in slot mode, then
-// a slot-update kernel), replayed from a HIP graph captured once per class.
-// Slots that are free or finished return at once, so admissions and
-// completions never change the launches.  After each chunk the scheduler reads
-// the slot table back, finishes the requests whose steps are done (final
-// imaginary-time scaling, observables, optional state copy) and frees their
-// slots for the queue.
+// One scheduler thread owns every GPU call and works in rounds.  A round
+//  1. admits queued requests in arrival order while the HBM budget allows and
+//     a slot of their shape class (dim, n, precision, box, dt) is free: the
+//     state upload goes to a side stream while the GPU still runs the previous
+//     round, and the slot-table entry is written on the main stream after it;
+//  2. enqueues one chunk of batched steps per shape class with requests in it
+//     (the fused axis passes in slot mode, then the slot-update kernel).  Small
+//     classes replay a captured graph over all slots, large ones launch rows
+//     for their owned slots only.  Chunks are sized from the measured GPU time
+//     per step so that every running request receives about the same GPU time
+//     per round, whatever its grid: small solves finish in few rounds instead
+//     of advancing at the pace of the largest grid;
+//  3. copies the slot tables back and only then waits for the previous
+//     round's chunk, and finishes the requests that chunk completed (final
+//     imaginary-time scaling, observables, optional state download, all on the
+//     side stream) while the GPU runs the chunk just enqueued.
+// A finished or free slot costs its rows an early return, so a request that
+// completes inside a chunk never changes the launches, and its state is left
+// alone by the chunk that follows; that is what lets the host finish it one
+// round late without stalling the GPU.
 #include <algorithm>
 #include <atomic>
 #include <chrono>
 #include <condition_variable>
 #include <cmath>
+#include <cstdlib>
 #include <cstring>
 #include <deque>
 #include <map>
@@ -36,7 +46,8 @@ enum ReqState { RQ_QUEUED = 0, RQ_RUNNING = 1, RQ_DONE = 2 };
 struct Req {
   uint64_t id = 0;
   gpe_request r{};
-  std::vector<double> psi0;
+  std::vector<double> psi0_d;  // FP64 classes: the initial state as given
+  std::vector<float> psi0_f;   // FP32 classes: rounded once at submit
   ReqState state = RQ_QUEUED;
   gpe_status status = GPE_EBUSY;
   gpe_obs obs{};
@@ -46,7 +57,6 @@ struct Req {
   bool cancel = false;
   uint64_t need = 0;        // device bytes a fresh slot context takes
   uint64_t need_class = 0;  // device bytes a new shape class takes
-  int cls = -1, slot = -1;
 };
 
 struct ClassKey {
@@ -69,47 +79,57 @@ ClassKey key_of(const gpe_request &r) {
   return k;
 }
 
+// Slot life: free -> running -> (finished and released) or draining -> free.
+// A draining slot (cancelled, or its chunk failed) has had its table entry
+// cleared on the main stream but may still be touched by a chunk already in
+// flight; it is released once that chunk is known to be done.
+enum SlotState { SS_FREE = 0, SS_RUN = 1, SS_DRAIN = 2 };
+
 struct ShapeClass {
   ClassKey key{};
   int S = 0;
-  gpe_ctx *proto = nullptr;           // owns the class tables
-  std::vector<gpe_ctx *> ctx;         // per slot, kept for reuse while memory allows
-  std::vector<gpe::Slot> h;           // host mirror of the slot table
-  gpe::Slot *d = nullptr;             // device slot table
-  std::vector<uint64_t> owner;        // request id per slot (0: free)
-  double *partial = nullptr;          // norm partials, S x blocks of the last pass
+  gpe_ctx *proto = nullptr;             // geometry, twiddles, weights; no state
+  std::vector<gpe_ctx *> ctx;           // per slot, kept for reuse while memory allows
+  std::vector<uint64_t> owner;          // request id per slot (0: none)
+  std::vector<int> sstate;              // SlotState
+  std::vector<int> steps_total;
+  std::vector<long long> admit_round;   // round whose chunk first ran the slot
+  std::vector<long long> drain_until;   // draining: last round whose chunk may touch it
+  std::vector<gpe_status> drain_status;
+  gpe::Slot *d = nullptr;               // device slot table
+  gpe::Slot *hp[2] = {nullptr, nullptr};  // pinned read-backs, by round parity
+  bool hp_valid[2] = {false, false};
+  bool failed[2] = {false, false};
+  double *partial = nullptr;            // norm partials, S x blocks of the last pass
   long long bpg_last = 0;
   void *kreal[3] = {nullptr, nullptr, nullptr}, *kimag[3] = {nullptr, nullptr, nullptr};
   hipGraphExec_t graph = nullptr;
-  bool use_graph = false;             // small grids: replay chunks from a graph over all slots
-  int *d_map = nullptr;               // large grids: launch rows for the active slots only
-  std::vector<int> h_map;
+  bool use_graph = false;               // small grids: replay a chunk graph over all slots
+  int *d_map = nullptr;                 // large grids: rows for the owned slots only
+  int rows = 0;
   bool map_dirty = true;
-  int active = 0;
-  bool failed = false;                // a chunk failed to launch this round
-  uint64_t fixed_bytes = 0;           // proto context + slot table + partials
+  int owned = 0;                        // slots running or draining
+  int running = 0;                      // slots running
+  hipEvent_t ev0[2] = {nullptr, nullptr}, ev1[2] = {nullptr, nullptr};
+  int timed_steps[2] = {0, 0}, timed_running[2] = {0, 0};
+  double step_ms = 0;                   // measured GPU ms per batched step (0: unknown)
+  int step_running = 0;                 // running slots when it was measured
+  uint64_t fixed_bytes = 0;             // table holder + slot table + map + partials
 };
-
-void destroy_class(ShapeClass *c) {
-  if (c->graph) (void)hipGraphExecDestroy(c->graph);
-  for (gpe_ctx *x : c->ctx)
-    if (x) gpe_destroy(x);
-  if (c->proto) gpe_destroy(c->proto);
-  if (c->d) (void)hipFree(c->d);
-  if (c->partial) (void)hipFree(c->partial);
-  if (c->d_map) (void)hipFree(c->d_map);
-  delete c;
-}
 
 }  // namespace
 
 struct gpe_server {
-  hipStream_t stream = nullptr;
+  hipStream_t stream = nullptr;  // batched steps and slot-table writes
+  hipStream_t aux = nullptr;     // uploads, final scaling, observables, downloads
+  hipEvent_t done[2] = {nullptr, nullptr};  // end of a round's chunks and read-backs
+  hipEvent_t ev_up = nullptr;
   int device = 0;
   uint64_t budget = 0;
   std::atomic<uint64_t> used{0};
   int max_slots = 1, max_active = 0, chunk = 16;
   bool use_graph = true;
+  double quantum_ms = 1.0;  // GPU time per running request per round
   std::mutex mu;
   std::condition_variable cv_work, cv_done;
   std::deque<uint64_t> queue;
@@ -136,20 +156,39 @@ long long sites_of(const gpe_desc &d) {
   return n;
 }
 
-// Device bytes a shape class holds besides its slot contexts: the prototype
-// context, its two kinetic tables per axis, the slot table and norm partials.
+void destroy_class(gpe_server *s, ShapeClass *c) {
+  (void)hipStreamSynchronize(s->stream);
+  (void)hipStreamSynchronize(s->aux);
+  if (c->graph) (void)hipGraphExecDestroy(c->graph);
+  for (gpe_ctx *x : c->ctx)
+    if (x) gpe_destroy(x);
+  if (c->proto) gpe_destroy(c->proto);
+  if (c->d) (void)hipFree(c->d);
+  if (c->partial) (void)hipFree(c->partial);
+  if (c->d_map) (void)hipFree(c->d_map);
+  for (int p = 0; p < 2; ++p) {
+    if (c->hp[p]) (void)hipHostFree(c->hp[p]);
+    if (c->ev0[p]) (void)hipEventDestroy(c->ev0[p]);
+    if (c->ev1[p]) (void)hipEventDestroy(c->ev1[p]);
+  }
+  delete c;
+}
+
+// Device bytes a shape class holds besides its slot contexts: the table holder
+// (geometry, twiddles, weights, its partials), two kinetic tables per axis,
+// the slot table, the slot map and the norm partials of every slot.
 uint64_t class_bytes(const gpe_desc &d, int max_slots) {
   int n3[3] = {1, 1, 1};
   const int off = 3 - d.dim;
   for (int j = 0; j < d.dim; ++j) n3[j + off] = d.n[j];
   uint64_t ktabs = 0;
   for (int ax = off; ax < 3; ++ax) ktabs += 2 * (uint64_t)n3[ax] * 16;
-  const int wlast = 16;  // the last pass of the default order is axis 0 (3D) or 1 (2D)
+  // the last pass of the default order is view axis 0 (3D) or 1 (2D)
   const int last = off;
-  const long long bpg =
-      gpe::pass_shape(d.precision, n3, last, last == 0 ? wlast : (d.precision == GPE_FP32 ? 16 : 8))
-          .blocks;
-  return context_bytes(d) + ktabs + (uint64_t)max_slots * (sizeof(gpe::Slot) + sizeof(int)) +
+  const int wlast = last == 0 ? 16 : (d.precision == GPE_FP32 ? 16 : 8);
+  const long long bpg = gpe::pass_shape(d.precision, n3, last, wlast).blocks;
+  return context_bytes(d, false) + ktabs +
+         (uint64_t)max_slots * (sizeof(gpe::Slot) + sizeof(int)) +
          (uint64_t)max_slots * bpg * gpe::kRedSlots * sizeof(double);
 }
 
@@ -159,13 +198,11 @@ ShapeClass *find_class(gpe_server *s, const ClassKey &k) {
   return nullptr;
 }
 
-// Enqueue one batched step of class c on the server stream: graph classes
-// launch a row per slot (free or finished rows return at once); the others a
-// row per active slot through the slot map.
+// One batched step of class c on the main stream.
 gpe_status enqueue_step(gpe_server *s, ShapeClass *c) {
   gpe_ctx *p = c->proto;
   const int na = n_axes(p);
-  const int rows = c->use_graph ? c->S : (int)c->h_map.size();
+  const int rows = c->use_graph ? c->S : c->rows;
   if (rows == 0) return GPE_OK;
   for (int i = 0; i < na; ++i) {
     const int ax = order_axis(p, i);
@@ -179,8 +216,7 @@ gpe_status enqueue_step(gpe_server *s, ShapeClass *c) {
     a.mtab = c->kreal[ax];
     a.mtab_imag = c->kimag[ax];
     a.partial = c->partial;
-    hipError_t e = gpe::launch_axis_pass(p->prec, a, s->stream);
-    if (e != hipSuccess) return GPE_EDEVICE;
+    if (gpe::launch_axis_pass(p->prec, a, s->stream) != hipSuccess) return GPE_EDEVICE;
   }
   return gpe::launch_slot_update(c->d, c->S, c->partial, c->bpg_last, p->dV, s->stream) ==
                  hipSuccess
@@ -188,19 +224,41 @@ gpe_status enqueue_step(gpe_server *s, ShapeClass *c) {
              : GPE_EDEVICE;
 }
 
-gpe_status run_chunk(gpe_server *s, ShapeClass *c) {
+// Steps to give class c this round: quantum_ms of GPU time per running
+// request, from the GPU time per step measured on its last chunk.  Large
+// grids are bandwidth-bound (time grows with the running slots); small ones
+// are launch-bound (it does not), and run whole graph replays.
+int steps_for(gpe_server *s, ShapeClass *c) {
+  const int run = std::max(1, c->running);
+  double ms = c->step_ms;
+  if (ms <= 0) {
+    if (c->use_graph) return s->chunk;
+    const double bytes = 6.0 * (double)run * (double)c->proto->sites * (double)c->proto->esize;
+    ms = 0.02 + bytes / 4.0e9;  // about 4 TB/s per pass, read and write
+  } else if (!c->use_graph && c->step_running > 0) {
+    ms *= (double)run / (double)c->step_running;
+  }
+  const double k = s->quantum_ms * run / ms;
+  if (c->use_graph) {
+    const long long reps = std::max(1LL, std::min(256LL, std::llround(k / s->chunk)));
+    return (int)(reps * s->chunk);
+  }
+  return (int)std::max(1LL, std::min(4096LL, std::llround(k)));
+}
+
+gpe_status run_chunk(gpe_server *s, ShapeClass *c, int steps) {
   if (!c->use_graph) {
     if (c->map_dirty) {
-      c->h_map.clear();
+      gpe::SlotMap m;
+      m.n = 0;
       for (int i = 0; i < c->S; ++i)
-        if (c->owner[i]) c->h_map.push_back(i);
-      if (!c->h_map.empty() &&
-          hipMemcpyAsync(c->d_map, c->h_map.data(), c->h_map.size() * sizeof(int),
-                         hipMemcpyHostToDevice, s->stream) != hipSuccess)
+        if (c->owner[i]) m.idx[m.n++] = i;
+      if (m.n > 0 && gpe::launch_map_write(c->d_map, m, s->stream) != hipSuccess)
         return GPE_EDEVICE;
+      c->rows = m.n;
       c->map_dirty = false;
     }
-    for (int k = 0; k < s->chunk; ++k) {
+    for (int k = 0; k < steps; ++k) {
       gpe_status st = enqueue_step(s, c);
       if (st != GPE_OK) return st;
     }
@@ -223,7 +281,9 @@ gpe_status run_chunk(gpe_server *s, ShapeClass *c) {
       return GPE_EDEVICE;
     }
   }
-  return hipGraphLaunch(c->graph, s->stream) == hipSuccess ? GPE_OK : GPE_EDEVICE;
+  for (int k = 0; k < steps; k += s->chunk)
+    if (hipGraphLaunch(c->graph, s->stream) != hipSuccess) return GPE_EDEVICE;
+  return GPE_OK;
 }
 
 gpe_status create_class(gpe_server *s, const gpe_request &r, ShapeClass **out) {
@@ -231,9 +291,9 @@ gpe_status create_class(gpe_server *s, const gpe_request &r, ShapeClass **out) {
   c->key = key_of(r);
   c->S = s->max_slots;
   gpe_desc d = r.desc;
-  gpe_status st = gpe_create(&d, nullptr, nullptr, s->stream, &c->proto);
+  gpe_status st = create_context(&d, nullptr, nullptr, s->stream, false, &c->proto);
   if (st != GPE_OK) {
-    destroy_class(c);
+    destroy_class(s, c);
     return st;
   }
   gpe_ctx *p = c->proto;
@@ -241,7 +301,7 @@ gpe_status create_class(gpe_server *s, const gpe_request &r, ShapeClass **out) {
     const int ax = order_axis(p, i);
     if ((st = get_table(p, ax, TB_KREAL, r.dt, &c->kreal[ax])) != GPE_OK ||
         (st = get_table(p, ax, TB_KIMAG, r.dt, &c->kimag[ax])) != GPE_OK) {
-      destroy_class(c);
+      destroy_class(s, c);
       return st;
     }
   }
@@ -251,16 +311,26 @@ gpe_status create_class(gpe_server *s, const gpe_request &r, ShapeClass **out) {
   // negligible for small grids (where launch latency dominates) and not for
   // large ones.
   c->use_graph = s->use_graph && p->sites * c->S <= (1LL << 22);
-  c->h.assign(c->S, gpe::Slot{});
   c->owner.assign(c->S, 0);
+  c->sstate.assign(c->S, SS_FREE);
+  c->steps_total.assign(c->S, 0);
+  c->admit_round.assign(c->S, 0);
+  c->drain_until.assign(c->S, 0);
+  c->drain_status.assign(c->S, GPE_OK);
   c->ctx.assign(c->S, nullptr);
   const size_t pbytes = (size_t)c->S * c->bpg_last * gpe::kRedSlots * sizeof(double);
-  if (hipMalloc(&c->d, c->S * sizeof(gpe::Slot)) != hipSuccess ||
-      hipMalloc(&c->partial, pbytes) != hipSuccess ||
-      hipMalloc(&c->d_map, c->S * sizeof(int)) != hipSuccess ||
-      hipMemcpyAsync(c->d, c->h.data(), c->S * sizeof(gpe::Slot), hipMemcpyHostToDevice,
-                     s->stream) != hipSuccess) {
-    destroy_class(c);
+  const size_t tbytes = (size_t)c->S * sizeof(gpe::Slot);
+  std::vector<gpe::Slot> zero(c->S, gpe::Slot{});
+  bool ok = hipMalloc(&c->d, tbytes) == hipSuccess &&
+            hipMalloc(&c->partial, pbytes) == hipSuccess &&
+            hipMalloc(&c->d_map, c->S * sizeof(int)) == hipSuccess &&
+            hipHostMalloc((void **)&c->hp[0], tbytes, hipHostMallocDefault) == hipSuccess &&
+            hipHostMalloc((void **)&c->hp[1], tbytes, hipHostMallocDefault) == hipSuccess;
+  for (int q = 0; ok && q < 2; ++q)
+    ok = hipEventCreate(&c->ev0[q]) == hipSuccess && hipEventCreate(&c->ev1[q]) == hipSuccess;
+  ok = ok && hipMemcpy(c->d, zero.data(), tbytes, hipMemcpyHostToDevice) == hipSuccess;
+  if (!ok) {
+    destroy_class(s, c);
     return GPE_ENOMEM;
   }
   c->fixed_bytes = p->dev_bytes + c->S * (sizeof(gpe::Slot) + sizeof(int)) + pbytes;
@@ -284,9 +354,9 @@ void reclaim(gpe_server *s, uint64_t need, const ClassKey &keep) {
   }
   for (size_t k = 0; k < s->classes.size() && s->used + need > s->budget;) {
     ShapeClass *c = s->classes[k];
-    if (c->active == 0 && !(c->key == keep)) {
+    if (c->owned == 0 && !(c->key == keep)) {
       s->used -= c->fixed_bytes;
-      destroy_class(c);
+      destroy_class(s, c);
       s->classes.erase(s->classes.begin() + k);
     } else {
       ++k;
@@ -299,34 +369,47 @@ void finish(gpe_server *s, Req *r, gpe_status st) {
   r->status = st;
   r->state = RQ_DONE;
   r->t_done = now_s(s);
-  r->psi0.clear();
-  r->psi0.shrink_to_fit();
+  r->psi0_d.clear();
+  r->psi0_d.shrink_to_fit();
+  r->psi0_f.clear();
+  r->psi0_f.shrink_to_fit();
   ++s->completed;
   if (st == GPE_OK) s->site_steps += (double)sites_of(r->r.desc) * (double)r->steps_done;
   s->cv_done.notify_all();
 }
 
+Req *req_of(gpe_server *s, uint64_t id) {
+  std::lock_guard<std::mutex> lk(s->mu);
+  return s->reqs[id].get();
+}
+
 // GPU setup of an admitted request: class, slot context, state, slot entry.
-gpe_status admit(gpe_server *s, Req *r) {
+gpe_status admit(gpe_server *s, Req *r, long long round) {
   ShapeClass *c = find_class(s, key_of(r->r));
   gpe_status st = GPE_OK;
   if (!c && (st = create_class(s, r->r, &c)) != GPE_OK) return st;
   int i = -1;
   for (int j = 0; j < c->S; ++j)
-    if (c->owner[j] == 0 && (i < 0 || (c->ctx[j] && !c->ctx[i]))) i = j;  // prefer a warm slot
+    if (c->sstate[j] == SS_FREE && (i < 0 || (c->ctx[j] && !c->ctx[i]))) i = j;  // warm first
   if (i < 0) return GPE_EBUSY;
   if (!c->ctx[i]) {
     gpe_desc d = r->r.desc;
-    if ((st = gpe_create(&d, nullptr, &r->r.trap, s->stream, &c->ctx[i])) != GPE_OK) return st;
+    if ((st = create_context(&d, nullptr, &r->r.trap, s->aux, true, &c->ctx[i])) != GPE_OK)
+      return st;
     s->used += c->ctx[i]->dev_bytes;
   } else {
     c->ctx[i]->desc = r->r.desc;
     if ((st = set_potential(c->ctx[i], nullptr, &r->r.trap)) != GPE_OK) return st;
   }
   gpe_ctx *x = c->ctx[i];
-  if ((st = gpe_set_state(x, r->psi0.data())) != GPE_OK) return st;
-  gpe::Slot &sl = c->h[i];
-  sl = gpe::Slot{};
+  const void *src = x->prec == GPE_FP32 ? (const void *)r->psi0_f.data()
+                                        : (const void *)r->psi0_d.data();
+  if (hipMemcpyAsync(x->psi, src, x->sites * x->esize, hipMemcpyHostToDevice, s->aux) !=
+          hipSuccess ||
+      hipEventRecord(s->ev_up, s->aux) != hipSuccess ||
+      hipStreamWaitEvent(s->stream, s->ev_up, 0) != hipSuccess)
+    return GPE_EDEVICE;
+  gpe::Slot sl{};
   sl.psi = x->psi;
   sl.g = r->r.desc.g;
   for (int j = 0; j < 3; ++j) sl.hv[j] = x->hv[j];
@@ -335,26 +418,46 @@ gpe_status admit(gpe_server *s, Req *r) {
   sl.steps_done = 0;
   sl.scale = 1.0;
   sl.norm_target = r->r.desc.norm_target;
-  if (hipMemcpyAsync(c->d + i, &sl, sizeof(gpe::Slot), hipMemcpyHostToDevice, s->stream) !=
-      hipSuccess)
-    return GPE_EDEVICE;
+  if (gpe::launch_slot_write(c->d + i, sl, s->stream) != hipSuccess) return GPE_EDEVICE;
   c->owner[i] = r->id;
-  ++c->active;
+  c->sstate[i] = SS_RUN;
+  c->steps_total[i] = sl.steps_total;
+  c->admit_round[i] = round;
+  ++c->owned;
+  ++c->running;
   c->map_dirty = true;
-  r->cls = (int)(std::find(s->classes.begin(), s->classes.end(), c) - s->classes.begin());
-  r->slot = i;
   return GPE_OK;
 }
 
-// Request in slot i of class c is done (or cancelled): finish and free the slot.
-void complete(gpe_server *s, ShapeClass *c, int i, Req *r, bool cancelled) {
+// Clear slot i's table entry on the main stream (after the chunks already
+// enqueued; later chunks skip the slot).
+void clear_entry(gpe_server *s, ShapeClass *c, int i) {
+  gpe::Slot sl{};
+  sl.mode = gpe::SLOT_FREE;
+  (void)gpe::launch_slot_write(c->d + i, sl, s->stream);
+}
+
+void release(gpe_server *s, ShapeClass *c, int i) {
+  if (c->sstate[i] == SS_RUN) --c->running;
+  c->owner[i] = 0;
+  c->sstate[i] = SS_FREE;
+  --c->owned;
+  c->map_dirty = true;
+  std::lock_guard<std::mutex> lk(s->mu);
+  --s->running;
+}
+
+// Slot i finished its steps (seen in a read-back): final scaling, observables
+// and state download on the side stream, then the slot is free.  The chunk
+// now in flight skips the slot, so none of this races with it.
+void complete(gpe_server *s, ShapeClass *c, int i, Req *r) {
   gpe_ctx *x = c->ctx[i];
-  r->steps_done = c->h[i].steps_done;
+  r->steps_done = c->steps_total[i];
   gpe_status st = GPE_OK;
-  if (c->h[i].mode == gpe::SLOT_IMAG && r->steps_done > 0) {
+  if (r->r.mode == 1 && r->steps_done > 0) {
     double *scale_dev = reinterpret_cast<double *>(reinterpret_cast<char *>(c->d + i) +
                                                    offsetof(gpe::Slot, scale));
-    if (gpe::launch_scale(x->prec, x->psi, x->sites, scale_dev, s->stream) != hipSuccess)
+    if (gpe::launch_scale(x->prec, x->psi, x->sites, scale_dev, s->aux) != hipSuccess)
       st = GPE_EDEVICE;
   }
   gpe_obs o{};
@@ -364,124 +467,168 @@ void complete(gpe_server *s, ShapeClass *c, int i, Req *r, bool cancelled) {
     r->psi_out.resize(2 * (size_t)x->sites);
     if (gpe_get_state(x, r->psi_out.data()) != GPE_OK) st = GPE_EDEVICE;
   }
-  c->h[i].mode = gpe::SLOT_FREE;
-  (void)hipMemcpyAsync(c->d + i, &c->h[i], sizeof(gpe::Slot), hipMemcpyHostToDevice, s->stream);
-  c->owner[i] = 0;
-  --c->active;
-  c->map_dirty = true;
-  {
-    std::lock_guard<std::mutex> lk(s->mu);
-    --s->running;
+  clear_entry(s, c, i);
+  release(s, c, i);
+  finish(s, r, st);
+}
+
+// Start draining slot i: clear its entry now, release it once the chunk of
+// round `until` (the last one that may still touch it) is known done.
+void drain(gpe_server *s, ShapeClass *c, int i, long long until, gpe_status why) {
+  clear_entry(s, c, i);
+  if (c->sstate[i] == SS_RUN) --c->running;
+  c->sstate[i] = SS_DRAIN;
+  c->drain_until[i] = until;
+  c->drain_status[i] = why;
+}
+
+// The chunk of round q is done and its slot tables are on the host: update
+// the step-time estimates, finish completed requests, start or end drains.
+// `now` is the round whose chunk is in flight.
+void retire(gpe_server *s, long long q, long long now) {
+  const int par = (int)(q & 1);
+  for (ShapeClass *c : s->classes) {
+    if (!c->hp_valid[par]) continue;
+    c->hp_valid[par] = false;
+    float ms = 0;
+    if (!c->failed[par] && c->timed_steps[par] > 0 &&
+        hipEventElapsedTime(&ms, c->ev0[par], c->ev1[par]) == hipSuccess && ms > 0) {
+      c->step_ms = ms / c->timed_steps[par];
+      c->step_running = c->timed_running[par];
+    }
+    for (int i = 0; i < c->S; ++i) {
+      if (!c->owner[i]) continue;
+      Req *r = req_of(s, c->owner[i]);
+      if (c->sstate[i] == SS_DRAIN) {
+        if (q >= c->drain_until[i]) {
+          const gpe_status why = c->drain_status[i];
+          r->steps_done = std::min<int64_t>(r->steps_done, c->steps_total[i]);
+          release(s, c, i);
+          finish(s, r, why);
+        }
+        continue;
+      }
+      if (c->admit_round[i] > q) continue;  // the read-back predates this request
+      r->steps_done = c->hp[par][i].steps_done;
+      if (c->failed[par]) {
+        drain(s, c, i, now, GPE_EDEVICE);
+      } else if (r->cancel) {
+        drain(s, c, i, now, GPE_ECANCELED);
+      } else if (c->hp[par][i].steps_done >= c->steps_total[i]) {
+        complete(s, c, i, r);
+      }
+    }
   }
-  finish(s, r, cancelled ? GPE_ECANCELED : st);
+}
+
+// Admit queued requests in arrival order, one at a time, so that the bytes
+// charged for each are known before the next decision.
+void admit_queued(gpe_server *s, long long round) {
+  for (;;) {
+    std::unique_lock<std::mutex> lk(s->mu);
+    if (s->stop || s->queue.empty()) return;
+    Req *r = s->reqs[s->queue.front()].get();
+    if (r->cancel) {
+      s->queue.pop_front();
+      r->state = RQ_DONE;
+      r->status = GPE_ECANCELED;
+      r->t_done = now_s(s);
+      ++s->completed;
+      s->cv_done.notify_all();
+      continue;
+    }
+    if (s->max_active > 0 && s->running >= s->max_active) return;
+    ShapeClass *c = find_class(s, key_of(r->r));
+    bool warm = false, free_slot = c == nullptr;
+    if (c)
+      for (int j = 0; j < c->S; ++j)
+        if (c->sstate[j] == SS_FREE) {
+          free_slot = true;
+          warm = warm || c->ctx[j] != nullptr;
+        }
+    if (!free_slot) return;
+    const uint64_t need = (warm ? 0 : r->need) + (c ? 0 : r->need_class);
+    if (s->used + need > s->budget) {
+      reclaim(s, need, key_of(r->r));
+      if (s->used + need > s->budget) return;
+    }
+    s->queue.pop_front();
+    r->state = RQ_RUNNING;
+    r->t_start = now_s(s);
+    ++s->running;
+    lk.unlock();
+    const gpe_status st = admit(s, r, round);
+    if (st != GPE_OK) {
+      {
+        std::lock_guard<std::mutex> lk2(s->mu);
+        --s->running;
+      }
+      finish(s, r, st == GPE_EBUSY ? GPE_EDEVICE : st);
+    }
+  }
 }
 
 void scheduler(gpe_server *s) {
   (void)hipSetDevice(s->device);
+  long long round = 0;
+  bool pending = false;  // the previous round enqueued a chunk not yet retired
   for (;;) {
-    // Admission, one request at a time and in arrival order, so that the bytes
-    // charged for each admitted request are known before the next decision.
-    bool admitted_any = false;
     const auto tb = std::chrono::steady_clock::now();
-    for (;;) {
-      std::unique_lock<std::mutex> lk(s->mu);
-      if (s->stop || s->queue.empty()) break;
-      Req *r = s->reqs[s->queue.front()].get();
-      if (r->cancel) {
-        s->queue.pop_front();
-        r->state = RQ_DONE;
-        r->status = GPE_ECANCELED;
-        r->t_done = now_s(s);
-        ++s->completed;
-        s->cv_done.notify_all();
-        continue;
-      }
-      if (s->max_active > 0 && s->running >= s->max_active) break;
-      ShapeClass *c = find_class(s, key_of(r->r));
-      if (c && c->active >= c->S) break;
-      bool warm = false;
-      if (c)
-        for (int j = 0; j < c->S; ++j) warm = warm || (c->owner[j] == 0 && c->ctx[j]);
-      const uint64_t need = (warm ? 0 : r->need) + (c ? 0 : r->need_class);
-      if (s->used + need > s->budget) {
-        reclaim(s, need, key_of(r->r));
-        if (s->used + need > s->budget) break;
-      }
-      s->queue.pop_front();
-      r->state = RQ_RUNNING;
-      r->t_start = now_s(s);
-      ++s->running;
-      lk.unlock();
-      const gpe_status st = admit(s, r);
-      if (st != GPE_OK) {
-        {
-          std::lock_guard<std::mutex> lk2(s->mu);
-          --s->running;
-        }
-        finish(s, r, st == GPE_EBUSY ? GPE_EDEVICE : st);
-      }
-      admitted_any = true;
-    }
-    {
-      std::unique_lock<std::mutex> lk(s->mu);
-      if (s->stop) break;
-      if (!admitted_any && s->running == 0) {
-        s->cv_work.wait(lk, [&] { return s->stop || !s->queue.empty(); });
-        continue;
-      }
-    }
+    admit_queued(s, round);
+    const int par = (int)(round & 1);
     bool any = false;
     for (ShapeClass *c : s->classes) {
-      if (!c->active) continue;
+      c->hp_valid[par] = false;
+      if (!c->owned) continue;
       any = true;
-      c->failed = run_chunk(s, c) != GPE_OK;
+      const int steps = steps_for(s, c);
+      (void)hipEventRecord(c->ev0[par], s->stream);
+      c->failed[par] = run_chunk(s, c, steps) != GPE_OK;
+      (void)hipEventRecord(c->ev1[par], s->stream);
+      c->timed_steps[par] = steps;
+      c->timed_running[par] = c->running;
+      (void)hipMemcpyAsync(c->hp[par], c->d, c->S * sizeof(gpe::Slot), hipMemcpyDeviceToHost,
+                           s->stream);
+      c->hp_valid[par] = true;
     }
-    for (ShapeClass *c : s->classes)
-      if (c->active)
-        (void)hipMemcpyAsync(c->h.data(), c->d, c->S * sizeof(gpe::Slot), hipMemcpyDeviceToHost,
-                             s->stream);
-    (void)hipStreamSynchronize(s->stream);
-    for (ShapeClass *c : s->classes) {
-      for (int i = 0; i < c->S; ++i) {
-        if (!c->owner[i]) continue;
-        Req *r;
-        {
-          std::lock_guard<std::mutex> lk(s->mu);
-          r = s->reqs[c->owner[i]].get();
-        }
-        if (c->failed) {
-          c->owner[i] = 0;
-          --c->active;
-          c->map_dirty = true;
-          c->h[i].mode = gpe::SLOT_FREE;
-          (void)hipMemcpyAsync(c->d + i, &c->h[i], sizeof(gpe::Slot), hipMemcpyHostToDevice,
-                               s->stream);
-          {
-            std::lock_guard<std::mutex> lk(s->mu);
-            --s->running;
-          }
-          finish(s, r, GPE_EDEVICE);
-        } else if (r->cancel || c->h[i].steps_done >= c->h[i].steps_total) {
-          complete(s, c, i, r, r->cancel);
-        }
-      }
+    if (any) (void)hipEventRecord(s->done[par], s->stream);
+    if (pending) {
+      (void)hipEventSynchronize(s->done[par ^ 1]);
+      retire(s, round - 1, round);
     }
-    if (any || admitted_any) {
-      std::lock_guard<std::mutex> lk(s->mu);
+    pending = any;
+    ++round;
+    std::unique_lock<std::mutex> lk(s->mu);
+    if (any || s->running > 0)
       s->busy += std::chrono::duration<double>(std::chrono::steady_clock::now() - tb).count();
-    }
+    if (s->stop) break;
+    if (!pending && s->running == 0)
+      s->cv_work.wait(lk, [&] { return s->stop || !s->queue.empty(); });
+    if (s->stop) break;
   }
-  // shutting down: cancel whatever is still held
+  // Shutting down: let the GPU finish, then cancel whatever is still held.
+  (void)hipStreamSynchronize(s->stream);
+  (void)hipStreamSynchronize(s->aux);
   for (ShapeClass *c : s->classes)
     for (int i = 0; i < c->S; ++i)
       if (c->owner[i]) {
-        Req *r;
-        {
-          std::lock_guard<std::mutex> lk(s->mu);
-          r = s->reqs[c->owner[i]].get();
-        }
-        complete(s, c, i, r, true);
+        Req *r = req_of(s, c->owner[i]);
+        release(s, c, i);
+        finish(s, r, GPE_ECANCELED);
       }
+}
+
+// Free everything the server holds (the scheduler thread has ended).
+void release_server(gpe_server *s) {
+  if (s->stream) (void)hipStreamSynchronize(s->stream);
+  if (s->aux) (void)hipStreamSynchronize(s->aux);
+  for (ShapeClass *c : s->classes) destroy_class(s, c);
+  s->classes.clear();
+  for (hipEvent_t e : {s->done[0], s->done[1], s->ev_up})
+    if (e) (void)hipEventDestroy(e);
+  if (s->aux) (void)hipStreamDestroy(s->aux);
+  if (s->stream) (void)hipStreamDestroy(s->stream);
+  delete s;
 }
 
 }  // namespace
@@ -492,10 +639,15 @@ gpe_status gpe_server_create(uint64_t hbm_budget_bytes, int32_t max_slots, int32
                              int32_t chunk_steps, gpe_server **out) {
   if (!out || max_slots < 1 || max_active < 0 || chunk_steps < 1) return GPE_EINVAL;
   *out = nullptr;
+  if (max_slots > gpe::kMaxSlots) return GPE_EUNSUPPORTED;
   gpe_server *s = new gpe_server();
   if (hipGetDevice(&s->device) != hipSuccess ||
-      hipStreamCreateWithFlags(&s->stream, hipStreamNonBlocking) != hipSuccess) {
-    delete s;
+      hipStreamCreateWithFlags(&s->stream, hipStreamNonBlocking) != hipSuccess ||
+      hipStreamCreateWithFlags(&s->aux, hipStreamNonBlocking) != hipSuccess ||
+      hipEventCreateWithFlags(&s->done[0], hipEventDisableTiming) != hipSuccess ||
+      hipEventCreateWithFlags(&s->done[1], hipEventDisableTiming) != hipSuccess ||
+      hipEventCreateWithFlags(&s->ev_up, hipEventDisableTiming) != hipSuccess) {
+    release_server(s);
     return GPE_EDEVICE;
   }
   size_t free_b = 0, total_b = 0;
@@ -504,7 +656,13 @@ gpe_status gpe_server_create(uint64_t hbm_budget_bytes, int32_t max_slots, int32
   s->max_slots = max_slots;
   s->max_active = max_active;
   s->chunk = chunk_steps;
+  // Experiment overrides: graph replay for small classes, GPU time per
+  // running request per round.
   if (const char *g = std::getenv("GPE_SERVER_GRAPH")) s->use_graph = std::atoi(g) != 0;
+  if (const char *q = std::getenv("GPE_SERVER_QUANTUM_MS")) {
+    const double v = std::atof(q);
+    if (v > 0) s->quantum_ms = v;
+  }
   s->t0 = std::chrono::steady_clock::now();
   s->th = std::thread(scheduler, s);
   *out = s;
@@ -526,7 +684,13 @@ gpe_status gpe_server_submit(gpe_server *s, const gpe_request *req, uint64_t *id
   auto r = std::make_unique<Req>();
   r->r = *req;
   r->r.psi0 = nullptr;
-  r->psi0.assign(req->psi0, req->psi0 + 2 * sites_of(d));
+  const size_t nreal = 2 * (size_t)sites_of(d);
+  if (d.precision == GPE_FP32) {
+    r->psi0_f.resize(nreal);
+    for (size_t i = 0; i < nreal; ++i) r->psi0_f[i] = (float)req->psi0[i];
+  } else {
+    r->psi0_d.assign(req->psi0, req->psi0 + nreal);
+  }
   r->need = context_bytes(d);
   r->need_class = class_bytes(d, s->max_slots);
   if (r->need + r->need_class > s->budget) return GPE_ENOMEM;
@@ -612,10 +776,7 @@ void gpe_server_destroy(gpe_server *s) {
   }
   s->cv_work.notify_all();
   if (s->th.joinable()) s->th.join();
-  (void)hipStreamSynchronize(s->stream);
-  for (ShapeClass *c : s->classes) destroy_class(c);
-  (void)hipStreamDestroy(s->stream);
-  delete s;
+  release_server(s);
 }
 
 }  // extern "C"

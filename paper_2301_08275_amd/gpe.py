@@ -482,7 +482,8 @@ class Server:
 
     budget: HBM bytes for admitted requests (0: the device's free memory);
     max_slots: slots per shape class; max_active: requests running at once
-    (0: no cap, 1: one at a time); chunk_steps: steps between completion checks.
+    (0: no cap, 1: one at a time); chunk_steps: steps per replayed graph of a
+    small-grid class (each round runs whole replays).
     """
 
     def __init__(self, budget=0, max_slots=16, max_active=0, chunk_steps=16):
