@@ -223,6 +223,8 @@ def main():
     ap.add_argument("--no-cpu", action="store_true")
     ap.add_argument("--no-fp32", action="store_true")
     ap.add_argument("--copy-calibration", action="store_true")
+    ap.add_argument("--no-tune", action="store_true",
+                    help="skip the launch-shape tuner (use the default shapes)")
     ap.add_argument("--serving", type=int, default=64,
                     help="requests of the serving mix to run (0: skip)")
     ap.add_argument("--serving-slots", type=int, default=16)
@@ -256,8 +258,12 @@ def main():
     sites = n ** 3
     spectra = not args.no_spectra
 
-    results = {}
+    results, tuning = {}, {}
     for prec in (["fp64"] if args.no_fp32 else ["fp64", "fp32"]):
+        if not args.no_tune:
+            # untimed: pick the launch shapes of this shape class on this device
+            log("tuning %s" % prec)
+            tuning[prec] = gpe.gpe_autotune(gpe.make_desc((n, n, n), lo, hi, g, prec), steps=5)
         log("timing %s" % prec)
         ctx = gpe.Context((n, n, n), lo, hi, g, precision=prec,
                           norm_target=(2 * 3.141592653589793) ** 3, stream=stream)
@@ -302,6 +308,7 @@ def main():
                           "hbm_GBps_at_96B_per_site_step":
                               96.0 * sites / (step_ms * 1e-3) / 1e9},
         "kernels": kernel_table(r64["kinds"]),
+        "tuning": tuning.get("fp64", "defaults"),
     }
     if "fp32" in results:
         r32 = results["fp32"]
@@ -313,7 +320,8 @@ def main():
                        "stepping_only_ms_per_step": s32 / args.steps,
                        "dominant_kernel": n32, "achieved_GBps": ach32,
                        "frac": ach32 / HBM_PEAK_GBS,
-                       "kernels": kernel_table(r32["kinds"])}
+                       "kernels": kernel_table(r32["kinds"]),
+                       "tuning": tuning.get("fp32", "defaults")}
     if args.serving > 0:
         log("serving mix: %d requests" % args.serving)
         out["serving"] = serving_bench(args.serving, args.serving_slots, args.serving_chunk)

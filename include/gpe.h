@@ -193,6 +193,40 @@ const char *gpe_last_error(const gpe_ctx *ctx);
 void gpe_destroy(gpe_ctx *ctx);
 
 /* ------------------------------------------------------------------------
+ * Launch-shape tuning per shape class (dim, n, precision).  None of these
+ * choices changes the arithmetic of a line, so results do not depend on them
+ * except through the order of the axis passes (rounding only).  Contexts and
+ * server classes created after an entry is set use it; earlier ones keep
+ * their shapes.  The table is process-wide and thread-safe.
+ * ---------------------------------------------------------------------- */
+typedef struct {
+  int32_t width[3];       /* strided axes (all but the last): columns per workgroup, 8 or 16 */
+  int32_t xcd_remap[3];   /* strided axes: 1 = each XCD takes a contiguous run of tiles */
+  int32_t pass_order[3];  /* the axes (0 = slowest) in the order a step visits them */
+  double ms_per_step;     /* measured real-time step (gpe_autotune), else 0 */
+} gpe_tuning;             /* entries beyond dim (and width/xcd_remap of the last axis) are 0 */
+
+/* Time the real-time step of this shape class on the current device for
+ * every width and tile order of each strided axis, then for every pass order
+ * (coordinate descent from the current entry or the defaults; `steps` timed
+ * steps per candidate, the minimum of two runs), record the fastest in the
+ * table and copy it to *out (nullable).  Allocates a scratch context of the
+ * class for the duration of the call.  g, box and norm_target of desc are not
+ * used. */
+gpe_status gpe_autotune(const gpe_desc *desc, int32_t steps, gpe_tuning *out);
+
+/* Set (validated; GPE_EINVAL on a bad entry) or read the entry of a class.
+ * gpe_tuning_get returns the defaults with *found = 0 when there is none. */
+gpe_status gpe_tuning_set(const gpe_desc *desc, const gpe_tuning *t);
+gpe_status gpe_tuning_get(const gpe_desc *desc, gpe_tuning *out, int32_t *found);
+void gpe_tuning_clear(void);
+
+/* Save the table as JSON / merge a saved table into it (all entries are
+ * validated before any is applied; GPE_EINVAL on a malformed file). */
+gpe_status gpe_tuning_save(const char *path);
+gpe_status gpe_tuning_load(const char *path);
+
+/* ------------------------------------------------------------------------
  * Serving: a request scheduler over one GPU (no counterpart in the paper,
  * which solves one problem per run).  Independent solves of the problems
  * above are submitted from any host thread; a scheduler thread admits them in

@@ -506,7 +506,8 @@ uint64_t context_bytes(const gpe_desc &d, bool with_state) {
     sites *= d.n[j];
   }
   const uint64_t es = d.precision == GPE_FP32 ? 8 : 16;
-  const int wdef[3] = {16, d.precision == GPE_FP32 ? 16 : 8, 8};
+  int wdef[3], xcd[3], order[3];
+  effective_tuning(d, wdef, xcd, order);
   long long maxb = 1;
   uint64_t tables = 0;
   for (int ax = off; ax < 3; ++ax) {
@@ -547,7 +548,7 @@ gpe_status create_context(const gpe_desc *desc, const double *V_host, const gpe_
   c->dim = desc->dim;
   c->prec = desc->precision;
   c->esize = c->prec == GPE_FP32 ? 8 : 16;
-  if (c->prec == GPE_FP32) c->wreq[1] = 16;
+  effective_tuning(*desc, c->wreq, c->xcd_remap, c->pass_order);
   const int off = 3 - c->dim;
   c->sites = 1;
   c->dV = 1;

@@ -86,6 +86,10 @@ gpe_status compute_obs(gpe_ctx *c, const double *scale, gpe_obs *o);
 int n_axes(const gpe_ctx *c);
 int order_axis(const gpe_ctx *c, int i);
 int view_axis(const gpe_ctx *c, int user_axis);
+gpe_status validate_desc(const gpe_desc *d, std::string &msg);
+// Launch shapes a new context of this class uses (view axes): the tuning
+// table's entry, else the defaults.
+void effective_tuning(const gpe_desc &d, int wreq[3], int xcd[3], int order[3]);
 // Device bytes of a context (with_state: including the state array).
 uint64_t context_bytes(const gpe_desc &d, bool with_state = true);
 // gpe_create, optionally without the state array (a holder of the tables of

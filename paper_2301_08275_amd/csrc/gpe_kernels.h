@@ -147,6 +147,9 @@ struct SlotMap {
 hipError_t launch_slot_write(Slot *dst, const Slot &value, hipStream_t s);
 hipError_t launch_map_write(int *dst, const SlotMap &m, hipStream_t s);
 
+// Fill a state with index-hashed values in [-1, 1) (for timing runs).
+hipError_t launch_fill_noise(int precision, void *psi, long long sites, hipStream_t s);
+
 // Precision conversion copies (device to device).
 hipError_t launch_convert(int src_prec, const void *src, int dst_prec, void *dst,
                           long long sites, hipStream_t s);

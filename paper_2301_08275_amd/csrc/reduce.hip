@@ -87,6 +87,20 @@ __global__ void convert_kernel(const S *__restrict__ src, D *__restrict__ dst, l
     dst[i] = (D)src[i];
 }
 
+// Pseudo-random state for timing runs only (a hash of the index, values in
+// [-1, 1)): data-dependent effects such as power draw then match a real run.
+template <typename T>
+__global__ void fill_noise_kernel(T *__restrict__ psi, long long n) {
+  for (long long i = (long long)blockIdx.x * blockDim.x + threadIdx.x; i < n;
+       i += (long long)gridDim.x * blockDim.x) {
+    unsigned long long z = (unsigned long long)i * 0x9E3779B97F4A7C15ull + 0x632BE59BD9B4E019ull;
+    z = (z ^ (z >> 30)) * 0xBF58476D1CE4E5B9ull;
+    z = (z ^ (z >> 27)) * 0x94D049BB133111EBull;
+    z ^= z >> 31;
+    psi[i] = (T)((double)(z >> 11) * 0x1.0p-52 - 1.0);
+  }
+}
+
 unsigned grid_for(long long n, int threads) {
   long long b = (n + threads - 1) / threads;
   if (b > 65536) b = 65536;
@@ -131,6 +145,17 @@ hipError_t launch_scale(int precision, void *psi, long long sites, double *c,
     hipLaunchKernelGGL(scale_kernel<double>, dim3(grid_for(n, 256)), dim3(256), 0, s,
                        static_cast<double *>(psi), n, c);
   hipLaunchKernelGGL(set_one_kernel, dim3(1), dim3(1), 0, s, c);
+  return hipGetLastError();
+}
+
+hipError_t launch_fill_noise(int precision, void *psi, long long sites, hipStream_t s) {
+  const long long n = 2 * sites;
+  if (precision == 1)
+    hipLaunchKernelGGL(fill_noise_kernel<float>, dim3(grid_for(n, 256)), dim3(256), 0, s,
+                       static_cast<float *>(psi), n);
+  else
+    hipLaunchKernelGGL(fill_noise_kernel<double>, dim3(grid_for(n, 256)), dim3(256), 0, s,
+                       static_cast<double *>(psi), n);
   return hipGetLastError();
 }
 

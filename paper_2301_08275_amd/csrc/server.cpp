@@ -183,10 +183,13 @@ uint64_t class_bytes(const gpe_desc &d, int max_slots) {
   for (int j = 0; j < d.dim; ++j) n3[j + off] = d.n[j];
   uint64_t ktabs = 0;
   for (int ax = off; ax < 3; ++ax) ktabs += 2 * (uint64_t)n3[ax] * 16;
-  // the last pass of the default order is view axis 0 (3D) or 1 (2D)
-  const int last = off;
-  const int wlast = last == 0 ? 16 : (d.precision == GPE_FP32 ? 16 : 8);
-  const long long bpg = gpe::pass_shape(d.precision, n3, last, wlast).blocks;
+  // blocks of the last pass of a step, with the launch shapes the class will use
+  int wreq[3], xcd[3], order[3];
+  effective_tuning(d, wreq, xcd, order);
+  int last = -1;
+  for (int j = 0; j < 3; ++j)
+    if (order[j] >= off) last = order[j];
+  const long long bpg = gpe::pass_shape(d.precision, n3, last, wreq[last]).blocks;
   return context_bytes(d, false) + ktabs +
          (uint64_t)max_slots * (sizeof(gpe::Slot) + sizeof(int)) +
          (uint64_t)max_slots * bpg * gpe::kRedSlots * sizeof(double);

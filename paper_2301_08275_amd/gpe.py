@@ -90,6 +90,11 @@ class gpe_server_stats(ctypes.Structure):
                 ("bytes_in_use", ctypes.c_uint64)]
 
 
+class gpe_tuning(ctypes.Structure):
+    _fields_ = [("width", ctypes.c_int32 * 3), ("xcd_remap", ctypes.c_int32 * 3),
+                ("pass_order", ctypes.c_int32 * 3), ("ms_per_step", ctypes.c_double)]
+
+
 _P = ctypes.c_void_p
 _D = ctypes.c_double
 _I32 = ctypes.c_int32
@@ -125,6 +130,13 @@ SIGNATURES = {
     "gpe_server_destroy": (None, [_P]),
     "gpe_request_bytes": (_I32, [ctypes.POINTER(gpe_desc), _I32, ctypes.POINTER(ctypes.c_uint64),
                                  ctypes.POINTER(ctypes.c_uint64)]),
+    "gpe_autotune": (_I32, [ctypes.POINTER(gpe_desc), _I32, ctypes.POINTER(gpe_tuning)]),
+    "gpe_tuning_set": (_I32, [ctypes.POINTER(gpe_desc), ctypes.POINTER(gpe_tuning)]),
+    "gpe_tuning_get": (_I32, [ctypes.POINTER(gpe_desc), ctypes.POINTER(gpe_tuning),
+                              ctypes.POINTER(_I32)]),
+    "gpe_tuning_clear": (None, []),
+    "gpe_tuning_save": (_I32, [ctypes.c_char_p]),
+    "gpe_tuning_load": (_I32, [ctypes.c_char_p]),
 }
 
 _lib = None
@@ -305,6 +317,56 @@ def gpe_request_bytes(desc, max_slots):
     if st != GPE_OK:
         raise GpeError(st, "gpe_request_bytes")
     return cb.value, sb.value
+
+
+def _tuning_dict(t, dim):
+    return {"width": list(t.width[:dim]), "xcd_remap": list(t.xcd_remap[:dim]),
+            "pass_order": list(t.pass_order[:dim]), "ms_per_step": t.ms_per_step}
+
+
+def gpe_autotune(desc, steps=10):
+    """Time the launch shapes of this shape class; record and return the best."""
+    t = gpe_tuning()
+    st = load_library().gpe_autotune(ctypes.byref(desc), int(steps), ctypes.byref(t))
+    if st != GPE_OK:
+        raise GpeError(st, "gpe_autotune")
+    return _tuning_dict(t, desc.dim)
+
+
+def gpe_tuning_set(desc, width, xcd_remap, pass_order):
+    t = gpe_tuning()
+    for j in range(desc.dim):
+        t.width[j] = int(width[j])
+        t.xcd_remap[j] = int(xcd_remap[j])
+        t.pass_order[j] = int(pass_order[j])
+    st = load_library().gpe_tuning_set(ctypes.byref(desc), ctypes.byref(t))
+    if st != GPE_OK:
+        raise GpeError(st, "gpe_tuning_set")
+
+
+def gpe_tuning_get(desc):
+    """(entry as a dict, found) -- the defaults when there is no entry."""
+    t, found = gpe_tuning(), _I32(0)
+    st = load_library().gpe_tuning_get(ctypes.byref(desc), ctypes.byref(t), ctypes.byref(found))
+    if st != GPE_OK:
+        raise GpeError(st, "gpe_tuning_get")
+    return _tuning_dict(t, desc.dim), bool(found.value)
+
+
+def gpe_tuning_clear():
+    load_library().gpe_tuning_clear()
+
+
+def gpe_tuning_save(path):
+    st = load_library().gpe_tuning_save(os.fsencode(path))
+    if st != GPE_OK:
+        raise GpeError(st, "gpe_tuning_save")
+
+
+def gpe_tuning_load(path):
+    st = load_library().gpe_tuning_load(os.fsencode(path))
+    if st != GPE_OK:
+        raise GpeError(st, "gpe_tuning_load")
 
 
 # ------------------------------------------------------------- convenience ---

@@ -1,0 +1,101 @@
+"""GPU checks of the launch-shape tuner: every candidate shape gives the same
+arithmetic per line (bitwise-equal results for widths and tile orders; pass
+orders agree with the oracle), and tuned contexts keep oracle parity."""
+import itertools
+import sys
+
+import numpy as np
+import pytest
+
+import oracle
+from paper_2301_08275_amd import gpe
+from paper_2301_08275_amd import inputs as I
+
+pytestmark = pytest.mark.gpu
+
+
+def say(*a):
+    print(*a, flush=True)
+    sys.stdout.flush()
+
+
+def rel(a, b):
+    return float(np.linalg.norm(np.ravel(a - b)) / np.linalg.norm(np.ravel(b)))
+
+
+@pytest.fixture(autouse=True)
+def clean_table():
+    gpe.gpe_tuning_clear()
+    yield
+    gpe.gpe_tuning_clear()
+
+
+def run(shape, lo, hi, g, trap, psi0, steps, prec="fp64"):
+    with gpe.Context(shape, lo, hi, g, precision=prec, harmonic=trap) as ctx:
+        ctx.set_state(psi0)
+        ctx.evolve(1e-3, steps)
+        return ctx.get_state()
+
+
+@pytest.mark.parametrize("prec", ["fp64", "fp32"])
+def test_widths_and_tile_orders_are_bitwise_neutral(prec):
+    shape, lo, hi = (64, 32, 128), (-6.0,) * 3, (6.0,) * 3
+    trap = [1.0, 2.0, 3.0]
+    psi0 = I.noisy_gaussian(shape, lo, hi, seed=7)
+    d = gpe.make_desc(shape, lo, hi, 20.0, prec)
+    ref = run(shape, lo, hi, 20.0, trap, psi0, 12, prec)
+    for w0, w1, x0, x1 in itertools.product([8, 16], [8, 16], [0, 1], [0, 1]):
+        gpe.gpe_tuning_set(d, [w0, w1, 0], [x0, x1, 0], [2, 1, 0])
+        say(prec, "width", w0, w1, "xcd", x0, x1)
+        got = run(shape, lo, hi, 20.0, trap, psi0, 12, prec)
+        assert np.array_equal(got, ref), (w0, w1, x0, x1)
+
+
+def test_pass_orders_match_the_oracle():
+    shape, lo, hi = (32, 64, 16), (-5.0,) * 3, (5.0,) * 3
+    trap = [1.0, 1.5, 2.0]
+    psi0 = I.noisy_gaussian(shape, lo, hi, seed=8)
+    V = I.harmonic(shape, lo, hi, trap)
+    ref = oracle.tssp_real(psi0, lo, hi, V, 30.0, 1e-3, 20)
+    d = gpe.make_desc(shape, lo, hi, 30.0)
+    for order in itertools.permutations(range(3)):
+        gpe.gpe_tuning_set(d, [8, 8, 0], [1, 1, 0], list(order))
+        say("order", order)
+        got = run(shape, lo, hi, 30.0, trap, psi0, 20)
+        assert rel(got, ref) < 1e-12, order
+
+
+@pytest.mark.parametrize("shape", [(128, 128), (64, 64, 64)])
+def test_autotune_records_an_entry_and_keeps_parity(shape):
+    dim = len(shape)
+    lo, hi = (-8.0,) * dim, (8.0,) * dim
+    trap = [1.0] * dim
+    d = gpe.make_desc(shape, lo, hi, 10.0)
+    say("autotune", shape)
+    t = gpe.gpe_autotune(d, steps=5)
+    assert t["ms_per_step"] > 0
+    assert sorted(t["pass_order"]) == list(range(dim))
+    got_t, found = gpe.gpe_tuning_get(d)
+    assert found and got_t == t
+    psi0 = I.noisy_gaussian(shape, lo, hi, seed=9)
+    V = I.harmonic(shape, lo, hi, trap)
+    ref = oracle.tssp_real(psi0, lo, hi, V, 10.0, 1e-3, 30)
+    got = run(shape, lo, hi, 10.0, trap, psi0, 30)
+    assert rel(got, ref) < 1e-12
+
+
+def test_server_uses_the_tuned_shapes():
+    """A server class created after tuning (pass order changed) still gives
+    the single-context result bitwise."""
+    shape, lo, hi = (64, 64, 32), (-6.0,) * 3, (6.0,) * 3
+    d = gpe.make_desc(shape, lo, hi, 5.0)
+    gpe.gpe_tuning_set(d, [16, 16, 0], [0, 0, 0], [0, 2, 1])
+    psi0 = I.noisy_gaussian(shape, lo, hi, seed=10)
+    ref = run(shape, lo, hi, 5.0, [1.0, 1.0, 2.0], psi0, 25)
+    with gpe.Server(max_slots=4, chunk_steps=8) as srv:
+        rid = srv.submit(shape, lo, hi, 5.0, psi0, mode="real", dt=1e-3, nsteps=25,
+                         trap=[1.0, 1.0, 2.0], keep_state=True)
+        srv.wait_idle()
+        out = srv.poll(rid)
+    assert out["status"] == gpe.GPE_OK
+    assert rel(out["psi"], ref) < 1e-12
