@@ -381,13 +381,19 @@ __device__ __forceinline__ void inverse_fft(cx<T> *v, int t, int c, T *lre, T *l
   stage<PL, 0, +1>(v, t, tw);
 }
 
+// Analytic harmonic potential sum_j hv[j] x_j^2 at site (j0, j1, j2).
+__device__ __forceinline__ double harmonic_potential(const double (&lo)[3], const double (&h)[3],
+                                                     const double (&hv)[3], int j0, int j1,
+                                                     int j2) {
+  const double x0 = lo[0] + j0 * h[0], x1 = lo[1] + j1 * h[1], x2 = lo[2] + j2 * h[2];
+  return hv[0] * x0 * x0 + hv[1] * x1 * x1 + hv[2] * x2 * x2;
+}
+
 __device__ __forceinline__ double site_potential(const PassArgs &a, int vkind, const double (&hv)[3],
                                                  int j0, int j1, int j2) {
   if (vkind == V_NONE) return 0.0;
   if (vkind == V_ARRAY) return a.V[((long long)j0 * a.n[1] + j1) * a.n[2] + j2];
-  const double x0 = a.lo[0] + j0 * a.h[0], x1 = a.lo[1] + j1 * a.h[1],
-               x2 = a.lo[2] + j2 * a.h[2];
-  return hv[0] * x0 * x0 + hv[1] * x1 * x1 + hv[2] * x2 * x2;
+  return harmonic_potential(a.lo, a.h, hv, j0, j1, j2);
 }
 
 // sin and cos of x in FP64: Cody-Waite reduction x = n pi/2 + r with pi/2 split

@@ -134,6 +134,25 @@ hipError_t launch_sum_columns(const double *partial, long long count, int len, d
 hipError_t launch_slot_update(Slot *slots, int nslots, const double *partial,
                               long long blocks_per_grid, double dV, hipStream_t s);
 
+// On-chip batched class: one workgroup holds a whole square 2D grid in LDS
+// and runs several steps of its slot without touching HBM in between.
+struct OnchipArgs {
+  Slot *slots;
+  const int *slot_map;  // grid row -> slot index
+  int steps;            // steps per launch (each slot runs min(steps, remaining))
+  int rows_first;       // 1: a step starts with the lines along the last axis
+  int n;                // grid is n x n
+  double dt, dV;
+  double lo[3], h[3];   // 3D view coordinates (view axis 0 unused)
+  const void *tw_row, *tw_col;  // twiddles along the last / first axis
+  const void *kr_row, *kr_col;  // real-time kinetic factors per axis
+  const void *ki_row, *ki_col;  // imaginary-time kinetic factors per axis
+};
+// Square 2D grids whose state fits one workgroup's LDS: n <= 64 in FP64,
+// n <= 128 in FP32.
+bool onchip_supported(int precision, int n);
+hipError_t launch_onchip(int precision, const OnchipArgs &a, int rows, hipStream_t s);
+
 // Most slots a shape class holds (the active-slot map travels as a kernel
 // argument).
 constexpr int kMaxSlots = 256;

@@ -11,7 +11,11 @@
 //     for their owned slots only.  Chunks are sized from the measured GPU time
 //     per step so that every running request receives about the same GPU time
 //     per round, whatever its grid: small solves finish in few rounds instead
-//     of advancing at the pace of the largest grid;
+//     of advancing at the pace of the largest grid.  Small square 2D grids
+//     form on-chip classes instead: one workgroup per request holds the whole
+//     grid in LDS and runs the chunk's steps in one launch, on a side stream,
+//     so they occupy a few CUs beside the large classes and are paced to
+//     last about as long as the main stream's round;
 //  3. copies the slot tables back and only then waits for the previous
 //     round's chunk, and finishes the requests that chunk completed (final
 //     imaginary-time scaling, observables, optional state download, all on the
@@ -105,6 +109,8 @@ struct ShapeClass {
   void *kreal[3] = {nullptr, nullptr, nullptr}, *kimag[3] = {nullptr, nullptr, nullptr};
   hipGraphExec_t graph = nullptr;
   bool use_graph = false;               // small grids: replay a chunk graph over all slots
+  bool onchip = false;                  // square 2D grid held in LDS, steps looped in-kernel
+  hipStream_t strm = nullptr;           // stream of the class's launches and table writes
   int *d_map = nullptr;                 // large grids: rows for the owned slots only
   int rows = 0;
   bool map_dirty = true;
@@ -122,13 +128,18 @@ struct ShapeClass {
 struct gpe_server {
   hipStream_t stream = nullptr;  // batched steps and slot-table writes
   hipStream_t aux = nullptr;     // uploads, final scaling, observables, downloads
-  hipEvent_t done[2] = {nullptr, nullptr};  // end of a round's chunks and read-backs
+  hipStream_t side = nullptr;    // on-chip classes (beside the main stream)
+  hipEvent_t done[2] = {nullptr, nullptr};       // end of a round's main-stream work
+  hipEvent_t done_side[2] = {nullptr, nullptr};  // end of a round's side-stream work
+  bool used_main[2] = {false, false}, used_side[2] = {false, false};
+  double main_round_ms = 0;      // GPU time of the main stream's last retired round
   hipEvent_t ev_up = nullptr;
   int device = 0;
   uint64_t budget = 0;
   std::atomic<uint64_t> used{0};
   int max_slots = 1, max_active = 0, chunk = 16;
   bool use_graph = true;
+  bool use_onchip = true;
   double quantum_ms = 1.0;  // GPU time per running request per round
   std::mutex mu;
   std::condition_variable cv_work, cv_done;
@@ -158,6 +169,7 @@ long long sites_of(const gpe_desc &d) {
 
 void destroy_class(gpe_server *s, ShapeClass *c) {
   (void)hipStreamSynchronize(s->stream);
+  (void)hipStreamSynchronize(s->side);
   (void)hipStreamSynchronize(s->aux);
   if (c->graph) (void)hipGraphExecDestroy(c->graph);
   for (gpe_ctx *x : c->ctx)
@@ -219,9 +231,9 @@ gpe_status enqueue_step(gpe_server *s, ShapeClass *c) {
     a.mtab = c->kreal[ax];
     a.mtab_imag = c->kimag[ax];
     a.partial = c->partial;
-    if (gpe::launch_axis_pass(p->prec, a, s->stream) != hipSuccess) return GPE_EDEVICE;
+    if (gpe::launch_axis_pass(p->prec, a, c->strm) != hipSuccess) return GPE_EDEVICE;
   }
-  return gpe::launch_slot_update(c->d, c->S, c->partial, c->bpg_last, p->dV, s->stream) ==
+  return gpe::launch_slot_update(c->d, c->S, c->partial, c->bpg_last, p->dV, c->strm) ==
                  hipSuccess
              ? GPE_OK
              : GPE_EDEVICE;
@@ -230,10 +242,17 @@ gpe_status enqueue_step(gpe_server *s, ShapeClass *c) {
 // Steps to give class c this round: quantum_ms of GPU time per running
 // request, from the GPU time per step measured on its last chunk.  Large
 // grids are bandwidth-bound (time grows with the running slots); small ones
-// are launch-bound (it does not), and run whole graph replays.
+// are launch-bound (it does not), and run whole graph replays.  On-chip
+// classes run beside the main stream on a few CUs: they are paced to last
+// about as long as the main stream's last round.
 int steps_for(gpe_server *s, ShapeClass *c) {
   const int run = std::max(1, c->running);
   double ms = c->step_ms;
+  if (c->onchip) {
+    if (ms <= 0) return s->chunk;
+    const double target = std::max(s->quantum_ms * run, s->main_round_ms);
+    return (int)std::max(1LL, std::min(65536LL, std::llround(target / ms)));
+  }
   if (ms <= 0) {
     if (c->use_graph) return s->chunk;
     const double bytes = 6.0 * (double)run * (double)c->proto->sites * (double)c->proto->esize;
@@ -256,10 +275,34 @@ gpe_status run_chunk(gpe_server *s, ShapeClass *c, int steps) {
       m.n = 0;
       for (int i = 0; i < c->S; ++i)
         if (c->owner[i]) m.idx[m.n++] = i;
-      if (m.n > 0 && gpe::launch_map_write(c->d_map, m, s->stream) != hipSuccess)
+      if (m.n > 0 && gpe::launch_map_write(c->d_map, m, c->strm) != hipSuccess)
         return GPE_EDEVICE;
       c->rows = m.n;
       c->map_dirty = false;
+    }
+    if (c->onchip) {
+      if (c->rows == 0) return GPE_OK;
+      gpe_ctx *p = c->proto;
+      gpe::OnchipArgs a{};
+      a.slots = c->d;
+      a.slot_map = c->d_map;
+      a.steps = steps;
+      a.rows_first = order_axis(p, 0) == 2 ? 1 : 0;
+      a.n = p->n3[2];
+      a.dt = c->key.dt;
+      a.dV = p->dV;
+      for (int j = 0; j < 3; ++j) {
+        a.lo[j] = p->lo3[j];
+        a.h[j] = p->h3[j];
+      }
+      a.tw_row = p->tw[2];
+      a.tw_col = p->tw[1];
+      a.kr_row = c->kreal[2];
+      a.kr_col = c->kreal[1];
+      a.ki_row = c->kimag[2];
+      a.ki_col = c->kimag[1];
+      return gpe::launch_onchip(p->prec, a, c->rows, c->strm) == hipSuccess ? GPE_OK
+                                                                            : GPE_EDEVICE;
     }
     for (int k = 0; k < steps; ++k) {
       gpe_status st = enqueue_step(s, c);
@@ -269,11 +312,11 @@ gpe_status run_chunk(gpe_server *s, ShapeClass *c, int steps) {
   }
   if (!c->graph) {
     hipGraph_t g = nullptr;
-    if (hipStreamBeginCapture(s->stream, hipStreamCaptureModeThreadLocal) != hipSuccess)
+    if (hipStreamBeginCapture(c->strm, hipStreamCaptureModeThreadLocal) != hipSuccess)
       return GPE_EDEVICE;
     gpe_status st = GPE_OK;
     for (int k = 0; k < s->chunk && st == GPE_OK; ++k) st = enqueue_step(s, c);
-    if (hipStreamEndCapture(s->stream, &g) != hipSuccess || st != GPE_OK) {
+    if (hipStreamEndCapture(c->strm, &g) != hipSuccess || st != GPE_OK) {
       if (g) (void)hipGraphDestroy(g);
       return GPE_EDEVICE;
     }
@@ -285,7 +328,7 @@ gpe_status run_chunk(gpe_server *s, ShapeClass *c, int steps) {
     }
   }
   for (int k = 0; k < steps; k += s->chunk)
-    if (hipGraphLaunch(c->graph, s->stream) != hipSuccess) return GPE_EDEVICE;
+    if (hipGraphLaunch(c->graph, c->strm) != hipSuccess) return GPE_EDEVICE;
   return GPE_OK;
 }
 
@@ -313,7 +356,10 @@ gpe_status create_class(gpe_server *s, const gpe_request &r, ShapeClass **out) {
   // Graph replay over all slots pays for the empty rows' dispatch, which is
   // negligible for small grids (where launch latency dominates) and not for
   // large ones.
-  c->use_graph = s->use_graph && p->sites * c->S <= (1LL << 22);
+  c->onchip = s->use_onchip && p->dim == 2 && p->n3[1] == p->n3[2] &&
+              gpe::onchip_supported(p->prec, p->n3[2]);
+  c->use_graph = !c->onchip && s->use_graph && p->sites * c->S <= (1LL << 22);
+  c->strm = c->onchip ? s->side : s->stream;
   c->owner.assign(c->S, 0);
   c->sstate.assign(c->S, SS_FREE);
   c->steps_total.assign(c->S, 0);
@@ -410,7 +456,7 @@ gpe_status admit(gpe_server *s, Req *r, long long round) {
   if (hipMemcpyAsync(x->psi, src, x->sites * x->esize, hipMemcpyHostToDevice, s->aux) !=
           hipSuccess ||
       hipEventRecord(s->ev_up, s->aux) != hipSuccess ||
-      hipStreamWaitEvent(s->stream, s->ev_up, 0) != hipSuccess)
+      hipStreamWaitEvent(c->strm, s->ev_up, 0) != hipSuccess)
     return GPE_EDEVICE;
   gpe::Slot sl{};
   sl.psi = x->psi;
@@ -421,7 +467,7 @@ gpe_status admit(gpe_server *s, Req *r, long long round) {
   sl.steps_done = 0;
   sl.scale = 1.0;
   sl.norm_target = r->r.desc.norm_target;
-  if (gpe::launch_slot_write(c->d + i, sl, s->stream) != hipSuccess) return GPE_EDEVICE;
+  if (gpe::launch_slot_write(c->d + i, sl, c->strm) != hipSuccess) return GPE_EDEVICE;
   c->owner[i] = r->id;
   c->sstate[i] = SS_RUN;
   c->steps_total[i] = sl.steps_total;
@@ -437,7 +483,7 @@ gpe_status admit(gpe_server *s, Req *r, long long round) {
 void clear_entry(gpe_server *s, ShapeClass *c, int i) {
   gpe::Slot sl{};
   sl.mode = gpe::SLOT_FREE;
-  (void)gpe::launch_slot_write(c->d + i, sl, s->stream);
+  (void)gpe::launch_slot_write(c->d + i, sl, c->strm);
 }
 
 void release(gpe_server *s, ShapeClass *c, int i) {
@@ -490,6 +536,7 @@ void drain(gpe_server *s, ShapeClass *c, int i, long long until, gpe_status why)
 // `now` is the round whose chunk is in flight.
 void retire(gpe_server *s, long long q, long long now) {
   const int par = (int)(q & 1);
+  double main_ms = 0;
   for (ShapeClass *c : s->classes) {
     if (!c->hp_valid[par]) continue;
     c->hp_valid[par] = false;
@@ -498,6 +545,7 @@ void retire(gpe_server *s, long long q, long long now) {
         hipEventElapsedTime(&ms, c->ev0[par], c->ev1[par]) == hipSuccess && ms > 0) {
       c->step_ms = ms / c->timed_steps[par];
       c->step_running = c->timed_running[par];
+      if (!c->onchip) main_ms += ms;
     }
     for (int i = 0; i < c->S; ++i) {
       if (!c->owner[i]) continue;
@@ -522,6 +570,7 @@ void retire(gpe_server *s, long long q, long long now) {
       }
     }
   }
+  s->main_round_ms = main_ms;
 }
 
 // Admit queued requests in arrival order, one at a time, so that the bytes
@@ -580,23 +629,27 @@ void scheduler(gpe_server *s) {
     admit_queued(s, round);
     const int par = (int)(round & 1);
     bool any = false;
+    s->used_main[par] = s->used_side[par] = false;
     for (ShapeClass *c : s->classes) {
       c->hp_valid[par] = false;
       if (!c->owned) continue;
       any = true;
+      (c->onchip ? s->used_side : s->used_main)[par] = true;
       const int steps = steps_for(s, c);
-      (void)hipEventRecord(c->ev0[par], s->stream);
+      (void)hipEventRecord(c->ev0[par], c->strm);
       c->failed[par] = run_chunk(s, c, steps) != GPE_OK;
-      (void)hipEventRecord(c->ev1[par], s->stream);
+      (void)hipEventRecord(c->ev1[par], c->strm);
       c->timed_steps[par] = steps;
       c->timed_running[par] = c->running;
       (void)hipMemcpyAsync(c->hp[par], c->d, c->S * sizeof(gpe::Slot), hipMemcpyDeviceToHost,
-                           s->stream);
+                           c->strm);
       c->hp_valid[par] = true;
     }
-    if (any) (void)hipEventRecord(s->done[par], s->stream);
+    if (s->used_main[par]) (void)hipEventRecord(s->done[par], s->stream);
+    if (s->used_side[par]) (void)hipEventRecord(s->done_side[par], s->side);
     if (pending) {
-      (void)hipEventSynchronize(s->done[par ^ 1]);
+      if (s->used_main[par ^ 1]) (void)hipEventSynchronize(s->done[par ^ 1]);
+      if (s->used_side[par ^ 1]) (void)hipEventSynchronize(s->done_side[par ^ 1]);
       retire(s, round - 1, round);
     }
     pending = any;
@@ -611,6 +664,7 @@ void scheduler(gpe_server *s) {
   }
   // Shutting down: let the GPU finish, then cancel whatever is still held.
   (void)hipStreamSynchronize(s->stream);
+  (void)hipStreamSynchronize(s->side);
   (void)hipStreamSynchronize(s->aux);
   for (ShapeClass *c : s->classes)
     for (int i = 0; i < c->S; ++i)
@@ -624,12 +678,14 @@ void scheduler(gpe_server *s) {
 // Free everything the server holds (the scheduler thread has ended).
 void release_server(gpe_server *s) {
   if (s->stream) (void)hipStreamSynchronize(s->stream);
+  if (s->side) (void)hipStreamSynchronize(s->side);
   if (s->aux) (void)hipStreamSynchronize(s->aux);
   for (ShapeClass *c : s->classes) destroy_class(s, c);
   s->classes.clear();
-  for (hipEvent_t e : {s->done[0], s->done[1], s->ev_up})
+  for (hipEvent_t e : {s->done[0], s->done[1], s->done_side[0], s->done_side[1], s->ev_up})
     if (e) (void)hipEventDestroy(e);
   if (s->aux) (void)hipStreamDestroy(s->aux);
+  if (s->side) (void)hipStreamDestroy(s->side);
   if (s->stream) (void)hipStreamDestroy(s->stream);
   delete s;
 }
@@ -647,6 +703,9 @@ gpe_status gpe_server_create(uint64_t hbm_budget_bytes, int32_t max_slots, int32
   if (hipGetDevice(&s->device) != hipSuccess ||
       hipStreamCreateWithFlags(&s->stream, hipStreamNonBlocking) != hipSuccess ||
       hipStreamCreateWithFlags(&s->aux, hipStreamNonBlocking) != hipSuccess ||
+      hipStreamCreateWithFlags(&s->side, hipStreamNonBlocking) != hipSuccess ||
+      hipEventCreateWithFlags(&s->done_side[0], hipEventDisableTiming) != hipSuccess ||
+      hipEventCreateWithFlags(&s->done_side[1], hipEventDisableTiming) != hipSuccess ||
       hipEventCreateWithFlags(&s->done[0], hipEventDisableTiming) != hipSuccess ||
       hipEventCreateWithFlags(&s->done[1], hipEventDisableTiming) != hipSuccess ||
       hipEventCreateWithFlags(&s->ev_up, hipEventDisableTiming) != hipSuccess) {
@@ -659,9 +718,10 @@ gpe_status gpe_server_create(uint64_t hbm_budget_bytes, int32_t max_slots, int32
   s->max_slots = max_slots;
   s->max_active = max_active;
   s->chunk = chunk_steps;
-  // Experiment overrides: graph replay for small classes, GPU time per
-  // running request per round.
+  // Experiment overrides: graph replay for small classes, on-chip classes,
+  // GPU time per running request per round.
   if (const char *g = std::getenv("GPE_SERVER_GRAPH")) s->use_graph = std::atoi(g) != 0;
+  if (const char *o = std::getenv("GPE_SERVER_ONCHIP")) s->use_onchip = std::atoi(o) != 0;
   if (const char *q = std::getenv("GPE_SERVER_QUANTUM_MS")) {
     const double v = std::atof(q);
     if (v > 0) s->quantum_ms = v;
