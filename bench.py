@@ -223,8 +223,11 @@ def main():
     ap.add_argument("--no-cpu", action="store_true")
     ap.add_argument("--no-fp32", action="store_true")
     ap.add_argument("--copy-calibration", action="store_true")
+    ap.add_argument("--tune", action="store_true",
+                    help="run the launch-shape tuner for the bench grid instead of loading "
+                         "the shipped tuning cache")
     ap.add_argument("--no-tune", action="store_true",
-                    help="skip the launch-shape tuner (use the default shapes)")
+                    help="use the default launch shapes (no cache, no tuner)")
     ap.add_argument("--serving", type=int, default=64,
                     help="requests of the serving mix to run (0: skip)")
     ap.add_argument("--serving-slots", type=int, default=16)
@@ -258,12 +261,21 @@ def main():
     sites = n ** 3
     spectra = not args.no_spectra
 
+    from paper_2301_08275_amd import tune_cache
+
     results, tuning = {}, {}
+    tuning_source = "defaults"
+    if not args.no_tune and not args.tune and os.path.exists(tune_cache.SHIPPED):
+        gpe.gpe_tuning_load(tune_cache.SHIPPED)
+        tuning_source = os.path.basename(tune_cache.SHIPPED)
     for prec in (["fp64"] if args.no_fp32 else ["fp64", "fp32"]):
-        if not args.no_tune:
+        d = gpe.make_desc((n, n, n), lo, hi, g, prec)
+        if args.tune:
             # untimed: pick the launch shapes of this shape class on this device
             log("tuning %s" % prec)
-            tuning[prec] = gpe.gpe_autotune(gpe.make_desc((n, n, n), lo, hi, g, prec), steps=5)
+            gpe.gpe_autotune(d, steps=5)
+            tuning_source = "gpe_autotune"
+        tuning[prec] = dict(gpe.gpe_tuning_get(d)[0], source=tuning_source)
         log("timing %s" % prec)
         ctx = gpe.Context((n, n, n), lo, hi, g, precision=prec,
                           norm_target=(2 * 3.141592653589793) ** 3, stream=stream)
@@ -308,7 +320,7 @@ def main():
                           "hbm_GBps_at_96B_per_site_step":
                               96.0 * sites / (step_ms * 1e-3) / 1e9},
         "kernels": kernel_table(r64["kinds"]),
-        "tuning": tuning.get("fp64", "defaults"),
+        "tuning": tuning["fp64"],
     }
     if "fp32" in results:
         r32 = results["fp32"]
@@ -321,7 +333,7 @@ def main():
                        "dominant_kernel": n32, "achieved_GBps": ach32,
                        "frac": ach32 / HBM_PEAK_GBS,
                        "kernels": kernel_table(r32["kinds"]),
-                       "tuning": tuning.get("fp32", "defaults")}
+                       "tuning": tuning["fp32"]}
     if args.serving > 0:
         log("serving mix: %d requests" % args.serving)
         out["serving"] = serving_bench(args.serving, args.serving_slots, args.serving_chunk)
