@@ -268,7 +268,7 @@ def main():
     if not args.no_tune and not args.tune and os.path.exists(tune_cache.SHIPPED):
         gpe.gpe_tuning_load(tune_cache.SHIPPED)
         tuning_source = os.path.basename(tune_cache.SHIPPED)
-    for prec in (["fp64"] if args.no_fp32 else ["fp64", "fp32"]):
+    for prec in (["fp64"] if args.no_fp32 else ["fp64", "fp32", "fp32s"]):
         d = gpe.make_desc((n, n, n), lo, hi, g, prec)
         if args.tune:
             # untimed: pick the launch shapes of this shape class on this device
@@ -334,6 +334,19 @@ def main():
                        "frac": ach32 / HBM_PEAK_GBS,
                        "kernels": kernel_table(r32["kinds"]),
                        "tuning": tuning["fp32"]}
+    if "fp32s" in results:
+        # FP32 state in HBM (half the bytes), FP64 arithmetic in every pass
+        rs = results["fp32s"]
+        vs = sites * args.steps / (rs["ms"] * 1e-3)
+        ns, a_s, achs, bs = rs["dom"]
+        ss = sum(v["total_ms"] for k, v in rs["kinds"].items() if k.startswith("step_"))
+        out["fp32_state"] = {"value": vs, "ms_per_step": rs["ms"] / args.steps,
+                             "speedup_vs_fp64": vs / value,
+                             "stepping_only_ms_per_step": ss / args.steps,
+                             "dominant_kernel": ns, "achieved_GBps": achs,
+                             "frac": achs / HBM_PEAK_GBS,
+                             "kernels": kernel_table(rs["kinds"]),
+                             "tuning": tuning["fp32s"]}
     if args.serving > 0:
         log("serving mix: %d requests" % args.serving)
         out["serving"] = serving_bench(args.serving, args.serving_slots, args.serving_chunk)

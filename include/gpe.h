@@ -50,13 +50,15 @@ typedef enum {
   GPE_ECANCELED = -8     /* request cancelled before it finished */
 } gpe_status;
 
-typedef enum { GPE_FP64 = 0, GPE_FP32 = 1 } gpe_precision;
+typedef enum { GPE_FP64 = 0, GPE_FP32 = 1, GPE_FP32_STATE = 2 } gpe_precision;
 
-/* Problem description (Eq. 2's grid, g and normalisation).  The state
- * precision is GPE_FP64 or GPE_FP32; in FP32 the state and the FFT are FP32
- * while phase arguments, sums and the imaginary-time renormalisation stay
- * FP64.  norm_target is the value of dV * sum |psi|^2 that the ground-state
- * method renormalises to (1 when the particle number is absorbed in g). */
+/* Problem description (Eq. 2's grid, g and normalisation).  precision:
+ * GPE_FP64; GPE_FP32, the state and the FFT in FP32 while phase arguments,
+ * sums and the imaginary-time renormalisation stay FP64; GPE_FP32_STATE, the
+ * state held in FP32 in device memory (half the bytes of FP64) and every
+ * operation of a pass in FP64 (one FP32 rounding per pass, at the store).
+ * norm_target is the value of dV * sum |psi|^2 that the ground-state method
+ * renormalises to (1 when the particle number is absorbed in g). */
 typedef struct {
   int32_t dim;
   int32_t n[3];
@@ -128,14 +130,16 @@ gpe_status gpe_set_potential(gpe_ctx *ctx, const double *V_host,
 /* Copy a host FP64 state in (interleaved complex, n sites); synchronous. */
 gpe_status gpe_set_state(gpe_ctx *ctx, const double *psi_host);
 
-/* Copy a device state in from dptr (interleaved complex of precision src,
- * n sites, device memory of the context's device); enqueued on the stream. */
+/* Copy a device state in from dptr (interleaved complex, src = GPE_FP64 for
+ * FP64 or GPE_FP32 for FP32 values, n sites, device memory of the context's
+ * device); enqueued on the stream. */
 gpe_status gpe_set_state_device(gpe_ctx *ctx, const void *dptr, int32_t src);
 
 /* Copy the state out to a host FP64 buffer (2 n doubles); synchronous. */
 gpe_status gpe_get_state(gpe_ctx *ctx, double *psi_host_out);
 
-/* Copy the state out to device memory in precision dst; enqueued. */
+/* Copy the state out to device memory as FP64 (dst = GPE_FP64) or FP32
+ * (dst = GPE_FP32) values; enqueued. */
 gpe_status gpe_get_state_device(gpe_ctx *ctx, void *dptr, int32_t dst);
 
 /* Real-time TSSP (Numerical Scheme section): nsteps Strang steps

@@ -491,7 +491,15 @@ enum PassMode : int {
   MODE_SLOTS = 5,          // batched shape class: operations from each block's slot
 };
 
-template <typename T, class PL, int W, bool STRIDED, int MODE>
+// Storage type of the state in HBM, converted on load and store: the
+// arithmetic type T, or FP32 storage with FP64 arithmetic (SX = float,
+// T = double).
+template <typename T, typename SX>
+__device__ __forceinline__ cx<T> cvt(const cx<SX> &u) {
+  return {(T)u.x, (T)u.y};
+}
+
+template <typename T, class PL, int W, bool STRIDED, int MODE, typename SX = T>
 __global__ void __launch_bounds__(PL::TPL * W)
 axis_pass_kernel(const PassArgs a) {
   constexpr int N = PL::N, E = PL::E, TPL = PL::TPL;
@@ -584,8 +592,8 @@ axis_pass_kernel(const PassArgs a) {
   }
   const int axis = STRIDED ? a.axis : 2;
 
-  const cx<T> *__restrict__ src = static_cast<const cx<T> *>(psrc);
-  cx<T> *__restrict__ dst = static_cast<cx<T> *>(pdst);
+  const cx<SX> *__restrict__ src = static_cast<const cx<SX> *>(psrc);
+  cx<SX> *__restrict__ dst = static_cast<cx<SX> *>(pdst);
   const tab_t<T> *__restrict__ tw = static_cast<const tab_t<T> *>(a.tw);
   const tab_t<T> *__restrict__ mtab = static_cast<const tab_t<T> *>(ptab);
   constexpr int R0 = PL::rad(0), RL = PL::rad(PL::M - 1);
@@ -601,7 +609,7 @@ axis_pass_kernel(const PassArgs a) {
 #pragma unroll
       for (int d = 0; d < R0; ++d) {
         const int p = PL::pos(0, t + TPL * b, d);
-        v[b * R0 + d] = valid ? src[base + p * S] : cx<T>{0, 0};
+        v[b * R0 + d] = valid ? cvt<T>(src[base + p * S]) : cx<T>{0, 0};
       }
     if (has_scale || pre != PH_NONE || (red & RED_REAL)) {
       const double sc = has_scale ? *pscale : 1.0;
@@ -639,7 +647,7 @@ axis_pass_kernel(const PassArgs a) {
 #pragma unroll
       for (int d = 0; d < RL; ++d) {
         const int p = PL::pos(PL::M - 1, t + TPL * b, d);
-        v[b * RL + d] = valid ? src[base + PL::freq(p) * S] : cx<T>{0, 0};
+        v[b * RL + d] = valid ? cvt<T>(src[base + PL::freq(p) * S]) : cx<T>{0, 0};
       }
   }
 
@@ -654,7 +662,7 @@ axis_pass_kernel(const PassArgs a) {
         if (red & RED_KIN) acc[kSlotKin] += a.kw[f] * ((double)u.x * u.x + (double)u.y * u.y);
         if (mid == MID_TABLE) u = table_mul(u, mtab[f]);
         v[b * RL + d] = u;
-        if (!inverse && store && valid) dst[base + f * S] = u;
+        if (!inverse && store && valid) dst[base + f * S] = cvt<SX>(u);
       }
   }
 
@@ -669,7 +677,7 @@ axis_pass_kernel(const PassArgs a) {
           cx<T> u = v[b * R0 + d];
           if (post == PH_DERIV) {
             // combine the derivative with the state at this site (re-read)
-            const cx<T> q = valid ? src[base + p * S] : cx<T>{0, 0};
+            const cx<T> q = valid ? cvt<T>(src[base + p * S]) : cx<T>{0, 0};
             const double qr = q.x, qi = q.y, dr = u.x, di = u.y;
             const double mag = sqrt(qr * qr + qi * qi);
             const double zr = qr * dr + qi * di, zi = qr * di - qi * dr;  // conj(q) d
@@ -689,7 +697,7 @@ axis_pass_kernel(const PassArgs a) {
 #pragma unroll
         for (int d = 0; d < R0; ++d) {
           const int p = PL::pos(0, t + TPL * b, d);
-          dst[base + p * S] = v[b * R0 + d];
+          dst[base + p * S] = cvt<SX>(v[b * R0 + d]);
         }
     }
   }
@@ -718,58 +726,63 @@ __host__ __device__ constexpr int fit_w(int N, int esize, int W) {
   return W;
 }
 
-template <typename T, class PL, int W, bool STRIDED>
+template <typename T, class PL, int W, bool STRIDED, typename SX>
 void launch_mode(const PassArgs &a, int mode, dim3 grid, dim3 block, hipStream_t s) {
   switch (mode) {
     case MODE_PLAIN:
-      hipLaunchKernelGGL((axis_pass_kernel<T, PL, W, STRIDED, MODE_PLAIN>), grid, block, 0, s, a);
+      hipLaunchKernelGGL((axis_pass_kernel<T, PL, W, STRIDED, MODE_PLAIN, SX>), grid, block, 0, s,
+                         a);
       break;
     case MODE_PRE_REAL:
-      hipLaunchKernelGGL((axis_pass_kernel<T, PL, W, STRIDED, MODE_PRE_REAL>), grid, block, 0, s, a);
-      break;
-    case MODE_PRE_IMAG:
-      hipLaunchKernelGGL((axis_pass_kernel<T, PL, W, STRIDED, MODE_PRE_IMAG>), grid, block, 0, s, a);
-      break;
-    case MODE_POST_IMAG_RED:
-      hipLaunchKernelGGL((axis_pass_kernel<T, PL, W, STRIDED, MODE_POST_IMAG_RED>), grid, block, 0,
+      hipLaunchKernelGGL((axis_pass_kernel<T, PL, W, STRIDED, MODE_PRE_REAL, SX>), grid, block, 0,
                          s, a);
       break;
+    case MODE_PRE_IMAG:
+      hipLaunchKernelGGL((axis_pass_kernel<T, PL, W, STRIDED, MODE_PRE_IMAG, SX>), grid, block, 0,
+                         s, a);
+      break;
+    case MODE_POST_IMAG_RED:
+      hipLaunchKernelGGL((axis_pass_kernel<T, PL, W, STRIDED, MODE_POST_IMAG_RED, SX>), grid,
+                         block, 0, s, a);
+      break;
     case MODE_SLOTS:
-      hipLaunchKernelGGL((axis_pass_kernel<T, PL, W, STRIDED, MODE_SLOTS>), grid, block, 0, s, a);
+      hipLaunchKernelGGL((axis_pass_kernel<T, PL, W, STRIDED, MODE_SLOTS, SX>), grid, block, 0, s,
+                         a);
       break;
     default:
-      hipLaunchKernelGGL((axis_pass_kernel<T, PL, W, STRIDED, MODE_GENERIC>), grid, block, 0, s, a);
+      hipLaunchKernelGGL((axis_pass_kernel<T, PL, W, STRIDED, MODE_GENERIC, SX>), grid, block, 0,
+                         s, a);
   }
 }
 
-template <typename T, int N>
+template <typename T, int N, typename SX>
 hipError_t launch_n(const PassArgs &a, const PassShape &sh, int mode, hipStream_t s) {
   using PL = typename PlanFor<N>::type;
   const dim3 grid((unsigned)sh.blocks, (unsigned)(a.slots ? a.nslots : 1)), block((unsigned)sh.threads);
   constexpr int W16 = fit_w(N, (int)(2 * sizeof(T)), 16);
   if (!sh.strided) {
-    launch_mode<T, PL, contig_lines<N>(), false>(a, mode, grid, block, s);
+    launch_mode<T, PL, contig_lines<N>(), false, SX>(a, mode, grid, block, s);
   } else if (sh.W == 8) {
-    launch_mode<T, PL, 8, true>(a, mode, grid, block, s);
+    launch_mode<T, PL, 8, true, SX>(a, mode, grid, block, s);
   } else if (sh.W == 16 && W16 == 16) {
-    launch_mode<T, PL, (W16 == 16 ? 16 : 8), true>(a, mode, grid, block, s);
+    launch_mode<T, PL, (W16 == 16 ? 16 : 8), true, SX>(a, mode, grid, block, s);
   } else {
     return hipErrorInvalidValue;
   }
   return hipGetLastError();
 }
 
-template <typename T>
+template <typename T, typename SX = T>
 hipError_t launch_t(const PassArgs &a, const PassShape &sh, int mode, hipStream_t s) {
   switch (sh.N) {
-    case 8: return launch_n<T, 8>(a, sh, mode, s);
-    case 16: return launch_n<T, 16>(a, sh, mode, s);
-    case 32: return launch_n<T, 32>(a, sh, mode, s);
-    case 64: return launch_n<T, 64>(a, sh, mode, s);
-    case 128: return launch_n<T, 128>(a, sh, mode, s);
-    case 256: return launch_n<T, 256>(a, sh, mode, s);
-    case 512: return launch_n<T, 512>(a, sh, mode, s);
-    case 1024: return launch_n<T, 1024>(a, sh, mode, s);
+    case 8: return launch_n<T, 8, SX>(a, sh, mode, s);
+    case 16: return launch_n<T, 16, SX>(a, sh, mode, s);
+    case 32: return launch_n<T, 32, SX>(a, sh, mode, s);
+    case 64: return launch_n<T, 64, SX>(a, sh, mode, s);
+    case 128: return launch_n<T, 128, SX>(a, sh, mode, s);
+    case 256: return launch_n<T, 256, SX>(a, sh, mode, s);
+    case 512: return launch_n<T, 512, SX>(a, sh, mode, s);
+    case 1024: return launch_n<T, 1024, SX>(a, sh, mode, s);
     default: return hipErrorInvalidValue;
   }
 }

@@ -6,6 +6,7 @@ namespace pass {
 
 hipError_t launch_f64(const PassArgs &a, const PassShape &sh, int mode, hipStream_t s);
 hipError_t launch_f32(const PassArgs &a, const PassShape &sh, int mode, hipStream_t s);
+hipError_t launch_s32(const PassArgs &a, const PassShape &sh, int mode, hipStream_t s);
 
 int tpl_of(int N) {
   switch (N) {
@@ -54,7 +55,7 @@ PassShape pass_shape(int precision, const int n[3], int axis, int wreq) {
     sh.blocks = (lines + sh.W - 1) / sh.W;
   } else {
     const int want = wreq == 16 ? 16 : 8;
-    const int ws = fit_w(sh.N, precision == 1 ? 8 : 16, want);
+    const int ws = fit_w(sh.N, math_f32(precision) ? 8 : 16, want);
     sh.W = n[2] >= ws ? ws : 8;
     sh.threads = tpl * sh.W;
     const long long outer = axis == 1 ? n[0] : n[1];
@@ -67,7 +68,9 @@ hipError_t launch_axis_pass(int precision, const PassArgs &a, hipStream_t s) {
   const PassShape sh = pass_shape(precision, a.n, a.axis, a.wreq);
   if (sh.threads == 0 || (sh.strided && a.n[2] < sh.W)) return hipErrorInvalidValue;
   const int mode = pass::pick_mode(a, sh);
-  return precision == 1 ? pass::launch_f32(a, sh, mode, s) : pass::launch_f64(a, sh, mode, s);
+  if (precision == 1) return pass::launch_f32(a, sh, mode, s);
+  if (precision == 2) return pass::launch_s32(a, sh, mode, s);
+  return pass::launch_f64(a, sh, mode, s);
 }
 
 }  // namespace gpe

@@ -185,7 +185,7 @@ std::string kind_name(int prec, const gpe::PassArgs &a) {
   else if (!a.inverse) op = "fft";
   else if (a.post == gpe::PH_DERIV) op = "deriv";
   static const char ax[3] = {'x', 'y', 'z'};
-  return std::string(op) + "_" + ax[a.axis] + (prec == 1 ? "_fp32" : "_fp64");
+  return std::string(op) + "_" + ax[a.axis] + (prec == 1 ? "_fp32" : prec == 2 ? "_fp32s" : "_fp64");
 }
 
 gpe_status launch_pass(gpe_ctx *c, const gpe::PassArgs &a) {
@@ -286,8 +286,8 @@ gpe_status validate_desc(const gpe_desc *d, std::string &msg) {
     }
   }
   if (!std::isfinite(d->g)) { msg = "g must be finite"; return GPE_EINVAL; }
-  if (d->precision != GPE_FP64 && d->precision != GPE_FP32) {
-    msg = "precision must be GPE_FP64 or GPE_FP32";
+  if (d->precision != GPE_FP64 && d->precision != GPE_FP32 && d->precision != GPE_FP32_STATE) {
+    msg = "precision must be GPE_FP64, GPE_FP32 or GPE_FP32_STATE";
     return GPE_EINVAL;
   }
   if (!(d->norm_target > 0) || !std::isfinite(d->norm_target)) {
@@ -505,7 +505,7 @@ uint64_t context_bytes(const gpe_desc &d, bool with_state) {
     n3[j + off] = d.n[j];
     sites *= d.n[j];
   }
-  const uint64_t es = d.precision == GPE_FP32 ? 8 : 16;
+  const uint64_t es = gpe::state_f32(d.precision) ? 8 : 16;
   int wdef[3], xcd[3], order[3];
   effective_tuning(d, wdef, xcd, order);
   long long maxb = 1;
@@ -547,7 +547,7 @@ gpe_status create_context(const gpe_desc *desc, const double *V_host, const gpe_
   c->desc = *desc;
   c->dim = desc->dim;
   c->prec = desc->precision;
-  c->esize = c->prec == GPE_FP32 ? 8 : 16;
+  c->esize = gpe::state_f32(c->prec) ? 8 : 16;
   effective_tuning(*desc, c->wreq, c->xcd_remap, c->pass_order);
   const int off = 3 - c->dim;
   c->sites = 1;

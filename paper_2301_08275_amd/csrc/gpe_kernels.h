@@ -153,6 +153,11 @@ struct OnchipArgs {
 bool onchip_supported(int precision, int n);
 hipError_t launch_onchip(int precision, const OnchipArgs &a, int rows, hipStream_t s);
 
+// Precision codes of a context: 0 FP64; 1 FP32 state and arithmetic; 2 FP32
+// state with FP64 arithmetic.
+inline bool state_f32(int precision) { return precision != 0; }
+inline bool math_f32(int precision) { return precision == 1; }
+
 // Most slots a shape class holds (the active-slot map travels as a kernel
 // argument).
 constexpr int kMaxSlots = 256;

@@ -274,6 +274,7 @@ hipError_t launch_oc(const OnchipArgs &a, int rows, hipStream_t s) {
 }  // namespace pass
 
 bool onchip_supported(int precision, int n) {
+  if (precision != 0 && precision != 1) return false;
   const int nmax = precision == 1 ? 128 : 64;
   return n >= 8 && n <= nmax && (n & (n - 1)) == 0;
 }

@@ -138,7 +138,7 @@ hipError_t launch_map_write(int *dst, const SlotMap &m, hipStream_t s) {
 hipError_t launch_scale(int precision, void *psi, long long sites, double *c,
                         hipStream_t s) {
   const long long n = 2 * sites;  // real components
-  if (precision == 1)
+  if (state_f32(precision))
     hipLaunchKernelGGL(scale_kernel<float>, dim3(grid_for(n, 256)), dim3(256), 0, s,
                        static_cast<float *>(psi), n, c);
   else
@@ -150,7 +150,7 @@ hipError_t launch_scale(int precision, void *psi, long long sites, double *c,
 
 hipError_t launch_fill_noise(int precision, void *psi, long long sites, hipStream_t s) {
   const long long n = 2 * sites;
-  if (precision == 1)
+  if (state_f32(precision))
     hipLaunchKernelGGL(fill_noise_kernel<float>, dim3(grid_for(n, 256)), dim3(256), 0, s,
                        static_cast<float *>(psi), n);
   else
@@ -163,6 +163,9 @@ hipError_t launch_convert(int src_prec, const void *src, int dst_prec, void *dst
                           long long sites, hipStream_t s) {
   const long long n = 2 * sites;
   const dim3 g(grid_for(n, 256)), b(256);
+  // storage types only: codes 1 and 2 both hold FP32 values
+  src_prec = state_f32(src_prec) ? 1 : 0;
+  dst_prec = state_f32(dst_prec) ? 1 : 0;
   if (src_prec == 0 && dst_prec == 1)
     hipLaunchKernelGGL((convert_kernel<double, float>), g, b, 0, s,
                        static_cast<const double *>(src), static_cast<float *>(dst), n);

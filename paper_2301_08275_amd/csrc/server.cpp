@@ -451,7 +451,7 @@ gpe_status admit(gpe_server *s, Req *r, long long round) {
     if ((st = set_potential(c->ctx[i], nullptr, &r->r.trap)) != GPE_OK) return st;
   }
   gpe_ctx *x = c->ctx[i];
-  const void *src = x->prec == GPE_FP32 ? (const void *)r->psi0_f.data()
+  const void *src = gpe::state_f32(x->prec) ? (const void *)r->psi0_f.data()
                                         : (const void *)r->psi0_d.data();
   if (hipMemcpyAsync(x->psi, src, x->sites * x->esize, hipMemcpyHostToDevice, s->aux) !=
           hipSuccess ||
@@ -740,7 +740,8 @@ gpe_status gpe_server_submit(gpe_server *s, const gpe_request *req, uint64_t *id
     if (d.n[j] < 8 || d.n[j] > 1024 || (d.n[j] & (d.n[j] - 1))) return GPE_EUNSUPPORTED;
     if (!(d.hi[j] > d.lo[j])) return GPE_EINVAL;
   }
-  if (!std::isfinite(d.g) || (d.precision != GPE_FP64 && d.precision != GPE_FP32) ||
+  if (!std::isfinite(d.g) ||
+      (d.precision != GPE_FP64 && d.precision != GPE_FP32 && d.precision != GPE_FP32_STATE) ||
       !(d.norm_target > 0) || !(req->dt > 0) || !std::isfinite(req->dt) || req->nsteps < 0 ||
       req->nsteps > 2000000000 || (req->mode != 0 && req->mode != 1))
     return GPE_EINVAL;
@@ -748,7 +749,7 @@ gpe_status gpe_server_submit(gpe_server *s, const gpe_request *req, uint64_t *id
   r->r = *req;
   r->r.psi0 = nullptr;
   const size_t nreal = 2 * (size_t)sites_of(d);
-  if (d.precision == GPE_FP32) {
+  if (gpe::state_f32(d.precision)) {
     r->psi0_f.resize(nreal);
     for (size_t i = 0; i < nreal; ++i) r->psi0_f[i] = (float)req->psi0[i];
   } else {

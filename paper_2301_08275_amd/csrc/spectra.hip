@@ -116,7 +116,7 @@ hipError_t launch_shells(int precision, const ShellArgs &a, hipStream_t s) {
   const int blocks = shell_blocks(sites);
   const size_t lds = 4 * (size_t)a.nbins * sizeof(double);
   if (lds > 64 * 1024) return hipErrorInvalidValue;
-  if (precision == 1)
+  if (state_f32(precision))  // the packed fields are stored like the state
     hipLaunchKernelGGL(shell_kernel<float>, dim3(blocks), dim3(kShellThreads), lds, s, a);
   else
     hipLaunchKernelGGL(shell_kernel<double>, dim3(blocks), dim3(kShellThreads), lds, s, a);

@@ -50,7 +50,7 @@ std::map<TuneKey, gpe_tuning> g_table;
 // contiguous tile runs per XCD on the strided axes, slowest axis last.
 void defaults(const gpe_desc &d, int wreq[3], int xcd[3], int order[3]) {
   wreq[0] = 16;
-  wreq[1] = d.precision == GPE_FP32 ? 16 : 8;
+  wreq[1] = d.precision == GPE_FP64 ? 8 : 16;
   wreq[2] = 8;
   xcd[0] = xcd[1] = 1;
   xcd[2] = 0;
@@ -310,7 +310,8 @@ gpe_status gpe_tuning_save(const char *path) {
       std::snprintf(buf, sizeof(buf),
                     "%s\n    {\"dim\": %d, \"n\": %s, \"precision\": \"%s\", \"width\": %s, "
                     "\"xcd_remap\": %s, \"pass_order\": %s, \"ms_per_step\": %.6g}",
-                    first ? "" : ",", d, arr(k.n).c_str(), k.prec == GPE_FP32 ? "fp32" : "fp64",
+                    first ? "" : ",", d, arr(k.n).c_str(),
+                    k.prec == GPE_FP32 ? "fp32" : k.prec == GPE_FP32_STATE ? "fp32s" : "fp64",
                     arr(t.width).c_str(), arr(t.xcd_remap).c_str(), arr(t.pass_order).c_str(),
                     t.ms_per_step);
       s += buf;
@@ -359,9 +360,10 @@ gpe_status gpe_tuning_load(const char *path) {
         !int_array(e.get("xcd_remap"), d, t.xcd_remap) ||
         !int_array(e.get("pass_order"), d, t.pass_order))
       return GPE_EINVAL;
-    if (!prec || prec->kind != JVal::STR || (prec->str != "fp64" && prec->str != "fp32"))
+    if (!prec || prec->kind != JVal::STR ||
+        (prec->str != "fp64" && prec->str != "fp32" && prec->str != "fp32s"))
       return GPE_EINVAL;
-    desc.precision = prec->str == "fp32" ? GPE_FP32 : GPE_FP64;
+    desc.precision = prec->str == "fp32" ? GPE_FP32 : prec->str == "fp32s" ? GPE_FP32_STATE : GPE_FP64;
     for (int j = 0; j < d; ++j) {
       desc.lo[j] = 0;
       desc.hi[j] = 1;

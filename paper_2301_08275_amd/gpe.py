@@ -32,6 +32,8 @@ STATUS_NAMES = {0: "GPE_OK", -1: "GPE_EINVAL", -2: "GPE_ENOMEM", -3: "GPE_EDEVIC
 
 GPE_FP64 = 0
 GPE_FP32 = 1
+GPE_FP32_STATE = 2  # FP32 state in device memory, FP64 arithmetic
+PRECISIONS = {"fp64": GPE_FP64, "fp32": GPE_FP32, "fp32s": GPE_FP32_STATE}
 
 
 class gpe_desc(ctypes.Structure):
@@ -379,7 +381,8 @@ class Context:
     """One solver instance on the current HIP device.
 
     shape: grid points per axis (2 or 3 entries); lo, hi: box; g: interaction;
-    precision: "fp64" or "fp32"; V: FP64 array of `shape` or None; harmonic:
+    precision: "fp64", "fp32" (FP32 state and FFT) or "fp32s" (FP32 state,
+    FP64 arithmetic); V: FP64 array of `shape` or None; harmonic:
     trap frequencies per axis (V = 1/2 sum w^2 x^2) or None; stream: a
     hipStream_t handle (int) such as torch.cuda.current_stream().cuda_stream.
     """
@@ -400,7 +403,7 @@ class Context:
         for j in range(dim, 3):
             d.n[j] = 1
         d.g = float(g)
-        d.precision = GPE_FP32 if precision == "fp32" else GPE_FP64
+        d.precision = PRECISIONS[precision]
         d.norm_target = float(norm_target)
         self.precision = precision
         self.desc = d
@@ -534,7 +537,7 @@ def make_desc(shape, lo, hi, g, precision="fp64", norm_target=1.0):
     for j in range(dim, 3):
         d.n[j] = 1
     d.g = float(g)
-    d.precision = GPE_FP32 if precision == "fp32" else GPE_FP64
+    d.precision = PRECISIONS[precision]
     d.norm_target = float(norm_target)
     return d
 

@@ -23,3 +23,16 @@ def load_golden(name):
 @pytest.fixture(scope="session")
 def golden():
     return load_golden
+
+
+@pytest.hookimpl(trylast=True)  # after -m has deselected items
+def pytest_collection_modifyitems(config, items):
+    """When GPU tests will run, initialise torch's HIP runtime before anything
+    loads libgpe.so: torch ships its own copy of the runtime under the same
+    soname, and the library must bind to the one torch has loaded (a GPU test
+    that uses torch tensors next to the library needs that order)."""
+    if any(item.get_closest_marker("gpu") for item in items):
+        import torch
+
+        if torch.cuda.is_available():
+            torch.cuda.init()

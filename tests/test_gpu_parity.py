@@ -296,3 +296,92 @@ def test_fp32_ground_state_matches_table():
     assert conv
     assert abs(o["mu"] / 4.61136 - 1) < 2e-4
     assert abs(o["r_rms"] / 1.78722 - 1) < 2e-4
+
+
+# ----------------------------------------- FP32 state, FP64 arithmetic ---
+# One FP32 rounding per pass (the store), so the bars are far tighter than the
+# FP32 form's: rounding noise grows like sqrt(passes) * 2^-25 ~ 1e-6 after
+# 3000 passes, and round-to-nearest leaves no bias in the norm.
+
+def test_fp32s_transform():
+    shape = (64, 32, 128)
+    x = random_state(shape, 3)
+    with gpe.Context(shape, (0,) * 3, (1,) * 3, 0.0, precision="fp32s") as ctx:
+        ctx.set_state(x)
+        ctx.transform()
+        got = ctx.get_state()
+    assert rel(got, oracle.fft(x)) < 2e-7
+
+
+@pytest.mark.parametrize("n", [64, 128])
+def test_fp32s_turbulence(n):
+    say("fp32s turbulence", n)
+    lo, hi = (0.0,) * 3, (2 * np.pi,) * 3
+    psi0 = I.phase_field(n, seed=2)
+    steps = 1000 if n == 64 else 200
+    ref = oracle.tssp_real(psi0, lo, hi, None, 1.0, 5e-4, steps)
+    o_ref = oracle.observables(ref, lo, hi, None, 1.0)
+    with gpe.Context((n, n, n), lo, hi, 1.0, precision="fp32s",
+                     norm_target=(2 * np.pi) ** 3) as ctx:
+        ctx.set_state(psi0)
+        n0 = ctx.observables()["norm"]
+        ctx.evolve(5e-4, steps)
+        got = ctx.get_state()
+        o = ctx.observables()
+    assert rel(got, ref) < 1e-5
+    assert abs(o["norm"] - n0) / n0 < 1e-8
+    assert abs(o["energy"] - o_ref["energy"]) / abs(o_ref["energy"]) < 1e-7
+
+
+def test_fp32s_cfg0_1000_steps():
+    """The 2D trap workload: the state is localised (few sites carry the norm),
+    so the random walk of the per-pass FP32 rounding in the norm is larger than
+    on the turbulence state (measured 2.4e-8 after 1000 steps): bar 1e-7,
+    ten times inside the FP32 form's 1e-6."""
+    shape, lo, hi, V, psi0 = cfg0()
+    ref = oracle.tssp_real(psi0, lo, hi, V, 10.0, 1e-3, 1000)
+    with gpe.Context(shape, lo, hi, 10.0, harmonic=[1.0, 1.0], precision="fp32s") as ctx:
+        ctx.set_state(psi0)
+        ctx.evolve(1e-3, 1000)
+        got = ctx.get_state()
+        o = ctx.observables()
+    assert rel(got, ref) < 1e-5
+    assert abs(o["norm"] - 1) < 1e-7
+
+
+def test_fp32s_ground_state_matches_fp64():
+    """A Table 1 setup (2D, g = 62.742) for a fixed 4000 imaginary-time steps
+    in FP32 state and in FP64 (a stop rule would compare convergence, not
+    precision).  Slowly decaying modes keep the per-pass FP32 roundings for
+    ~1/(gap dt) steps, a random walk of ~sqrt(8000) * 3e-8 (measured 4.1e-6):
+    bars 2e-5 on the state and 1e-5 on mu and r_rms, inside the FP32 form's
+    1e-4."""
+    shape, lo, hi = (64, 64), (-12.0, -12.0), (12.0, 12.0)
+    out = {}
+    for prec in ("fp64", "fp32s"):
+        with gpe.Context(shape, lo, hi, 62.742, harmonic=[1.0, 1.0], precision=prec) as ctx:
+            ctx.set_state(I.gaussian(shape, lo, hi))
+            ctx.imag_steps(1e-3, 4000)
+            out[prec] = (ctx.get_state(), ctx.observables())
+    (s64, o64), (s32, o32) = out["fp64"], out["fp32s"]
+    say("fp32s ground state: rel %.3g, mu %.3g, r_rms %.3g" % (
+        rel(s32, s64), o32["mu"] / o64["mu"] - 1, o32["r_rms"] / o64["r_rms"] - 1))
+    assert rel(s32, s64) < 2e-5
+    assert abs(o32["mu"] / o64["mu"] - 1) < 1e-5
+    assert abs(o32["r_rms"] / o64["r_rms"] - 1) < 1e-5
+    assert abs(o64["mu"] / 4.61136 - 1) < 2e-4
+
+
+def test_fp32s_spectra_close_to_fp64():
+    lo, hi = (0.0,) * 3, (2 * np.pi,) * 3
+    psi0 = I.phase_field(64, seed=2)
+    out = {}
+    for prec in ("fp64", "fp32s"):
+        with gpe.Context((64,) * 3, lo, hi, 1.0, precision=prec,
+                         norm_target=(2 * np.pi) ** 3) as ctx:
+            ctx.set_state(psi0)
+            ctx.evolve(5e-4, 100)
+            out[prec] = ctx.spectra()
+    for key in ("n_k", "e_comp", "e_incomp", "e_qp"):
+        a, b = out["fp32s"][key], out["fp64"][key]
+        assert np.linalg.norm(a - b) <= 1e-6 * np.linalg.norm(b), key
