@@ -182,6 +182,8 @@ def serving_bench(nreq, max_slots, chunk):
         ids.append(srv.submit(**submit_args(r, p)))
     srv.wait_idle()
     res = [srv.poll(i) for i in ids]
+    for i in ids:
+        srv.release(i)
     srv.close()
     ok = sum(1 for x in res if x["status"] == gpe.GPE_OK)
     lat = [x["t_done"] - x["t_submit"] for x in res]

@@ -150,6 +150,19 @@ gpe_status gpe_get_state_device(gpe_ctx *ctx, void *dptr, int32_t dst);
  * (time reversal); dt = 0 or nsteps < 0 is GPE_EINVAL.  Asynchronous. */
 gpe_status gpe_evolve(gpe_ctx *ctx, double dt, int64_t nsteps);
 
+/* Real-time TSSP with an observable time series (the sigma(t), E(t) records
+ * of the dynamics setups): nsteps steps in chunks of `every` (the last may be
+ * shorter), and after each chunk the observables of the completed Strang step
+ * in series[k], k < *count = ceil(nsteps/every).  The device never waits on
+ * the host between chunks; one copy brings all records back at the end.  The
+ * state equals that of gpe_evolve called once per chunk (a single
+ * gpe_evolve over nsteps differs only by rounding: the chunk boundaries apply
+ * N(dt/2) twice where it applies N(dt) once).  capacity: entries of series
+ * (GPE_EINVAL if below ceil(nsteps/every)).  GPE_ENONFINITE if a record is
+ * not finite (all records are still written). */
+gpe_status gpe_evolve_record(gpe_ctx *ctx, double dt, int64_t nsteps, int32_t every,
+                             gpe_obs *series, int64_t capacity, int64_t *count);
+
 /* Imaginary-time ground state (Numerical Scheme section: t -> -i t with the
  * wavefunction normalised at every step).  Each step is
  * N_im(dt/2) K_im(dt) N_im(dt/2) followed by psi <- psi sqrt(norm_target /
@@ -291,6 +304,11 @@ gpe_status gpe_server_poll(gpe_server *srv, uint64_t id, gpe_result *out, double
  * observables or final state). */
 gpe_status gpe_server_cancel(gpe_server *srv, uint64_t id);
 
+/* Drop the record of a finished request, with its stored final state (a
+ * server keeps every finished request until it is released or the server is
+ * destroyed).  GPE_EBUSY while the request is queued or running, GPE_EINVAL
+ * for an unknown id. */
+gpe_status gpe_server_release(gpe_server *srv, uint64_t id);
 /* Block until no request is queued or running. */
 gpe_status gpe_server_wait_idle(gpe_server *srv);
 

@@ -324,8 +324,9 @@ gpe_status set_potential(gpe_ctx *c, const double *V_host, const gpe_harmonic *V
 
 // Read-only observation passes: per axis a forward transform with the
 // kinetic-weight sum; the first also takes the real-space sums.  scale (device,
-// nullable) multiplies the state on the fly.  Fills sums[0..3*kRedSlots).
-gpe_status observe_sums(gpe_ctx *c, const double *scale, double host[3][gpe::kRedSlots]) {
+// nullable) multiplies the state on the fly.  Enqueues the finalized sums,
+// 3 x kRedSlots doubles, at sums_dev (device); no host wait.
+gpe_status enqueue_observe(gpe_ctx *c, const double *scale, double *sums_dev) {
   for (int i = 0; i < n_axes(c); ++i) {
     const int ax = order_axis(c, i);
     gpe::PassArgs a = base_args(c, ax);
@@ -338,22 +339,18 @@ gpe_status observe_sums(gpe_ctx *c, const double *scale, double host[3][gpe::kRe
     gpe_status st = launch_pass(c, a);
     if (st != GPE_OK) return st;
     const gpe::PassShape sh = gpe::pass_shape(c->prec, c->n3, ax, c->wreq[ax]);
-    HIPCHK(c, gpe::launch_finalize(a.partial, sh.blocks, c->sums + i * gpe::kRedSlots,
+    HIPCHK(c, gpe::launch_finalize(a.partial, sh.blocks, sums_dev + i * gpe::kRedSlots,
                                    nullptr, 0, 1, c->stream), "finalize launch");
   }
-  std::vector<double> h(3 * gpe::kRedSlots, 0.0);
-  HIPCHK(c, hipMemcpyAsync(h.data(), c->sums, 3 * gpe::kRedSlots * sizeof(double),
-                           hipMemcpyDeviceToHost, c->stream), "sums download");
-  HIPCHK(c, hipStreamSynchronize(c->stream), "stream sync");
-  for (int i = 0; i < 3; ++i)
-    for (int k = 0; k < gpe::kRedSlots; ++k) host[i][k] = i < n_axes(c) ? h[i * gpe::kRedSlots + k] : 0;
   return GPE_OK;
 }
 
-gpe_status compute_obs(gpe_ctx *c, const double *scale, gpe_obs *o) {
+// The observables of one record of finalized sums (3 x kRedSlots, pass order).
+gpe_status obs_from_sums(gpe_ctx *c, const double *sums, gpe_obs *o) {
   double s[3][gpe::kRedSlots];
-  gpe_status st = observe_sums(c, scale, s);
-  if (st != GPE_OK) return st;
+  for (int i = 0; i < 3; ++i)
+    for (int k = 0; k < gpe::kRedSlots; ++k)
+      s[i][k] = i < n_axes(c) ? sums[i * gpe::kRedSlots + k] : 0;
   const double *r = &s[0][gpe::kSlotReal];
   double kin = 0;
   for (int i = 0; i < n_axes(c); ++i) kin += s[i][gpe::kSlotKin];
@@ -379,6 +376,16 @@ gpe_status compute_obs(gpe_ctx *c, const double *scale, gpe_obs *o) {
   bool finite = std::isfinite(out.norm) && std::isfinite(out.energy) && std::isfinite(r2);
   if (!finite) return fail(c, GPE_ENONFINITE, "observables are not finite");
   return GPE_OK;
+}
+
+gpe_status compute_obs(gpe_ctx *c, const double *scale, gpe_obs *o) {
+  gpe_status st = enqueue_observe(c, scale, c->sums);
+  if (st != GPE_OK) return st;
+  std::vector<double> h(3 * gpe::kRedSlots, 0.0);
+  HIPCHK(c, hipMemcpyAsync(h.data(), c->sums, 3 * gpe::kRedSlots * sizeof(double),
+                           hipMemcpyDeviceToHost, c->stream), "sums download");
+  HIPCHK(c, hipStreamSynchronize(c->stream), "stream sync");
+  return obs_from_sums(c, h.data(), o);
 }
 
 bool equal_lengths(const gpe_ctx *c) {
@@ -717,6 +724,47 @@ gpe_status gpe_evolve(gpe_ctx *c, double dt, int64_t nsteps) {
     }
   }
   return GPE_OK;
+}
+
+gpe_status gpe_evolve_record(gpe_ctx *c, double dt, int64_t nsteps, int32_t every,
+                             gpe_obs *series, int64_t capacity, int64_t *count) {
+  if (!c) return GPE_EINVAL;
+  if (!series || !count) return fail(c, GPE_EINVAL, "series or count is NULL");
+  if (every < 1) return fail(c, GPE_EINVAL, "every must be >= 1");
+  if (nsteps < 0) return fail(c, GPE_EINVAL, "nsteps must be >= 0");
+  const int64_t need = (nsteps + every - 1) / every;
+  *count = 0;
+  if (capacity < need) return fail(c, GPE_EINVAL, "series capacity is below ceil(nsteps/every)");
+  if (need == 0) return GPE_OK;
+  const size_t rec = 3 * gpe::kRedSlots;
+  double *dev = nullptr;
+  gpe_status st = dalloc(c, (void **)&dev, need * rec * sizeof(double), "series allocation");
+  if (st != GPE_OK) return st;
+  int64_t k = 0;
+  for (int64_t done = 0; done < nsteps && st == GPE_OK; ++k) {
+    const int64_t n = std::min<int64_t>(every, nsteps - done);
+    st = gpe_evolve(c, dt, n);
+    if (st == GPE_OK) st = enqueue_observe(c, nullptr, dev + k * rec);
+    done += n;
+  }
+  std::vector<double> h(need * rec, 0.0);
+  if (st == GPE_OK) {
+    hipError_t e = hipMemcpyAsync(h.data(), dev, h.size() * sizeof(double),
+                                  hipMemcpyDeviceToHost, c->stream);
+    if (e == hipSuccess) e = hipStreamSynchronize(c->stream);
+    if (e != hipSuccess) st = hipfail(c, e, "series download");
+  }
+  (void)hipStreamSynchronize(c->stream);
+  (void)hipFree(dev);
+  c->dev_bytes -= need * rec * sizeof(double);
+  if (st != GPE_OK) return st;
+  gpe_status first_bad = GPE_OK;
+  for (int64_t j = 0; j < need; ++j) {
+    const gpe_status sj = obs_from_sums(c, &h[j * rec], &series[j]);
+    if (sj != GPE_OK && first_bad == GPE_OK) first_bad = sj;
+  }
+  *count = need;
+  return first_bad;
 }
 
 gpe_status gpe_ground_state(gpe_ctx *c, double dt, double tol, int32_t check_every,

@@ -799,6 +799,16 @@ gpe_status gpe_server_cancel(gpe_server *s, uint64_t id) {
   return GPE_OK;
 }
 
+gpe_status gpe_server_release(gpe_server *s, uint64_t id) {
+  if (!s) return GPE_EINVAL;
+  std::lock_guard<std::mutex> lk(s->mu);
+  auto it = s->reqs.find(id);
+  if (it == s->reqs.end()) return GPE_EINVAL;
+  if (it->second->state != RQ_DONE) return GPE_EBUSY;
+  s->reqs.erase(it);
+  return GPE_OK;
+}
+
 gpe_status gpe_server_wait_idle(gpe_server *s) {
   if (!s) return GPE_EINVAL;
   std::unique_lock<std::mutex> lk(s->mu);

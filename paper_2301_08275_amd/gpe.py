@@ -114,6 +114,8 @@ SIGNATURES = {
     "gpe_get_state_device": (_I32, [_P, _P, _I32]),
     "gpe_evolve": (_I32, [_P, _D, _I64]),
     "gpe_ground_state": (_I32, [_P, _D, _D, _I32, _I64, ctypes.POINTER(_I64), _DP]),
+    "gpe_evolve_record": (_I32, [_P, _D, _I64, _I32, ctypes.POINTER(gpe_obs), _I64,
+                                 ctypes.POINTER(_I64)]),
     "gpe_observables": (_I32, [_P, ctypes.POINTER(gpe_obs), ctypes.POINTER(gpe_spectra)]),
     "gpe_spectra_bins": (_I32, [_P]),
     "gpe_transform": (_I32, [_P, _I32, _I32]),
@@ -128,6 +130,7 @@ SIGNATURES = {
     "gpe_server_poll": (_I32, [_P, ctypes.c_uint64, ctypes.POINTER(gpe_result), _DP]),
     "gpe_server_cancel": (_I32, [_P, ctypes.c_uint64]),
     "gpe_server_wait_idle": (_I32, [_P]),
+    "gpe_server_release": (_I32, [_P, ctypes.c_uint64]),
     "gpe_server_stats_read": (_I32, [_P, ctypes.POINTER(gpe_server_stats)]),
     "gpe_server_destroy": (None, [_P]),
     "gpe_request_bytes": (_I32, [ctypes.POINTER(gpe_desc), _I32, ctypes.POINTER(ctypes.c_uint64),
@@ -295,6 +298,10 @@ def gpe_server_poll(srv, rid, out, psi_out=None):
 
 def gpe_server_cancel(srv, rid):
     return load_library().gpe_server_cancel(srv, int(rid))
+
+
+def gpe_server_release(srv, rid):
+    return load_library().gpe_server_release(srv, ctypes.c_uint64(rid))
 
 
 def gpe_server_wait_idle(srv):
@@ -477,6 +484,18 @@ class Context:
     def evolve(self, dt, nsteps):
         gpe_evolve(self._ctx, dt, nsteps)
 
+    def evolve_record(self, dt, nsteps, every):
+        """Evolve and return the observables after every `every` steps (list of dicts)."""
+        cap = (int(nsteps) + int(every) - 1) // int(every)
+        series = (gpe_obs * max(cap, 1))()
+        count = _I64(0)
+        st = load_library().gpe_evolve_record(self._ctx, float(dt), int(nsteps), int(every),
+                                              series, cap, ctypes.byref(count))
+        _check(st, self._ctx)
+        return [dict(zip(OBS_KEYS, [o.norm, o.energy, o.mu, o.e_kin, o.e_pot, o.e_int,
+                                    o.sigma[0], o.sigma[1], o.sigma[2], o.r_rms]))
+                for o in series[:count.value]]
+
     def ground_state(self, dt, tol=1e-10, check_every=10, max_steps=1000000):
         st, steps, energy = gpe_ground_state(self._ctx, dt, tol, check_every, max_steps)
         return steps, energy, st == GPE_OK
@@ -598,6 +617,14 @@ class Server:
 
     def cancel(self, rid):
         return gpe_server_cancel(self._srv, rid)
+
+    def release(self, rid):
+        """Drop a finished request's record and stored state."""
+        st = gpe_server_release(self._srv, rid)
+        if st == GPE_OK:
+            self._keep.pop(rid, None)
+            self._shapes.pop(rid, None)
+        return st
 
     def wait_idle(self):
         gpe_server_wait_idle(self._srv)

@@ -385,3 +385,56 @@ def test_fp32s_spectra_close_to_fp64():
     for key in ("n_k", "e_comp", "e_incomp", "e_qp"):
         a, b = out["fp32s"][key], out["fp64"][key]
         assert np.linalg.norm(a - b) <= 1e-6 * np.linalg.norm(b), key
+
+
+# ------------------------------------------------ observable time series ---
+
+@pytest.mark.parametrize("nsteps,every", [(100, 10), (95, 10), (7, 20)])
+def test_evolve_record_matches_chunked_calls(nsteps, every):
+    """gpe_evolve_record equals gpe_evolve in chunks of `every` followed by
+    gpe_observables, record for record and in the final state (bitwise)."""
+    shape, lo, hi, V, psi0 = cfg0()
+    with gpe.Context(shape, lo, hi, 10.0, harmonic=[1.0, 1.0]) as ctx:
+        ctx.set_state(psi0)
+        series = ctx.evolve_record(1e-3, nsteps, every)
+        end = ctx.get_state()
+    ref, done = [], 0
+    with gpe.Context(shape, lo, hi, 10.0, harmonic=[1.0, 1.0]) as ctx:
+        ctx.set_state(psi0)
+        while done < nsteps:
+            n = min(every, nsteps - done)
+            ctx.evolve(1e-3, n)
+            ref.append(ctx.observables())
+            done += n
+        end_ref = ctx.get_state()
+    assert len(series) == len(ref) == -(-nsteps // every)
+    for a, b in zip(series, ref):
+        assert a == b
+    assert np.array_equal(end, end_ref)
+
+
+def test_evolve_record_time_series_against_oracle():
+    """The 3D anisotropic setup: sigma(t) and E(t) every 10 steps against the
+    oracle's observables of its own chunked run."""
+    shape, lo, hi = (32, 32, 32), (-6.0,) * 3, (6.0,) * 3
+    trap = [1.0, 2.0, 4.0]
+    V = I.harmonic(shape, lo, hi, trap)
+    psi = I.noisy_gaussian(shape, lo, hi, seed=12)
+    with gpe.Context(shape, lo, hi, 0.1, harmonic=trap) as ctx:
+        ctx.set_state(psi)
+        series = ctx.evolve_record(1e-3, 50, 10)
+    for rec in series:
+        psi = oracle.tssp_real(psi, lo, hi, V, 0.1, 1e-3, 10)
+        o = oracle.observables(psi, lo, hi, V, 0.1)
+        for key in ("norm", "energy", "sigma_x", "sigma_y", "sigma_z", "r_rms"):
+            assert abs(rec[key] - o[key]) <= 1e-11 * abs(o[key]), key
+
+
+def test_evolve_record_rejects_small_capacity():
+    shape, lo, hi, V, psi0 = cfg0()
+    with gpe.Context(shape, lo, hi, 10.0, harmonic=[1.0, 1.0]) as ctx:
+        obs = (gpe.gpe_obs * 2)()
+        count = gpe._I64(0)
+        st = gpe.load_library().gpe_evolve_record(ctx._ctx, 1e-3, 30, 10, obs, 2,
+                                                   gpe.ctypes.byref(count))
+        assert st == gpe.GPE_EINVAL and count.value == 0

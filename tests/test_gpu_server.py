@@ -178,3 +178,22 @@ def test_oversized_request_is_refused():
         with pytest.raises(gpe.GpeError) as e:
             srv.submit(**make_req(0, (256, 256), "real"))
         assert e.value.status == gpe.GPE_ENOMEM
+
+
+def test_release_drops_finished_records():
+    long = make_req(4, (128, 128), "real", nsteps=200000)
+    short = make_req(5, (64, 64), "real", nsteps=20)
+    with gpe.Server(max_slots=4, chunk_steps=4) as srv:
+        lid = srv.submit(**long)
+        sid = srv.submit(**short)
+        while srv.poll(sid) is None:
+            time.sleep(0.002)
+        assert srv.release(lid) == gpe.GPE_EBUSY      # still running
+        assert srv.release(sid) == gpe.GPE_OK
+        with pytest.raises(gpe.GpeError):
+            srv.poll(sid)                              # the record is gone
+        assert srv.release(sid) == gpe.GPE_EINVAL
+        srv.cancel(lid)
+        srv.wait_idle()
+        assert srv.poll(lid)["status"] == gpe.GPE_ECANCELED
+        assert srv.release(lid) == gpe.GPE_OK
