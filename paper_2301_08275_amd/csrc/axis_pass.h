@@ -455,28 +455,44 @@ __device__ __forceinline__ cx<T> apply_phase(int op, cx<T> v, double V, double g
   return {(T)(re * f), (T)(im * f)};
 }
 
-template <int NV>
+// Fixed-order block sums of NV values per thread; NT threads per block.
+// Full wavefronts add across lanes with shuffles, then wave totals in order;
+// a block smaller than a wavefront adds its threads' values in order (a
+// shuffle would read lanes that do not exist).
+template <int NV, int NT>
 __device__ __forceinline__ void block_reduce_store(double (&acc)[NV], double *out,
                                                    int slot0) {
-  __shared__ double red[16][NV];
-  const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
-  const int nw = (blockDim.x + 63) >> 6;
+  if constexpr (NT >= 64) {
+    __shared__ double red[16][NV];
+    const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+    constexpr int nw = NT / 64;
 #pragma unroll
-  for (int k = 0; k < NV; ++k) {
-    double x = acc[k];
+    for (int k = 0; k < NV; ++k) {
+      double x = acc[k];
 #pragma unroll
-    for (int o = 32; o >= 1; o >>= 1) x += __shfl_xor(x, o, 64);
-    acc[k] = x;
-  }
-  if (lane == 0) {
+      for (int o = 32; o >= 1; o >>= 1) x += __shfl_xor(x, o, 64);
+      acc[k] = x;
+    }
+    if (lane == 0) {
 #pragma unroll
-    for (int k = 0; k < NV; ++k) red[wave][k] = acc[k];
-  }
-  __syncthreads();
-  if (threadIdx.x < NV) {
-    double s = 0;
-    for (int w = 0; w < nw; ++w) s += red[w][threadIdx.x];
-    out[(long long)blockIdx.x * kRedSlots + slot0 + threadIdx.x] = s;
+      for (int k = 0; k < NV; ++k) red[wave][k] = acc[k];
+    }
+    __syncthreads();
+    if (threadIdx.x < NV) {
+      double s = 0;
+      for (int w = 0; w < nw; ++w) s += red[w][threadIdx.x];
+      out[(long long)blockIdx.x * kRedSlots + slot0 + threadIdx.x] = s;
+    }
+  } else {
+    __shared__ double red[NT][NV];
+#pragma unroll
+    for (int k = 0; k < NV; ++k) red[threadIdx.x][k] = acc[k];
+    __syncthreads();
+    if (threadIdx.x < NV) {
+      double s = 0;
+      for (int t = 0; t < NT; ++t) s += red[t][threadIdx.x];
+      out[(long long)blockIdx.x * kRedSlots + slot0 + threadIdx.x] = s;
+    }
   }
 }
 
@@ -707,7 +723,7 @@ axis_pass_kernel(const PassArgs a) {
 #pragma unroll
       for (int k = 0; k < kRedSlots; ++k) acc[k] = 0;
     }
-    block_reduce_store(acc, partial, 0);
+    block_reduce_store<kRedSlots, TPL * W>(acc, partial, 0);
   }
 }
 

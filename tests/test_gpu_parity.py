@@ -438,3 +438,23 @@ def test_evolve_record_rejects_small_capacity():
         st = gpe.load_library().gpe_evolve_record(ctx._ctx, 1e-3, 30, 10, obs, 2,
                                                    gpe.ctypes.byref(count))
         assert st == gpe.GPE_EINVAL and count.value == 0
+
+
+@pytest.mark.parametrize("shape", [(8, 16, 32), (16, 8, 64)])
+def test_reductions_with_blocks_smaller_than_a_wavefront(shape):
+    """Short strided axes run workgroups of 8-32 threads: observables and the
+    imaginary-time renormalisation sums still match the oracle."""
+    lo, hi = (-4.0,) * 3, (4.0,) * 3
+    trap = [2.0, 1.0, 1.5]
+    V = I.harmonic(shape, lo, hi, trap)
+    psi = I.noisy_gaussian(shape, lo, hi, seed=21)
+    o_ref = oracle.observables(psi, lo, hi, V, 3.0)
+    ref = oracle.tssp_imag(psi, lo, hi, V, 3.0, 1e-3, 10)
+    with gpe.Context(shape, lo, hi, 3.0, harmonic=trap) as ctx:
+        ctx.set_state(psi)
+        o = ctx.observables()
+        ctx.imag_steps(1e-3, 10)
+        got = ctx.get_state()
+    for key in ("norm", "energy", "e_kin", "sigma_x", "sigma_y", "sigma_z"):
+        assert abs(o[key] - o_ref[key]) <= 1e-12 * abs(o_ref[key]), key
+    assert rel(got, ref) < 1e-12
