@@ -248,7 +248,7 @@ gpe_status gpe_tuning_load(const char *path);
  * which solves one problem per run).  Independent solves of the problems
  * above are submitted from any host thread; a scheduler thread admits them in
  * arrival order while the HBM budget allows and a slot of their shape class
- * (dim, n, precision, box, dt) is free, and runs in rounds: each round gives
+ * (dim, n, precision, box, dt, real or imaginary time) is free, and runs in rounds: each round gives
  * every shape class with running requests one chunk of batched steps (all its
  * slots in the same launches), sized so that each running request receives
  * about the same GPU time per round (1 ms), and finishes the requests that

@@ -504,7 +504,8 @@ enum PassMode : int {
   MODE_PRE_REAL = 2,       // real-time phase, forward, table, inverse
   MODE_PRE_IMAG = 3,       // scale, imaginary-time phase, forward, table, inverse
   MODE_POST_IMAG_RED = 4,  // forward, table, inverse, imaginary-time phase, norm sum
-  MODE_SLOTS = 5,          // batched shape class: operations from each block's slot
+  MODE_SLOTS_REAL = 5,     // batched real-time class: operations from each block's slot
+  MODE_SLOTS_IMAG = 6,     // batched imaginary-time class
 };
 
 // Storage type of the state in HBM, converted on load and store: the
@@ -523,7 +524,8 @@ axis_pass_kernel(const PassArgs a) {
   __shared__ T lre[PL::M > 1 ? L::size : 1], lim[PL::M > 1 ? L::size : 1];
 
   constexpr bool G = MODE == MODE_GENERIC;
-  constexpr bool SL = MODE == MODE_SLOTS;
+  constexpr bool SLI = MODE == MODE_SLOTS_IMAG;
+  constexpr bool SL = MODE == MODE_SLOTS_REAL || SLI;
   const int forward = G ? a.forward : 1;
   const int inverse = G ? a.inverse : 1;
   const int store = G ? a.store : 1;
@@ -547,8 +549,9 @@ axis_pass_kernel(const PassArgs a) {
   if constexpr (SL) {
     const int si = a.slot_map ? a.slot_map[blockIdx.y] : (int)blockIdx.y;
     const Slot &sl = a.slots[si];
-    if (sl.mode == SLOT_FREE || sl.steps_done >= sl.steps_total) return;
-    const bool im = sl.mode == SLOT_IMAG;
+    const int step = sl.steps_done + a.slot_step;
+    if (sl.mode == SLOT_FREE || step >= sl.steps_total) return;
+    constexpr bool im = SLI;
     const bool first = a.slot_pass & SLOT_PASS_FIRST, last = a.slot_pass & SLOT_PASS_LAST;
     psrc = sl.psi;
     pdst = sl.psi;
@@ -559,11 +562,10 @@ axis_pass_kernel(const PassArgs a) {
     hv[2] = sl.hv[2];
     vkind = (hv[0] != 0 || hv[1] != 0 || hv[2] != 0) ? V_HARMONIC : V_NONE;
     pre = first ? (im ? PH_IMAG : PH_REAL) : PH_NONE;
-    tau_pre = (im || sl.steps_done == 0) ? 0.5 * a.dt : a.dt;
+    tau_pre = (im || step == 0) ? 0.5 * a.dt : a.dt;
     has_scale = first && im;
     pscale = &sl.scale;
-    post = last ? ((im || sl.steps_done == sl.steps_total - 1) ? (im ? PH_IMAG : PH_REAL)
-                                                               : PH_NONE)
+    post = last ? ((im || step == sl.steps_total - 1) ? (im ? PH_IMAG : PH_REAL) : PH_NONE)
                 : PH_NONE;
     tau_post = 0.5 * a.dt;
     red = (last && im) ? RED_NORM_OUT : RED_NONE;
@@ -761,9 +763,13 @@ void launch_mode(const PassArgs &a, int mode, dim3 grid, dim3 block, hipStream_t
       hipLaunchKernelGGL((axis_pass_kernel<T, PL, W, STRIDED, MODE_POST_IMAG_RED, SX>), grid,
                          block, 0, s, a);
       break;
-    case MODE_SLOTS:
-      hipLaunchKernelGGL((axis_pass_kernel<T, PL, W, STRIDED, MODE_SLOTS, SX>), grid, block, 0, s,
-                         a);
+    case MODE_SLOTS_REAL:
+      hipLaunchKernelGGL((axis_pass_kernel<T, PL, W, STRIDED, MODE_SLOTS_REAL, SX>), grid, block,
+                         0, s, a);
+      break;
+    case MODE_SLOTS_IMAG:
+      hipLaunchKernelGGL((axis_pass_kernel<T, PL, W, STRIDED, MODE_SLOTS_IMAG, SX>), grid, block,
+                         0, s, a);
       break;
     default:
       hipLaunchKernelGGL((axis_pass_kernel<T, PL, W, STRIDED, MODE_GENERIC, SX>), grid, block, 0,

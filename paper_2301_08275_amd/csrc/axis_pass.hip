@@ -27,7 +27,7 @@ namespace {
 // The specialised kernels assume full tiles and the standard hot-pass layout
 // (forward, per-frequency table, inverse, store); anything else runs generic.
 int pick_mode(const PassArgs &a, const PassShape &sh) {
-  if (a.slots) return MODE_SLOTS;
+  if (a.slots) return a.slot_imag ? MODE_SLOTS_IMAG : MODE_SLOTS_REAL;
   const bool full = sh.strided || ((long long)a.n[0] * a.n[1]) % sh.W == 0;
   if (!full || !a.forward || !a.inverse || !a.store || a.mid != MID_TABLE) return MODE_GENERIC;
   if (a.pre == PH_NONE && a.post == PH_NONE && a.red == RED_NONE && !a.scale) return MODE_PLAIN;

@@ -80,6 +80,8 @@ struct PassArgs {
   const int *slot_map;  // grid row -> slot index (null: row = slot)
   int nslots;           // grid rows (blockIdx.y) of a batched launch
   int slot_pass;        // SLOT_PASS_FIRST | SLOT_PASS_LAST bits
+  int slot_step;        // step of this launch within the chunk: slot step = steps_done + slot_step
+  int slot_imag;        // class mode: 0 real time, 1 imaginary time
   double dt;
   const void *mtab_imag;  // imaginary-time kinetic table of the class
 };
@@ -129,10 +131,15 @@ hipError_t launch_shells(int precision, const ShellArgs &a, hipStream_t s);
 hipError_t launch_sum_columns(const double *partial, long long count, int len, double *out,
                               hipStream_t s);
 
-// After the last pass of a batched step: per slot, form the imaginary-time
-// factor from its norm partials (fixed order) and advance steps_done.
+// After the last pass of step `step` of a chunk (imaginary-time classes): per
+// slot that ran it, form the renormalisation factor from the slot's norm
+// partials in fixed order.
 hipError_t launch_slot_update(Slot *slots, int nslots, const double *partial,
-                              long long blocks_per_grid, double dV, hipStream_t s);
+                              long long blocks_per_grid, double dV, int step, hipStream_t s);
+// After a chunk of `steps` steps: steps_done of every slot advances by
+// `steps`, clamped to steps_total (slot step counts change once per chunk;
+// within a chunk a launch names its step).
+hipError_t launch_slot_advance(Slot *slots, int nslots, int steps, hipStream_t s);
 
 // On-chip batched class: one workgroup holds a whole square 2D grid in LDS
 // and runs several steps of its slot without touching HBM in between.

@@ -50,28 +50,35 @@ __global__ void scale_kernel(T *__restrict__ psi, long long n, const double *__r
 
 __global__ void set_one_kernel(double *c) { *c = 1.0; }
 
-// One workgroup per slot: fixed-order sum of the slot's norm partials into the
-// imaginary-time factor, then steps_done += 1.
+// One workgroup per slot, after the last pass of step `step` of a chunk: the
+// slots that ran that step form their renormalisation factor from their norm
+// partials, in fixed order.
 __global__ void __launch_bounds__(kFinThreads)
 slot_update_kernel(Slot *__restrict__ slots, const double *__restrict__ partial,
-                   long long blocks_per_grid, double dV) {
+                   long long blocks_per_grid, double dV, int step) {
   Slot &sl = slots[blockIdx.x];
-  if (sl.mode == SLOT_FREE || sl.steps_done >= sl.steps_total) return;
+  if (sl.mode != SLOT_IMAG || sl.steps_done + step >= sl.steps_total) return;
   __shared__ double s[kFinThreads];
   const int tid = threadIdx.x;
-  if (sl.mode == SLOT_IMAG) {
-    const double *p = partial + (long long)blockIdx.x * blocks_per_grid * kRedSlots;
-    double acc = 0;
-    for (long long i = tid; i < blocks_per_grid; i += kFinThreads) acc += p[i * kRedSlots];
-    s[tid] = acc;
+  const double *p = partial + (long long)blockIdx.x * blocks_per_grid * kRedSlots;
+  double acc = 0;
+  for (long long i = tid; i < blocks_per_grid; i += kFinThreads) acc += p[i * kRedSlots];
+  s[tid] = acc;
+  __syncthreads();
+  for (int h = kFinThreads / 2; h >= 1; h >>= 1) {
+    if (tid < h) s[tid] += s[tid + h];
     __syncthreads();
-    for (int h = kFinThreads / 2; h >= 1; h >>= 1) {
-      if (tid < h) s[tid] += s[tid + h];
-      __syncthreads();
-    }
-    if (tid == 0) sl.scale = sqrt(sl.norm_target / (dV * s[0]));
   }
-  if (tid == 0) sl.steps_done += 1;
+  if (tid == 0) sl.scale = sqrt(sl.norm_target / (dV * s[0]));
+}
+
+__global__ void slot_advance_kernel(Slot *__restrict__ slots, int nslots, int steps) {
+  for (int i = threadIdx.x; i < nslots; i += blockDim.x) {
+    Slot &sl = slots[i];
+    if (sl.mode == SLOT_FREE) continue;
+    const int next = sl.steps_done + steps;
+    sl.steps_done = next < sl.steps_total ? next : sl.steps_total;
+  }
 }
 
 __global__ void slot_write_kernel(Slot *dst, Slot value) { *dst = value; }
@@ -118,9 +125,14 @@ hipError_t launch_finalize(const double *partial, long long count, double *out,
 }
 
 hipError_t launch_slot_update(Slot *slots, int nslots, const double *partial,
-                              long long blocks_per_grid, double dV, hipStream_t s) {
+                              long long blocks_per_grid, double dV, int step, hipStream_t s) {
   hipLaunchKernelGGL(slot_update_kernel, dim3(nslots), dim3(kFinThreads), 0, s, slots, partial,
-                     blocks_per_grid, dV);
+                     blocks_per_grid, dV, step);
+  return hipGetLastError();
+}
+
+hipError_t launch_slot_advance(Slot *slots, int nslots, int steps, hipStream_t s) {
+  hipLaunchKernelGGL(slot_advance_kernel, dim3(1), dim3(256), 0, s, slots, nslots, steps);
   return hipGetLastError();
 }
 

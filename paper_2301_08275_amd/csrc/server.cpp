@@ -2,11 +2,12 @@
 //
 // One scheduler thread owns every GPU call and works in rounds.  A round
 //  1. admits queued requests in arrival order while the HBM budget allows and
-//     a slot of their shape class (dim, n, precision, box, dt) is free: the
+//     a slot of their shape class (dim, n, precision, box, dt, mode) is free: the
 //     state upload goes to a side stream while the GPU still runs the previous
 //     round, and the slot-table entry is written on the main stream after it;
 //  2. enqueues one chunk of batched steps per shape class with requests in it
-//     (the fused axis passes in slot mode, then the slot-update kernel).  Small
+//     (the fused axis passes in slot mode; imaginary-time classes add a
+//     renormalisation kernel per step; step counts advance once per chunk).  Small
 //     classes replay a captured graph over all slots, large ones launch rows
 //     for their owned slots only.  Chunks are sized from the measured GPU time
 //     per step so that every running request receives about the same GPU time
@@ -64,7 +65,7 @@ struct Req {
 };
 
 struct ClassKey {
-  int dim, n[3], prec;
+  int dim, n[3], prec, mode;
   double lo[3], hi[3], dt;
   bool operator==(const ClassKey &o) const { return std::memcmp(this, &o, sizeof(*this)) == 0; }
 };
@@ -80,6 +81,7 @@ ClassKey key_of(const gpe_request &r) {
     k.hi[j] = r.desc.hi[j];
   }
   k.dt = r.dt;
+  k.mode = r.mode;
   return k;
 }
 
@@ -213,8 +215,8 @@ ShapeClass *find_class(gpe_server *s, const ClassKey &k) {
   return nullptr;
 }
 
-// One batched step of class c on the main stream.
-gpe_status enqueue_step(gpe_server *s, ShapeClass *c) {
+// Step k of a chunk of class c on the class stream (slot step = steps_done + k).
+gpe_status enqueue_step(gpe_server *s, ShapeClass *c, int k) {
   gpe_ctx *p = c->proto;
   const int na = n_axes(p);
   const int rows = c->use_graph ? c->S : c->rows;
@@ -231,9 +233,12 @@ gpe_status enqueue_step(gpe_server *s, ShapeClass *c) {
     a.mtab = c->kreal[ax];
     a.mtab_imag = c->kimag[ax];
     a.partial = c->partial;
+    a.slot_step = k;
+    a.slot_imag = c->key.mode == 1;
     if (gpe::launch_axis_pass(p->prec, a, c->strm) != hipSuccess) return GPE_EDEVICE;
   }
-  return gpe::launch_slot_update(c->d, c->S, c->partial, c->bpg_last, p->dV, c->strm) ==
+  if (c->key.mode != 1) return GPE_OK;  // real time: nothing to renormalise
+  return gpe::launch_slot_update(c->d, c->S, c->partial, c->bpg_last, p->dV, k, c->strm) ==
                  hipSuccess
              ? GPE_OK
              : GPE_EDEVICE;
@@ -305,17 +310,20 @@ gpe_status run_chunk(gpe_server *s, ShapeClass *c, int steps) {
                                                                             : GPE_EDEVICE;
     }
     for (int k = 0; k < steps; ++k) {
-      gpe_status st = enqueue_step(s, c);
+      gpe_status st = enqueue_step(s, c, k);
       if (st != GPE_OK) return st;
     }
-    return GPE_OK;
+    return gpe::launch_slot_advance(c->d, c->S, steps, c->strm) == hipSuccess ? GPE_OK
+                                                                              : GPE_EDEVICE;
   }
   if (!c->graph) {
     hipGraph_t g = nullptr;
     if (hipStreamBeginCapture(c->strm, hipStreamCaptureModeThreadLocal) != hipSuccess)
       return GPE_EDEVICE;
     gpe_status st = GPE_OK;
-    for (int k = 0; k < s->chunk && st == GPE_OK; ++k) st = enqueue_step(s, c);
+    for (int k = 0; k < s->chunk && st == GPE_OK; ++k) st = enqueue_step(s, c, k);
+    if (st == GPE_OK && gpe::launch_slot_advance(c->d, c->S, s->chunk, c->strm) != hipSuccess)
+      st = GPE_EDEVICE;
     if (hipStreamEndCapture(c->strm, &g) != hipSuccess || st != GPE_OK) {
       if (g) (void)hipGraphDestroy(g);
       return GPE_EDEVICE;
