@@ -90,8 +90,7 @@ def run_workload(ctx, torch, steps, warmup, dt, every, spectra):
         ctx.evolve(dt, chunk)
         done += chunk
         if spectra and done % every == 0:
-            ctx.observables()
-            ctx.spectra()
+            ctx.spectra(with_obs=True)  # one call: observables and shell spectra
             nspec += 1
     e1.record(stream)
     torch.cuda.synchronize()

@@ -345,10 +345,10 @@ __device__ __forceinline__ void exchange(cx<T> *v, int t, int c, T *lre, T *lim,
 
 template <class PL, int W, bool STRIDED, typename T>
 __device__ __forceinline__ void forward_fft(cx<T> *v, int t, int c, T *lre, T *lim,
-                                            const tab_t<T> *tw) {
+                                            const tab_t<T> *tw, bool first = true) {
   stage<PL, 0, -1>(v, t, tw);
   if constexpr (PL::M > 1) {
-    exchange<PL, W, STRIDED, 0, 1>(v, t, c, lre, lim, true);
+    exchange<PL, W, STRIDED, 0, 1>(v, t, c, lre, lim, first);
     stage<PL, 1, -1>(v, t, tw);
   }
   if constexpr (PL::M > 2) {
@@ -709,7 +709,20 @@ axis_pass_kernel(const PassArgs a) {
           v[b * R0 + d] = u;
         }
     }
-    if (store && valid) {
+    if (G && a.refwd) {
+      // transform the post-op result forward along this axis (the LDS was
+      // last read by the inverse stages, so the first exchange waits)
+      forward_fft<PL, W, STRIDED>(v, t, c, lre, lim, tw, false);
+      if (store && valid) {
+#pragma unroll
+        for (int b = 0; b < E / RL; ++b)
+#pragma unroll
+          for (int d = 0; d < RL; ++d) {
+            const int f = PL::freq(PL::pos(PL::M - 1, t + TPL * b, d));
+            dst[base + f * S] = cvt<SX>(v[b * RL + d]);
+          }
+      }
+    } else if (store && valid) {
 #pragma unroll
       for (int b = 0; b < E / R0; ++b)
 #pragma unroll

@@ -412,10 +412,12 @@ int shell_count(const gpe_ctx *c) {
 }
 
 // Forward transform along every axis, src -> dst (then in place on dst).
-gpe_status forward_all(gpe_ctx *c, const void *src, void *dst) {
+// Forward transforms along every axis except view axis `skip` (-1: none).
+gpe_status forward_all(gpe_ctx *c, const void *src, void *dst, int skip = -1) {
   bool first = true;
   for (int i = 0; i < n_axes(c); ++i) {
     const int ax = order_axis(c, i);
+    if (ax == skip) continue;
     gpe::PassArgs a = base_args(c, ax);
     a.src = first ? src : dst;
     a.dst = dst;
@@ -475,9 +477,10 @@ gpe_status compute_spectra(gpe_ctx *c, gpe_spectra *spec) {
     a.mid = gpe::MID_TABLE;
     a.mtab = deriv_tab[ax];
     a.post = gpe::PH_DERIV;
+    a.refwd = 1;  // Z_j leaves this pass already transformed along axis j
     st = launch_pass(c, a);
     if (st != GPE_OK) return st;
-    st = forward_all(c, c->work[j], c->work[j]);
+    st = forward_all(c, c->work[j], c->work[j], ax);
     if (st != GPE_OK) return st;
   }
   sa.kind = 1;

@@ -62,6 +62,8 @@ struct PassArgs {
   int forward;      // 1: run forward stages on input; 0: input is a spectrum
   int inverse;      // 1: run inverse stages; 0: store the spectrum (natural order)
   int store;        // 0: read-only pass (reductions only)
+  int refwd;        // 1 (generic mode): after the post op, transform forward again along
+                    // the axis and store that spectrum (natural order)
   int pre, post, mid, red;
   double tau_pre, tau_post, g;
   int vkind;          // V_NONE, V_ARRAY (V below) or V_HARMONIC (hv below)

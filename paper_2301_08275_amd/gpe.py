@@ -510,7 +510,9 @@ class Context:
                 o.sigma[0], o.sigma[1], o.sigma[2], o.r_rms]
         return dict(zip(OBS_KEYS, vals))
 
-    def spectra(self):
+    def spectra(self, with_obs=False):
+        """Shell spectra (dict of arrays and dk); with_obs: also the observables
+        computed by the same call, as (spectra, observables)."""
         nb = gpe_spectra_bins(self._ctx)
         arrs = {k: np.zeros(nb) for k in ("n_k", "e_comp", "e_incomp", "e_qp")}
         s = gpe_spectra()
@@ -522,6 +524,9 @@ class Context:
         o = gpe_obs()
         gpe_observables(self._ctx, o, s)
         arrs["dk"] = s.dk
+        if with_obs:
+            return arrs, dict(zip(OBS_KEYS, [o.norm, o.energy, o.mu, o.e_kin, o.e_pot, o.e_int,
+                                             o.sigma[0], o.sigma[1], o.sigma[2], o.r_rms]))
         return arrs
 
     def transform(self, axes=None, inverse=False):
