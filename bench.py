@@ -153,6 +153,42 @@ def percentile(xs, q):
     return xs[lo] + (xs[hi] - xs[lo]) * (k - lo)
 
 
+def ground_state_bench(torch):
+    """The 3D ground-state setup at 256^3: imaginary time from a Gaussian until
+    |dE| < 1e-10 between checks 10 steps apart, then the trap switches to
+    isotropic and the state evolves 2000 real-time steps with sigma and E
+    recorded every 10 steps.  Wall time of each phase (device time, state
+    resident)."""
+    from paper_2301_08275_amd import gpe
+    from paper_2301_08275_amd import inputs as I
+
+    n, g = 256, 50.0
+    shape, lo, hi = (n,) * 3, (-12.0,) * 3, (12.0,) * 3
+    psi0 = I.gaussian(shape, lo, hi, widths=[1.0, 2.0, 4.0])
+    with gpe.Context(shape, lo, hi, g, harmonic=[1.0, 2.0, 4.0]) as ctx:
+        ctx.set_state(psi0)
+        ctx.synchronize()
+        t0 = time.perf_counter()
+        steps, energy, conv = ctx.ground_state(1e-3, tol=1e-10, check_every=10, max_steps=200000)
+        ctx.synchronize()
+        t1 = time.perf_counter()
+        o = ctx.observables()
+        ctx.set_potential(harmonic=[1.0, 1.0, 1.0])
+        ctx.synchronize()
+        t2 = time.perf_counter()
+        series = ctx.evolve_record(1e-3, 2000, 10)
+        t3 = time.perf_counter()
+    return {"workload": "256^3 on [-12,12)^3, trap (1, 2, 4), g = 50, dt = 1e-3",
+            "ground_state": {"steps": steps, "converged": bool(conv), "seconds": t1 - t0,
+                             "ms_per_step": (t1 - t0) * 1e3 / max(1, steps), "energy": energy,
+                             "mu": o["mu"], "sigma": [o["sigma_x"], o["sigma_y"], o["sigma_z"]]},
+            "dynamics": {"steps": 2000, "records": len(series), "seconds": t3 - t2,
+                         "ms_per_step": (t3 - t2) * 1e3 / 2000,
+                         "sigma_z_max": max(r["sigma_z"] for r in series),
+                         "energy_drift": max(abs(r["energy"] - series[0]["energy"])
+                                             for r in series) / abs(series[0]["energy"])}}
+
+
 def serving_bench(nreq, max_slots, chunk):
     """The serving mix: requests arrive on a seeded Poisson stream (mean
     200/s); continuous batching through the request server against the same
@@ -232,6 +268,8 @@ def main():
     ap.add_argument("--serving", type=int, default=64,
                     help="requests of the serving mix to run (0: skip)")
     ap.add_argument("--serving-slots", type=int, default=16)
+    ap.add_argument("--no-ground-state", action="store_true",
+                    help="skip the 256^3 ground state + trap-switch dynamics timing")
     ap.add_argument("--serving-chunk", type=int, default=16)
     args = ap.parse_args()
     if args.gpus != 1:
@@ -348,6 +386,9 @@ def main():
                              "frac": achs / HBM_PEAK_GBS,
                              "kernels": kernel_table(rs["kinds"]),
                              "tuning": tuning["fp32s"]}
+    if not args.no_ground_state:
+        log("256^3 ground state and dynamics")
+        out["ground_state_256"] = ground_state_bench(torch)
     if args.serving > 0:
         log("serving mix: %d requests" % args.serving)
         out["serving"] = serving_bench(args.serving, args.serving_slots, args.serving_chunk)
