@@ -340,7 +340,7 @@ gpe_status enqueue_observe(gpe_ctx *c, const double *scale, double *sums_dev) {
     if (st != GPE_OK) return st;
     const gpe::PassShape sh = gpe::pass_shape(c->prec, c->n3, ax, c->wreq[ax]);
     HIPCHK(c, gpe::launch_finalize(a.partial, sh.blocks, sums_dev + i * gpe::kRedSlots,
-                                   nullptr, 0, 1, c->stream), "finalize launch");
+                                   nullptr, 0, 1, c->stream, c->fin), "finalize launch");
   }
   return GPE_OK;
 }
@@ -525,7 +525,8 @@ uint64_t context_bytes(const gpe_desc &d, bool with_state) {
     if (sh.blocks > maxb) maxb = sh.blocks;
     tables += (uint64_t)n3[ax] * (16 + sizeof(double));
   }
-  return (with_state ? (uint64_t)sites * es : 0) + 3 * (uint64_t)maxb * gpe::kRedSlots * sizeof(double) +
+  return (with_state ? (uint64_t)sites * es : 0) +
+         (uint64_t)gpe::kFinBlocks * gpe::kRedSlots * sizeof(double) + 3 * (uint64_t)maxb * gpe::kRedSlots * sizeof(double) +
          4 * gpe::kRedSlots * sizeof(double) + sizeof(double) + tables;
 }
 
@@ -617,6 +618,9 @@ gpe_status create_context(const gpe_desc *desc, const double *V_host, const gpe_
   if ((st = dalloc(c, (void **)&c->sums, 4 * gpe::kRedSlots * sizeof(double),
                    "sums allocation")) != GPE_OK) return bail(st);
   if ((st = dalloc(c, (void **)&c->scale, sizeof(double), "scale allocation")) != GPE_OK)
+    return bail(st);
+  if ((st = dalloc(c, (void **)&c->fin, gpe::kFinBlocks * gpe::kRedSlots * sizeof(double),
+                   "finalize scratch allocation")) != GPE_OK)
     return bail(st);
   const double one = 1.0;
   if (hipMemcpy(c->scale, &one, sizeof(double), hipMemcpyHostToDevice) != hipSuccess)
@@ -817,7 +821,7 @@ gpe_status gpe_ground_state(gpe_ctx *c, double dt, double tol, int32_t check_eve
       if (i == na - 1) {
         const gpe::PassShape sh = gpe::pass_shape(c->prec, c->n3, ax, c->wreq[ax]);
         HIPCHK(c, gpe::launch_finalize(c->partial, sh.blocks, c->sums + 3 * gpe::kRedSlots,
-                                       c->scale, c->desc.norm_target, c->dV, c->stream),
+                                       c->scale, c->desc.norm_target, c->dV, c->stream, c->fin),
                "finalize launch");
       }
     }
@@ -938,6 +942,7 @@ void gpe_destroy(gpe_ctx *c) {
   if (c->partial) (void)hipFree(c->partial);
   if (c->sums) (void)hipFree(c->sums);
   if (c->scale) (void)hipFree(c->scale);
+  if (c->fin) (void)hipFree(c->fin);
   if (c->own_stream && c->stream) (void)hipStreamDestroy(c->stream);
   delete c;
 }

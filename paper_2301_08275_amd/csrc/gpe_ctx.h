@@ -51,6 +51,7 @@ struct gpe_ctx {
   long long partial_region = 0;  // doubles per region
   double *sums = nullptr;      // finalized sums, 4 x kRedSlots
   double *scale = nullptr;     // imaginary-time c
+  double *fin = nullptr;       // two-stage finalize scratch, kFinBlocks x kRedSlots
   void *tw[3] = {nullptr, nullptr, nullptr};  // per axis (3D view) twiddles
   double *kw[3] = {nullptr, nullptr, nullptr};  // k^2/N weights per axis
   std::map<std::pair<int, std::pair<int, double>>, void *> tables;  // (axis,(kind,dt))

@@ -105,9 +105,13 @@ hipError_t launch_axis_pass(int precision, const PassArgs &a, hipStream_t s);
 // Sum `count` partial blocks of kRedSlots doubles in fixed order into
 // out[kRedSlots] (device), optionally deriving the imaginary-time scale:
 // if scale_out != null: *scale_out = sqrt(norm_target / (dV * sum slot 0)).
+// With scratch (>= kFinBlocks * kRedSlots doubles, device) and many blocks,
+// the sum runs in two fixed-order stages (kFinBlocks workgroups over fixed
+// row ranges, then one over their results): same determinism, less latency.
+constexpr int kFinBlocks = 64;
 hipError_t launch_finalize(const double *partial, long long count, double *out,
                            double *scale_out, double norm_target, double dV,
-                           hipStream_t s);
+                           hipStream_t s, double *scratch = nullptr);
 
 // psi <- c psi (c read from device), precision 0/1; sets *c = 1 afterwards.
 hipError_t launch_scale(int precision, void *psi, long long sites, double *c,

@@ -40,6 +40,35 @@ finalize_kernel(const double *__restrict__ partial, long long count,
   if (tid == 0 && scale_out) scale_out[0] = sqrt(norm_target / (dV * s[0][0]));
 }
 
+// First stage of a two-stage finalize: workgroup b adds rows
+// [b * chunk, min(count, (b + 1) * chunk)) in fixed order.
+__global__ void __launch_bounds__(kFinThreads)
+finalize_part_kernel(const double *__restrict__ partial, long long count, long long chunk,
+                     double *__restrict__ out) {
+  __shared__ double s[kRedSlots][kFinThreads];
+  const int tid = threadIdx.x;
+  const long long lo = (long long)blockIdx.x * chunk;
+  const long long hi = lo + chunk < count ? lo + chunk : count;
+  double acc[kRedSlots];
+#pragma unroll
+  for (int k = 0; k < kRedSlots; ++k) acc[k] = 0;
+  for (long long i = lo + tid; i < hi; i += kFinThreads) {
+#pragma unroll
+    for (int k = 0; k < kRedSlots; ++k) acc[k] += partial[i * kRedSlots + k];
+  }
+#pragma unroll
+  for (int k = 0; k < kRedSlots; ++k) s[k][tid] = acc[k];
+  __syncthreads();
+  for (int h = kFinThreads / 2; h >= 1; h >>= 1) {
+    if (tid < h) {
+#pragma unroll
+      for (int k = 0; k < kRedSlots; ++k) s[k][tid] += s[k][tid + h];
+    }
+    __syncthreads();
+  }
+  if (tid < kRedSlots) out[(long long)blockIdx.x * kRedSlots + tid] = s[tid][0];
+}
+
 template <typename T>
 __global__ void scale_kernel(T *__restrict__ psi, long long n, const double *__restrict__ c) {
   const double f = *c;
@@ -118,7 +147,16 @@ unsigned grid_for(long long n, int threads) {
 
 hipError_t launch_finalize(const double *partial, long long count, double *out,
                            double *scale_out, double norm_target, double dV,
-                           hipStream_t s) {
+                           hipStream_t s, double *scratch) {
+  if (scratch && count > 4 * kFinThreads) {
+    const long long chunk = (count + kFinBlocks - 1) / kFinBlocks;
+    const int blocks = (int)((count + chunk - 1) / chunk);
+    hipLaunchKernelGGL(finalize_part_kernel, dim3(blocks), dim3(kFinThreads), 0, s, partial,
+                       count, chunk, scratch);
+    hipLaunchKernelGGL(finalize_kernel, dim3(1), dim3(kFinThreads), 0, s, scratch,
+                       (long long)blocks, out, scale_out, norm_target, dV);
+    return hipGetLastError();
+  }
   hipLaunchKernelGGL(finalize_kernel, dim3(1), dim3(kFinThreads), 0, s, partial, count,
                      out, scale_out, norm_target, dV);
   return hipGetLastError();
