@@ -44,3 +44,13 @@ def test_missing_library_fails_loudly(tmp_path):
             gpe.load_library(str(tmp_path / "nope.so"))
         finally:
             gpe._lib = gpe._lib_saved
+
+
+def test_header_is_plain_c(tmp_path):
+    """include/gpe.h compiles as C99 (the boundary is a C ABI, not C++)."""
+    import subprocess
+
+    src = os.path.join(ROOT, "tests", "c", "abi_demo.c")
+    r = subprocess.run(["gcc", "-std=c99", "-Wall", "-Wextra", "-Werror", "-fsyntax-only",
+                        "-I", os.path.join(ROOT, "include"), src], capture_output=True, text=True)
+    assert r.returncode == 0, r.stderr
