@@ -220,11 +220,14 @@ typedef struct {
   int32_t width[3];       /* strided axes (all but the last): columns per workgroup, 8 or 16 */
   int32_t xcd_remap[3];   /* strided axes: 1 = each XCD takes a contiguous run of tiles */
   int32_t pass_order[3];  /* the axes (0 = slowest) in the order a step visits them */
+  int32_t plan[3];        /* radix plan per axis: 0 default; 1 the alternative (1024
+                             points only: stages 8, 8, 8, 2 with 8 points per thread
+                             instead of 16, 8, 8 with 16) */
   double ms_per_step;     /* measured real-time step (gpe_autotune), else 0 */
 } gpe_tuning;             /* entries beyond dim (and width/xcd_remap of the last axis) are 0 */
 
 /* Time the real-time step of this shape class on the current device for
- * every width and tile order of each strided axis, then for every pass order
+ * every radix plan, width and tile order of each axis, then for every pass order
  * (coordinate descent from the current entry or the defaults; `steps` timed
  * steps per candidate, the minimum of two runs), record the fastest in the
  * table and copy it to *out (nullable).  Allocates a scratch context of the

@@ -212,6 +212,11 @@ template <> struct PlanFor<128> { using type = Plan<128, 8, 8, 8, 2>; };
 template <> struct PlanFor<256> { using type = Plan<256, 8, 8, 8, 4>; };
 template <> struct PlanFor<512> { using type = Plan<512, 8, 8, 8, 8>; };
 template <> struct PlanFor<1024> { using type = Plan<1024, 16, 16, 8, 8>; };
+// Alternative plans, chosen per axis at run time (plan 1): 1024 points as four
+// stages of 8, 8, 8 and 2 with 8 points per thread -- half the registers of
+// the default, at the cost of one more LDS exchange each way.
+template <int N> struct PlanAlt { using type = typename PlanFor<N>::type; };
+template <> struct PlanAlt<1024> { using type = Plan<1024, 8, 8, 8, 8, 2>; };
 
 // LDS layout of a tile of W lines of N points (separate re and im planes).
 // Strided tiles are rows of W columns with one padding row after every eight
@@ -742,17 +747,15 @@ axis_pass_kernel(const PassArgs a) {
   }
 }
 
-template <int N>
+template <class PL>
 constexpr int contig_lines() {
-  return PlanFor<N>::type::TPL >= GPE_CONTIG_THREADS ? 1
-                                                     : GPE_CONTIG_THREADS / PlanFor<N>::type::TPL;
+  return PL::TPL >= GPE_CONTIG_THREADS ? 1 : GPE_CONTIG_THREADS / PL::TPL;
 }
 
 // Columns per workgroup for a strided axis: the requested width, halved until
 // the N x W tile (two planes plus padding) fits the 160 KiB of LDS and the
-// workgroup has at most 1024 threads.
-__host__ __device__ constexpr int fit_w(int N, int esize, int W) {
-  const int tpl = N <= 512 ? N / 8 : N / 16;
+// workgroup (tpl threads per line) has at most 1024 threads.
+__host__ __device__ constexpr int fit_w(int N, int esize, int W, int tpl) {
   while (W > 8 && (W * (N + N / 8) * esize > 160 * 1024 || tpl * W > 1024)) W /= 2;
   return W;
 }
@@ -790,13 +793,12 @@ void launch_mode(const PassArgs &a, int mode, dim3 grid, dim3 block, hipStream_t
   }
 }
 
-template <typename T, int N, typename SX>
-hipError_t launch_n(const PassArgs &a, const PassShape &sh, int mode, hipStream_t s) {
-  using PL = typename PlanFor<N>::type;
+template <typename T, int N, typename SX, class PL>
+hipError_t launch_np(const PassArgs &a, const PassShape &sh, int mode, hipStream_t s) {
   const dim3 grid((unsigned)sh.blocks, (unsigned)(a.slots ? a.nslots : 1)), block((unsigned)sh.threads);
-  constexpr int W16 = fit_w(N, (int)(2 * sizeof(T)), 16);
+  constexpr int W16 = fit_w(N, (int)(2 * sizeof(T)), 16, PL::TPL);
   if (!sh.strided) {
-    launch_mode<T, PL, contig_lines<N>(), false, SX>(a, mode, grid, block, s);
+    launch_mode<T, PL, contig_lines<PL>(), false, SX>(a, mode, grid, block, s);
   } else if (sh.W == 8) {
     launch_mode<T, PL, 8, true, SX>(a, mode, grid, block, s);
   } else if (sh.W == 16 && W16 == 16) {
@@ -805,6 +807,14 @@ hipError_t launch_n(const PassArgs &a, const PassShape &sh, int mode, hipStream_
     return hipErrorInvalidValue;
   }
   return hipGetLastError();
+}
+
+template <typename T, int N, typename SX>
+hipError_t launch_n(const PassArgs &a, const PassShape &sh, int mode, hipStream_t s) {
+  if constexpr (N == 1024) {
+    if (a.plan == 1) return launch_np<T, N, SX, typename PlanAlt<N>::type>(a, sh, mode, s);
+  }
+  return launch_np<T, N, SX, typename PlanFor<N>::type>(a, sh, mode, s);
 }
 
 template <typename T, typename SX = T>
@@ -822,7 +832,7 @@ hipError_t launch_t(const PassArgs &a, const PassShape &sh, int mode, hipStream_
   }
 }
 
-int tpl_of(int N);
+int tpl_of(int N, int plan);
 
 }  // namespace pass
 }  // namespace gpe

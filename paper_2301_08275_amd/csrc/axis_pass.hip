@@ -8,7 +8,8 @@ hipError_t launch_f64(const PassArgs &a, const PassShape &sh, int mode, hipStrea
 hipError_t launch_f32(const PassArgs &a, const PassShape &sh, int mode, hipStream_t s);
 hipError_t launch_s32(const PassArgs &a, const PassShape &sh, int mode, hipStream_t s);
 
-int tpl_of(int N) {
+int tpl_of(int N, int plan) {
+  if (plan == 1 && N == 1024) return PlanAlt<1024>::type::TPL;
   switch (N) {
     case 8: return PlanFor<8>::type::TPL;
     case 16: return PlanFor<16>::type::TPL;
@@ -41,12 +42,12 @@ int pick_mode(const PassArgs &a, const PassShape &sh) {
 }  // namespace
 }  // namespace pass
 
-PassShape pass_shape(int precision, const int n[3], int axis, int wreq) {
+PassShape pass_shape(int precision, const int n[3], int axis, int wreq, int plan) {
   using namespace pass;
   PassShape sh{};
   sh.N = n[axis];
   sh.strided = axis != 2;
-  const int tpl = tpl_of(sh.N);
+  const int tpl = tpl_of(sh.N, plan);
   if (tpl == 0) return sh;
   if (!sh.strided) {
     sh.W = tpl >= GPE_CONTIG_THREADS ? 1 : GPE_CONTIG_THREADS / tpl;
@@ -55,7 +56,7 @@ PassShape pass_shape(int precision, const int n[3], int axis, int wreq) {
     sh.blocks = (lines + sh.W - 1) / sh.W;
   } else {
     const int want = wreq == 16 ? 16 : 8;
-    const int ws = fit_w(sh.N, math_f32(precision) ? 8 : 16, want);
+    const int ws = fit_w(sh.N, math_f32(precision) ? 8 : 16, want, tpl);
     sh.W = n[2] >= ws ? ws : 8;
     sh.threads = tpl * sh.W;
     const long long outer = axis == 1 ? n[0] : n[1];
@@ -65,7 +66,7 @@ PassShape pass_shape(int precision, const int n[3], int axis, int wreq) {
 }
 
 hipError_t launch_axis_pass(int precision, const PassArgs &a, hipStream_t s) {
-  const PassShape sh = pass_shape(precision, a.n, a.axis, a.wreq);
+  const PassShape sh = pass_shape(precision, a.n, a.axis, a.wreq, a.plan);
   if (sh.threads == 0 || (sh.strided && a.n[2] < sh.W)) return hipErrorInvalidValue;
   const int mode = pass::pick_mode(a, sh);
   if (precision == 1) return pass::launch_f32(a, sh, mode, s);

@@ -164,6 +164,7 @@ gpe::PassArgs base_args(gpe_ctx *c, int vaxis) {
   }
   a.axis = vaxis;
   a.wreq = c->wreq[vaxis];
+  a.plan = c->plan[vaxis];
   a.xcd_remap = (vaxis != 2 && c->xcd_remap[vaxis]) ? 1 : 0;
   a.vkind = c->V ? gpe::V_ARRAY
                  : ((c->hv[0] != 0 || c->hv[1] != 0 || c->hv[2] != 0) ? gpe::V_HARMONIC
@@ -338,7 +339,7 @@ gpe_status enqueue_observe(gpe_ctx *c, const double *scale, double *sums_dev) {
     a.partial = c->partial + i * c->partial_region;
     gpe_status st = launch_pass(c, a);
     if (st != GPE_OK) return st;
-    const gpe::PassShape sh = gpe::pass_shape(c->prec, c->n3, ax, c->wreq[ax]);
+    const gpe::PassShape sh = gpe::pass_shape(c->prec, c->n3, ax, c->wreq[ax], c->plan[ax]);
     HIPCHK(c, gpe::launch_finalize(a.partial, sh.blocks, sums_dev + i * gpe::kRedSlots,
                                    nullptr, 0, 1, c->stream, c->fin), "finalize launch");
   }
@@ -516,12 +517,12 @@ uint64_t context_bytes(const gpe_desc &d, bool with_state) {
     sites *= d.n[j];
   }
   const uint64_t es = gpe::state_f32(d.precision) ? 8 : 16;
-  int wdef[3], xcd[3], order[3];
-  effective_tuning(d, wdef, xcd, order);
+  int wdef[3], xcd[3], order[3], plan[3];
+  effective_tuning(d, wdef, xcd, order, plan);
   long long maxb = 1;
   uint64_t tables = 0;
   for (int ax = off; ax < 3; ++ax) {
-    const gpe::PassShape sh = gpe::pass_shape(d.precision, n3, ax, wdef[ax]);
+    const gpe::PassShape sh = gpe::pass_shape(d.precision, n3, ax, wdef[ax], plan[ax]);
     if (sh.blocks > maxb) maxb = sh.blocks;
     tables += (uint64_t)n3[ax] * (16 + sizeof(double));
   }
@@ -559,7 +560,7 @@ gpe_status create_context(const gpe_desc *desc, const double *V_host, const gpe_
   c->dim = desc->dim;
   c->prec = desc->precision;
   c->esize = gpe::state_f32(c->prec) ? 8 : 16;
-  effective_tuning(*desc, c->wreq, c->xcd_remap, c->pass_order);
+  effective_tuning(*desc, c->wreq, c->xcd_remap, c->pass_order, c->plan);
   const int off = 3 - c->dim;
   c->sites = 1;
   c->dV = 1;
@@ -609,7 +610,7 @@ gpe_status create_context(const gpe_desc *desc, const double *V_host, const gpe_
   if (const char *w = std::getenv("GPE_TUNE_XCD")) c->xcd_remap[0] = c->xcd_remap[1] = std::atoi(w);
   long long maxb = 1;
   for (int ax = 3 - c->dim; ax < 3; ++ax) {
-    const gpe::PassShape sh = gpe::pass_shape(c->prec, c->n3, ax, c->wreq[ax]);
+    const gpe::PassShape sh = gpe::pass_shape(c->prec, c->n3, ax, c->wreq[ax], c->plan[ax]);
     if (sh.blocks > maxb) maxb = sh.blocks;
   }
   c->partial_region = maxb * gpe::kRedSlots;
@@ -819,7 +820,7 @@ gpe_status gpe_ground_state(gpe_ctx *c, double dt, double tol, int32_t check_eve
       gpe_status st = launch_pass(c, a);
       if (st != GPE_OK) return st;
       if (i == na - 1) {
-        const gpe::PassShape sh = gpe::pass_shape(c->prec, c->n3, ax, c->wreq[ax]);
+        const gpe::PassShape sh = gpe::pass_shape(c->prec, c->n3, ax, c->wreq[ax], c->plan[ax]);
         HIPCHK(c, gpe::launch_finalize(c->partial, sh.blocks, c->sums + 3 * gpe::kRedSlots,
                                        c->scale, c->desc.norm_target, c->dV, c->stream, c->fin),
                "finalize launch");

@@ -72,6 +72,9 @@ struct gpe_ctx {
   // Strided passes hand each XCD a contiguous run of tiles (measured: a few
   // percent faster at 512^3 than the default round-robin order).
   int xcd_remap[3] = {1, 1, 0};
+  // Radix plan per view axis (0 default, 1 the alternative plan where one
+  // exists).
+  int plan[3] = {0, 0, 0};
 };
 
 
@@ -90,7 +93,7 @@ int view_axis(const gpe_ctx *c, int user_axis);
 gpe_status validate_desc(const gpe_desc *d, std::string &msg);
 // Launch shapes a new context of this class uses (view axes): the tuning
 // table's entry, else the defaults.
-void effective_tuning(const gpe_desc &d, int wreq[3], int xcd[3], int order[3]);
+void effective_tuning(const gpe_desc &d, int wreq[3], int xcd[3], int order[3], int plan[3]);
 // Device bytes of a context (with_state: including the state array).
 uint64_t context_bytes(const gpe_desc &d, bool with_state = true);
 // gpe_create, optionally without the state array (a holder of the tables of

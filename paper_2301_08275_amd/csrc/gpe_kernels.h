@@ -68,6 +68,7 @@ struct PassArgs {
   double tau_pre, tau_post, g;
   int vkind;          // V_NONE, V_ARRAY (V below) or V_HARMONIC (hv below)
   int wreq;           // columns per workgroup requested for a strided axis (8 or 16)
+  int plan;           // radix plan of the axis (0 default, 1 alternative)
   int xcd_remap;      // strided axes: give each XCD a contiguous run of tiles
   const double *V;    // FP64 potential per site, or null
   double hv[3];       // analytic V = sum_j hv[j] x_j^2 when V is null
@@ -97,7 +98,10 @@ struct PassShape {
 };
 
 // Launch geometry the kernels are built for (must match the template choice).
-PassShape pass_shape(int precision, const int n[3], int axis, int wreq);
+// plan: 0 the default radix plan of the axis length, 1 the alternative
+// (only 1024 points has one; elsewhere 1 means 0).
+PassShape pass_shape(int precision, const int n[3], int axis, int wreq, int plan = 0);
+inline bool plan_available(int n, int plan) { return plan == 0 || (plan == 1 && n == 1024); }
 
 // Launch one axis pass; precision 0 = FP64, 1 = FP32.
 hipError_t launch_axis_pass(int precision, const PassArgs &a, hipStream_t s);

@@ -198,12 +198,12 @@ uint64_t class_bytes(const gpe_desc &d, int max_slots) {
   uint64_t ktabs = 0;
   for (int ax = off; ax < 3; ++ax) ktabs += 2 * (uint64_t)n3[ax] * 16;
   // blocks of the last pass of a step, with the launch shapes the class will use
-  int wreq[3], xcd[3], order[3];
-  effective_tuning(d, wreq, xcd, order);
+  int wreq[3], xcd[3], order[3], plan[3];
+  effective_tuning(d, wreq, xcd, order, plan);
   int last = -1;
   for (int j = 0; j < 3; ++j)
     if (order[j] >= off) last = order[j];
-  const long long bpg = gpe::pass_shape(d.precision, n3, last, wreq[last]).blocks;
+  const long long bpg = gpe::pass_shape(d.precision, n3, last, wreq[last], plan[last]).blocks;
   return context_bytes(d, false) + ktabs +
          (uint64_t)max_slots * (sizeof(gpe::Slot) + sizeof(int)) +
          (uint64_t)max_slots * bpg * gpe::kRedSlots * sizeof(double);
@@ -360,7 +360,7 @@ gpe_status create_class(gpe_server *s, const gpe_request &r, ShapeClass **out) {
     }
   }
   const int last = order_axis(p, n_axes(p) - 1);
-  c->bpg_last = gpe::pass_shape(p->prec, p->n3, last, p->wreq[last]).blocks;
+  c->bpg_last = gpe::pass_shape(p->prec, p->n3, last, p->wreq[last], p->plan[last]).blocks;
   // Graph replay over all slots pays for the empty rows' dispatch, which is
   // negligible for small grids (where launch latency dominates) and not for
   // large ones.

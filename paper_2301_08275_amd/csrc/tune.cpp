@@ -1,9 +1,10 @@
 // Launch-shape tuning per shape class (gpe_autotune and gpe_tuning_* calls).
 //
-// The fused axis passes have three run-time shape choices, none of which
-// changes the arithmetic of a line: the columns per workgroup of each strided
-// axis (8 or 16, i.e. 128- or 256-byte rows in FP64), whether each XCD takes a
-// contiguous run of tiles, and the order in which a step visits the axes.
+// The fused axis passes have four run-time shape choices: the columns per
+// workgroup of each strided axis (8 or 16, i.e. 128- or 256-byte rows in
+// FP64), whether each XCD takes a contiguous run of tiles, and the order in
+// which a step visits the axes (none changes the arithmetic of a line), and
+// the radix plan of a 1024-point axis (which changes the rounding only).
 // gpe_autotune times the real-time step over these on the device for one
 // shape class (dim, n, precision) by coordinate descent and records the
 // fastest in a process-wide table; every context created afterwards for that
@@ -48,7 +49,8 @@ std::map<TuneKey, gpe_tuning> g_table;
 // Defaults (measured at 512^3 on MI355X): 256-byte rows on the slowest axis,
 // 128-byte rows on the middle one in FP64 (64-byte rows of 16 columns in FP32),
 // contiguous tile runs per XCD on the strided axes, slowest axis last.
-void defaults(const gpe_desc &d, int wreq[3], int xcd[3], int order[3]) {
+void defaults(const gpe_desc &d, int wreq[3], int xcd[3], int order[3], int plan[3]) {
+  plan[0] = plan[1] = plan[2] = 0;
   wreq[0] = 16;
   wreq[1] = d.precision == GPE_FP64 ? 8 : 16;
   wreq[2] = 8;
@@ -59,7 +61,12 @@ void defaults(const gpe_desc &d, int wreq[3], int xcd[3], int order[3]) {
   order[2] = 0;
 }
 
-bool valid_tuning(int dim, const gpe_tuning &t, std::string &msg) {
+bool valid_tuning(int dim, const int *n, const gpe_tuning &t, std::string &msg) {
+  for (int j = 0; j < dim; ++j)
+    if (!gpe::plan_available(n[j], t.plan[j])) {
+      msg = "plan 1 exists only for 1024-point axes";
+      return false;
+    }
   for (int j = 0; j < dim - 1; ++j) {
     if (t.width[j] != 8 && t.width[j] != 16) {
       msg = "width must be 8 or 16 on the strided axes";
@@ -84,9 +91,11 @@ bool valid_tuning(int dim, const gpe_tuning &t, std::string &msg) {
 
 // ABI form (user axes) to the view-axis arrays of a context (3D view: 2D
 // problems use view axes 1 and 2).
-void to_view(int dim, const gpe_tuning &t, int wreq[3], int xcd[3], int order[3]) {
+void to_view(int dim, const gpe_tuning &t, int wreq[3], int xcd[3], int order[3],
+             int plan[3]) {
   const int off = 3 - dim;
   for (int j = 0; j < dim; ++j) {
+    plan[j + off] = t.plan[j];
     if (j < dim - 1) {
       wreq[j + off] = t.width[j];
       xcd[j + off] = t.xcd_remap[j];
@@ -98,10 +107,12 @@ void to_view(int dim, const gpe_tuning &t, int wreq[3], int xcd[3], int order[3]
   for (int ax = 0; ax < off; ++ax) order[k++] = ax;
 }
 
-void from_view(int dim, const int wreq[3], const int xcd[3], const int order[3], gpe_tuning *t) {
+void from_view(int dim, const int wreq[3], const int xcd[3], const int order[3],
+               const int plan[3], gpe_tuning *t) {
   const int off = 3 - dim;
   std::memset(t, 0, sizeof(*t));
   for (int j = 0; j < dim; ++j) {
+    t->plan[j] = plan[j + off];
     t->width[j] = j < dim - 1 ? wreq[j + off] : 0;
     t->xcd_remap[j] = j < dim - 1 ? xcd[j + off] : 0;
   }
@@ -238,11 +249,11 @@ double time_steps(gpe_ctx *c, int steps, hipEvent_t e0, hipEvent_t e1) {
 
 }  // namespace
 
-void effective_tuning(const gpe_desc &d, int wreq[3], int xcd[3], int order[3]) {
-  defaults(d, wreq, xcd, order);
+void effective_tuning(const gpe_desc &d, int wreq[3], int xcd[3], int order[3], int plan[3]) {
+  defaults(d, wreq, xcd, order, plan);
   std::lock_guard<std::mutex> lk(g_mu);
   auto it = g_table.find(key_of(d));
-  if (it != g_table.end()) to_view(d.dim, it->second, wreq, xcd, order);
+  if (it != g_table.end()) to_view(d.dim, it->second, wreq, xcd, order, plan);
 }
 
 }  // namespace gpe_host
@@ -255,10 +266,10 @@ gpe_status gpe_tuning_set(const gpe_desc *desc, const gpe_tuning *t) {
   std::string msg;
   gpe_status st = validate_desc(desc, msg);
   if (st != GPE_OK) return st;
-  if (!t || !valid_tuning(desc->dim, *t, msg)) return GPE_EINVAL;
+  if (!t || !valid_tuning(desc->dim, desc->n, *t, msg)) return GPE_EINVAL;
   gpe_tuning v = *t;
   for (int j = desc->dim - 1; j < 3; ++j) v.width[j] = v.xcd_remap[j] = 0;
-  for (int i = desc->dim; i < 3; ++i) v.pass_order[i] = 0;
+  for (int i = desc->dim; i < 3; ++i) v.pass_order[i] = v.plan[i] = 0;
   std::lock_guard<std::mutex> lk(g_mu);
   g_table[key_of(*desc)] = v;
   return GPE_OK;
@@ -278,9 +289,9 @@ gpe_status gpe_tuning_get(const gpe_desc *desc, gpe_tuning *out, int32_t *found)
       return GPE_OK;
     }
   }
-  int w[3], x[3], o[3];
-  defaults(*desc, w, x, o);
-  from_view(desc->dim, w, x, o, out);
+  int w[3], x[3], o[3], pl[3];
+  defaults(*desc, w, x, o, pl);
+  from_view(desc->dim, w, x, o, pl, out);
   out->ms_per_step = 0;
   if (found) *found = 0;
   return GPE_OK;
@@ -309,11 +320,11 @@ gpe_status gpe_tuning_save(const char *path) {
       };
       std::snprintf(buf, sizeof(buf),
                     "%s\n    {\"dim\": %d, \"n\": %s, \"precision\": \"%s\", \"width\": %s, "
-                    "\"xcd_remap\": %s, \"pass_order\": %s, \"ms_per_step\": %.6g}",
+                    "\"xcd_remap\": %s, \"pass_order\": %s, \"plan\": %s, \"ms_per_step\": %.6g}",
                     first ? "" : ",", d, arr(k.n).c_str(),
                     k.prec == GPE_FP32 ? "fp32" : k.prec == GPE_FP32_STATE ? "fp32s" : "fp64",
                     arr(t.width).c_str(), arr(t.xcd_remap).c_str(), arr(t.pass_order).c_str(),
-                    t.ms_per_step);
+                    arr(t.plan).c_str(), t.ms_per_step);
       s += buf;
       first = false;
     }
@@ -370,7 +381,10 @@ gpe_status gpe_tuning_load(const char *path) {
     }
     desc.norm_target = 1;
     std::string msg;
-    if (validate_desc(&desc, msg) != GPE_OK || !valid_tuning(d, t, msg)) return GPE_EINVAL;
+    const JVal *pl = e.get("plan");  // optional (files written before plans existed)
+    if (pl && !int_array(pl, d, t.plan)) return GPE_EINVAL;
+    if (validate_desc(&desc, msg) != GPE_OK || !valid_tuning(d, desc.n, t, msg))
+      return GPE_EINVAL;
     t.ms_per_step = ms && ms->kind == JVal::NUM ? ms->num : 0;
     entries.emplace_back(desc, t);
   }
@@ -391,8 +405,8 @@ gpe_status gpe_autotune(const gpe_desc *desc, int32_t steps, gpe_tuning *out) {
   // run the same instructions for any state, but a zero state draws less
   // power and would time faster than real data).  The real-time step uses no
   // partial sums, so the shapes tried need no other buffers.
-  int w0[3], x0[3], o0[3];
-  effective_tuning(d, w0, x0, o0);
+  int w0[3], x0[3], o0[3], p0[3];
+  effective_tuning(d, w0, x0, o0, p0);
   if ((st = create_context(&d, nullptr, nullptr, nullptr, true, &c)) != GPE_OK) return st;
   if (gpe::launch_fill_noise(c->prec, c->psi, c->sites, c->stream) != hipSuccess) {
     gpe_destroy(c);
@@ -404,37 +418,48 @@ gpe_status gpe_autotune(const gpe_desc *desc, int32_t steps, gpe_tuning *out) {
     gpe_destroy(c);
     return GPE_EDEVICE;
   }
-  auto apply = [&](const int w[3], const int x[3], const int o[3]) {
+  auto apply = [&](const int w[3], const int x[3], const int o[3], const int p[3]) {
     for (int j = 0; j < 3; ++j) {
       c->wreq[j] = w[j];
       c->xcd_remap[j] = x[j];
       c->pass_order[j] = o[j];
+      c->plan[j] = p[j];
     }
   };
-  int bw[3], bx[3], bo[3];
+  int bw[3], bx[3], bo[3], bp[3];
   std::memcpy(bw, w0, sizeof(bw));
   std::memcpy(bx, x0, sizeof(bx));
   std::memcpy(bo, o0, sizeof(bo));
-  apply(bw, bx, bo);
+  std::memcpy(bp, p0, sizeof(bp));
+  apply(bw, bx, bo, bp);
   double best = time_steps(c, steps, e0, e1);
   const int off = 3 - d.dim;
-  // 1. per strided axis: width x tile order
-  for (int ax = off; ax < 2 && best > 0; ++ax) {
-    for (int w : {8, 16}) {
-      if (gpe::pass_shape(d.precision, c->n3, ax, w).W != w) continue;  // does not fit
-      for (int x : {0, 1}) {
-        if (w == bw[ax] && x == bx[ax]) continue;
-        int tw[3], tx[3];
-        std::memcpy(tw, bw, sizeof(tw));
-        std::memcpy(tx, bx, sizeof(tx));
-        tw[ax] = w;
-        tx[ax] = x;
-        apply(tw, tx, bo);
-        const double t = time_steps(c, steps, e0, e1);
-        if (t > 0 && t < best) {
-          best = t;
-          std::memcpy(bw, tw, sizeof(bw));
-          std::memcpy(bx, tx, sizeof(bx));
+  // 1. per axis: radix plan x width x tile order (width and tile order on the
+  // strided axes only)
+  for (int ax = off; ax < 3 && best > 0; ++ax) {
+    for (int pl : {0, 1}) {
+      if (!gpe::plan_available(c->n3[ax], pl)) continue;
+      for (int w : {8, 16}) {
+        if (ax == 2 && w != bw[ax]) continue;
+        if (ax != 2 && gpe::pass_shape(d.precision, c->n3, ax, w, pl).W != w) continue;
+        for (int x : {0, 1}) {
+          if (ax == 2 && x != bx[ax]) continue;
+          if (pl == bp[ax] && w == bw[ax] && x == bx[ax]) continue;
+          int tw[3], tx[3], tp[3];
+          std::memcpy(tw, bw, sizeof(tw));
+          std::memcpy(tx, bx, sizeof(tx));
+          std::memcpy(tp, bp, sizeof(tp));
+          tw[ax] = w;
+          tx[ax] = x;
+          tp[ax] = pl;
+          apply(tw, tx, bo, tp);
+          const double t = time_steps(c, steps, e0, e1);
+          if (t > 0 && t < best) {
+            best = t;
+            std::memcpy(bw, tw, sizeof(bw));
+            std::memcpy(bx, tx, sizeof(bx));
+            std::memcpy(bp, tp, sizeof(bp));
+          }
         }
       }
     }
@@ -450,7 +475,7 @@ gpe_status gpe_autotune(const gpe_desc *desc, int32_t steps, gpe_tuning *out) {
     for (int i = 0; i < na; ++i) to[k++] = axes[perm[i]];
     for (int ax = 0; ax < off; ++ax) to[k++] = ax;
     if (std::equal(to, to + 3, bo) || best <= 0) continue;
-    apply(bw, bx, to);
+    apply(bw, bx, to, bp);
     const double t = time_steps(c, steps, e0, e1);
     if (t > 0 && t < best) {
       best = t;
@@ -462,7 +487,7 @@ gpe_status gpe_autotune(const gpe_desc *desc, int32_t steps, gpe_tuning *out) {
   gpe_destroy(c);
   if (!(best > 0)) return GPE_EDEVICE;
   gpe_tuning t{};
-  from_view(d.dim, bw, bx, bo, &t);
+  from_view(d.dim, bw, bx, bo, bp, &t);
   t.ms_per_step = best;
   if ((st = gpe_tuning_set(&d, &t)) != GPE_OK) return st;
   if (out) *out = t;

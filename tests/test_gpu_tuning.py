@@ -99,3 +99,25 @@ def test_server_uses_the_tuned_shapes():
         out = srv.poll(rid)
     assert out["status"] == gpe.GPE_OK
     assert rel(out["psi"], ref) < 1e-12
+
+
+@pytest.mark.parametrize("prec,tol", [("fp64", 1e-13), ("fp32s", 3e-7), ("fp32", 3e-6)])
+def test_alternative_radix_plan_matches_oracle(prec, tol):
+    """1024-point axes with the alternative plan (8, 8, 8, 2; 8 points per
+    thread), contiguous and strided: transforms and a few TSSP steps against
+    the oracle."""
+    shape, lo, hi = (8, 1024, 1024), (-4.0, -10.0, -10.0), (4.0, 10.0, 10.0)
+    d = gpe.make_desc(shape, lo, hi, 2.0, prec)
+    gpe.gpe_tuning_set(d, [16, 8, 0], [1, 1, 0], [2, 1, 0], plan=[0, 1, 1])
+    x = I.noisy_gaussian(shape, lo, hi, seed=31)
+    say("plan 1 transform", prec)
+    with gpe.Context(shape, lo, hi, 2.0, precision=prec) as ctx:
+        ctx.set_state(x)
+        ctx.transform()
+        got = ctx.get_state()
+    assert rel(got, oracle.fft(x)) < tol
+    say("plan 1 steps", prec)
+    V = I.harmonic(shape, lo, hi, [1.0, 0.5, 0.5])
+    ref = oracle.tssp_real(x, lo, hi, V, 2.0, 1e-3, 3)
+    got = run(shape, lo, hi, 2.0, [1.0, 0.5, 0.5], x, 3, prec)
+    assert rel(got, ref) < max(tol, 1e-12) * 10

@@ -28,6 +28,27 @@ def test_defaults_without_entry():
     assert t2["width"] == [8, 0] and t2["pass_order"] == [1, 0]
 
 
+def test_radix_plan_only_where_an_alternative_exists():
+    d = desc((1024, 1024, 64))
+    gpe.gpe_tuning_set(d, [16, 8, 0], [1, 1, 0], [2, 1, 0], plan=[1, 0, 0])
+    t, found = gpe.gpe_tuning_get(d)
+    assert found and t["plan"] == [1, 0, 0]
+    with pytest.raises(gpe.GpeError) as e:
+        gpe.gpe_tuning_set(d, [16, 8, 0], [1, 1, 0], [2, 1, 0], plan=[0, 0, 1])  # 64 points
+    assert e.value.status == gpe.GPE_EINVAL
+    assert gpe.gpe_tuning_get(desc((512, 512, 512)))[0]["plan"] == [0, 0, 0]
+
+
+def test_files_without_plans_load(tmp_path):
+    path = tmp_path / "old.json"
+    path.write_text('{"format": "gpe-tuning-1", "classes": [{"dim": 2, "n": [64, 64], '
+                    '"precision": "fp64", "width": [16, 0], "xcd_remap": [0, 0], '
+                    '"pass_order": [0, 1], "ms_per_step": 0.01}]}')
+    gpe.gpe_tuning_load(str(path))
+    t, found = gpe.gpe_tuning_get(desc((64, 64)))
+    assert found and t["plan"] == [0, 0] and t["width"] == [16, 0]
+
+
 def test_set_get_is_per_shape_class():
     d = desc((256, 256, 256))
     gpe.gpe_tuning_set(d, [8, 16, 0], [0, 1, 0], [0, 2, 1])
@@ -56,10 +77,12 @@ def test_invalid_entries_are_rejected(width, xcd, order):
 def test_save_load_round_trip(tmp_path):
     gpe.gpe_tuning_set(desc((512, 512, 512)), [16, 8, 0], [0, 1, 0], [2, 1, 0])
     gpe.gpe_tuning_set(desc((128, 256), "fp32"), [16, 0], [1, 0], [0, 1])
+    gpe.gpe_tuning_set(desc((1024,) * 3, "fp32s"), [8, 16, 0], [1, 0, 0], [2, 1, 0],
+                       plan=[0, 0, 1])
     path = tmp_path / "tune.json"
     gpe.gpe_tuning_save(str(path))
     data = json.loads(path.read_text())
-    assert data["format"] == "gpe-tuning-1" and len(data["classes"]) == 2
+    assert data["format"] == "gpe-tuning-1" and len(data["classes"]) == 3
     gpe.gpe_tuning_clear()
     assert not gpe.gpe_tuning_get(desc((512, 512, 512)))[1]
     gpe.gpe_tuning_load(str(path))
@@ -67,6 +90,8 @@ def test_save_load_round_trip(tmp_path):
     assert found and t["xcd_remap"] == [0, 1, 0]
     t, found = gpe.gpe_tuning_get(desc((128, 256), "fp32"))
     assert found and t["width"] == [16, 0] and t["pass_order"] == [0, 1]
+    t, found = gpe.gpe_tuning_get(desc((1024,) * 3, "fp32s"))
+    assert found and t["plan"] == [0, 0, 1] and t["width"] == [8, 16, 0]
 
 
 @pytest.mark.parametrize("text", [
