@@ -16,7 +16,7 @@ import time
 # (shape, precision): the 2D/3D workload grids and the serving mix's classes
 PRECS = ("fp64", "fp32", "fp32s")
 CLASSES = [((n, n, n), p) for n in (512, 256, 128, 64) for p in PRECS]
-CLASSES += [((1024, 1024, 1024), p) for p in ("fp32", "fp32s")]
+CLASSES += [((1024, 1024, 1024), p) for p in PRECS]
 CLASSES += [((n, n), p) for n in (512, 256, 128, 64) for p in PRECS]
 
 SHIPPED = os.path.join(os.path.dirname(os.path.abspath(__file__)), "tuning_mi355x.json")
