@@ -197,3 +197,49 @@ def test_release_drops_finished_records():
         srv.wait_idle()
         assert srv.poll(lid)["status"] == gpe.GPE_ECANCELED
         assert srv.release(lid) == gpe.GPE_OK
+
+
+def test_stress_mixed_requests_with_cancellations():
+    """120 small requests of every kind (2D/3D, real/imaginary, three
+    precisions, on-chip and streaming classes), a tight budget and random
+    cancellations: every request ends with a definite status, the budget
+    holds, and the uncancelled results match the single-context path."""
+    rng = np.random.default_rng(7)
+    shapes = [(32, 32), (64, 64), (128, 128), (64, 32), (16, 16, 16), (32, 32, 16)]
+    precs = ["fp64", "fp32", "fp32s"]
+    reqs = []
+    for i in range(120):
+        shape = shapes[i % len(shapes)]
+        mode = "imag" if i % 3 == 0 else "real"
+        r = make_req(100 + i, shape, mode, precs[i % 3], nsteps=int(rng.integers(1, 60)))
+        reqs.append(r)
+    cls = {}
+    for r in reqs:
+        key = (r["shape"], r["precision"], r["mode"])
+        if key not in cls:
+            cls[key] = gpe.gpe_request_bytes(gpe.make_desc(r["shape"], -BOX, BOX, 1.0,
+                                                           r["precision"]), 4)
+    budget = sum(c for c, s in cls.values()) // 2 + 6 * max(s for c, s in cls.values())
+    say("stress: budget %d bytes" % budget)
+    with gpe.Server(budget=budget, max_slots=4, chunk_steps=4) as srv:
+        ids = [srv.submit(**r) for r in reqs]
+        cancel = set(int(k) for k in rng.choice(len(ids), size=15, replace=False))
+        for k in sorted(cancel):
+            time.sleep(0.001)
+            srv.cancel(ids[k])
+        srv.wait_idle()
+        st = srv.stats()
+        res = [srv.poll(i) for i in ids]
+        assert st["bytes_in_use"] <= budget
+    assert st["completed"] == len(reqs)
+    for k, (r, out) in enumerate(zip(reqs, res)):
+        if k in cancel:
+            assert out["status"] in (gpe.GPE_OK, gpe.GPE_ECANCELED)
+        else:
+            assert out["status"] == gpe.GPE_OK, (k, out)
+    # a sample of the uncancelled results against the single-context path
+    for k in range(0, len(reqs), 17):
+        if k in cancel or res[k]["status"] != gpe.GPE_OK:
+            continue
+        tol = {"fp64": 1e-12, "fp32": 1e-5, "fp32s": 1e-6}[reqs[k]["precision"]]
+        assert rel(res[k]["psi"], solve_alone_ctx(reqs[k])) < tol, k
