@@ -119,10 +119,20 @@ gpe_status get_table(gpe_ctx *c, int vaxis, int kind, double dt, void **out) {
     *out = it->second;
     return GPE_OK;
   }
-  if (c->tables.size() > 64) {  // bounded cache: drop everything but keep going
+  if (c->tables.size() > 64) {
+    // Bounded cache.  One operation fetches tables of a single (kind, dt) for
+    // its axes, so those are kept: the caller may hold pointers to them.
+    // Graphs of cached steps refer to tables and go too.
     HIPCHK(c, hipStreamSynchronize(c->stream), "stream sync");
-    for (auto &kv : c->tables) (void)hipFree(kv.second);
-    c->tables.clear();
+    drop_step_graphs(c);
+    for (auto t = c->tables.begin(); t != c->tables.end();) {
+      if (t->first.second == key.second) {
+        ++t;
+        continue;
+      }
+      (void)hipFree(t->second);
+      t = c->tables.erase(t);
+    }
   }
   const int N = c->n3[vaxis];
   std::vector<double> re(N), im(N);
@@ -300,6 +310,7 @@ gpe_status validate_desc(const gpe_desc *d, std::string &msg) {
 
 gpe_status set_potential(gpe_ctx *c, const double *V_host, const gpe_harmonic *V_an) {
   if (V_host && V_an) return fail(c, GPE_EINVAL, "give V_host or V_an, not both");
+  drop_step_graphs(c);  // their launches carry the old potential
   for (int j = 0; j < 3; ++j) c->hv[j] = 0;
   if (V_an) {
     for (int j = 0; j < c->dim; ++j) {
@@ -701,6 +712,63 @@ gpe_status gpe_get_state_device(gpe_ctx *c, void *dptr, int32_t dst) {
   return GPE_OK;
 }
 
+}  // extern "C"
+
+namespace gpe_host {
+
+// Small grids are launch-bound: their steady-state steps (phase N(dt) in the
+// first pass, no closing phase) replay from a graph of kGraphSteps steps.
+constexpr long long kGraphSites = 1LL << 20;
+constexpr int kGraphSteps = 32;
+constexpr size_t kMaxStepGraphs = 8;  // distinct dt values kept per context
+
+// The steady-state step graph of this context for dt (null if capture is
+// not possible on the context stream; the caller then launches directly).
+hipGraphExec_t step_graph(gpe_ctx *c, double dt, void *const K[3]) {
+  auto it = c->step_graphs.find(dt);
+  if (it != c->step_graphs.end()) return it->second;
+  if (c->step_graphs.size() >= kMaxStepGraphs) drop_step_graphs(c);
+  hipGraph_t g = nullptr;
+  hipGraphExec_t ge = nullptr;
+  if (hipStreamBeginCapture(c->stream, hipStreamCaptureModeThreadLocal) != hipSuccess) {
+    (void)hipGetLastError();
+    return nullptr;
+  }
+  bool ok = true;
+  for (int s = 0; s < kGraphSteps && ok; ++s)
+    for (int i = 0; i < n_axes(c) && ok; ++i) {
+      const int ax = order_axis(c, i);
+      gpe::PassArgs a = base_args(c, ax);
+      a.mid = gpe::MID_TABLE;
+      a.mtab = K[ax];
+      if (i == 0) {
+        a.pre = gpe::PH_REAL;
+        a.tau_pre = dt;
+      }
+      ok = gpe::launch_axis_pass(c->prec, a, c->stream) == hipSuccess;
+    }
+  const bool ended = hipStreamEndCapture(c->stream, &g) == hipSuccess;
+  if (ok && ended && g) ok = hipGraphInstantiate(&ge, g, nullptr, nullptr, 0) == hipSuccess;
+  if (g) (void)hipGraphDestroy(g);
+  if (!(ok && ended) || !ge) {
+    (void)hipGetLastError();
+    return nullptr;
+  }
+  c->step_graphs[dt] = ge;
+  return ge;
+}
+
+void drop_step_graphs(gpe_ctx *c) {
+  if (c->step_graphs.empty()) return;
+  (void)hipStreamSynchronize(c->stream);
+  for (auto &kv : c->step_graphs) (void)hipGraphExecDestroy(kv.second);
+  c->step_graphs.clear();
+}
+
+}  // namespace gpe_host
+
+extern "C" {
+
 gpe_status gpe_evolve(gpe_ctx *c, double dt, int64_t nsteps) {
   if (!c) return GPE_EINVAL;
   if (!std::isfinite(dt) || dt == 0) return fail(c, GPE_EINVAL, "dt must be finite and nonzero");
@@ -713,7 +781,24 @@ gpe_status gpe_evolve(gpe_ctx *c, double dt, int64_t nsteps) {
     gpe_status st = get_table(c, ax, TB_KREAL, dt, &K[ax]);
     if (st != GPE_OK) return st;
   }
+  // Steps 1 .. nsteps-2 are identical; on small grids whole runs of them
+  // replay from the graph (the same launches, so the same results).
+  int64_t graph_from = nsteps, graph_reps = 0;
+  if (!c->timing && c->sites <= kGraphSites && nsteps >= 2 + kGraphSteps) {
+    if (hipGraphExec_t ge = step_graph(c, dt, K)) {
+      graph_reps = (nsteps - 2) / kGraphSteps;
+      graph_from = 1;
+      (void)ge;
+    }
+  }
   for (int64_t s = 0; s < nsteps; ++s) {
+    if (s == graph_from && graph_reps > 0) {
+      hipGraphExec_t ge = c->step_graphs[dt];
+      for (int64_t r = 0; r < graph_reps; ++r)
+        HIPCHK(c, hipGraphLaunch(ge, c->stream), "step graph launch");
+      s += graph_reps * kGraphSteps - 1;
+      continue;
+    }
     for (int i = 0; i < na; ++i) {
       const int ax = order_axis(c, i);
       gpe::PassArgs a = base_args(c, ax);
@@ -929,6 +1014,7 @@ void gpe_destroy(gpe_ctx *c) {
     (void)hipEventDestroy(ev.first);
     (void)hipEventDestroy(ev.second);
   }
+  for (auto &kv : c->step_graphs) (void)hipGraphExecDestroy(kv.second);
   for (auto &kv : c->tables) (void)hipFree(kv.second);
   for (int j = 0; j < 3; ++j) {
     if (c->tw[j]) (void)hipFree(c->tw[j]);

@@ -55,6 +55,9 @@ struct gpe_ctx {
   void *tw[3] = {nullptr, nullptr, nullptr};  // per axis (3D view) twiddles
   double *kw[3] = {nullptr, nullptr, nullptr};  // k^2/N weights per axis
   std::map<std::pair<int, std::pair<int, double>>, void *> tables;  // (axis,(kind,dt))
+  // Small grids: steady-state real-time steps replayed from a HIP graph, per
+  // dt (rebuilt when the potential changes).
+  std::map<double, hipGraphExec_t> step_graphs;
   size_t dev_bytes = 0;
 
   bool timing = false;
@@ -86,6 +89,7 @@ gpe_status get_table(gpe_ctx *c, int vaxis, int kind, double dt, void **out);
 gpe::PassArgs base_args(gpe_ctx *c, int vaxis);
 gpe_status launch_pass(gpe_ctx *c, const gpe::PassArgs &a);
 gpe_status set_potential(gpe_ctx *c, const double *V_host, const gpe_harmonic *V_an);
+void drop_step_graphs(gpe_ctx *c);
 gpe_status compute_obs(gpe_ctx *c, const double *scale, gpe_obs *o);
 int n_axes(const gpe_ctx *c);
 int order_axis(const gpe_ctx *c, int i);
