@@ -716,46 +716,113 @@ gpe_status gpe_get_state_device(gpe_ctx *c, void *dptr, int32_t dst) {
 
 namespace gpe_host {
 
-// Small grids are launch-bound: their steady-state steps (phase N(dt) in the
-// first pass, no closing phase) replay from a graph of kGraphSteps steps.
+// Small grids are launch-bound: runs of identical steps replay from graphs.
 constexpr long long kGraphSites = 1LL << 20;
-constexpr int kGraphSteps = 32;
-constexpr size_t kMaxStepGraphs = 8;  // distinct dt values kept per context
+constexpr int kGraphSteps = 32;        // steps per graph unless checks set it
+constexpr size_t kMaxStepGraphs = 8;   // graphs kept per context
 
-// The steady-state step graph of this context for dt (null if capture is
-// not possible on the context stream; the caller then launches directly).
-hipGraphExec_t step_graph(gpe_ctx *c, double dt, void *const K[3]) {
-  auto it = c->step_graphs.find(dt);
+// One real-time step: phase N(tau_pre) before the first pass, the kinetic
+// factor K in every pass, and a closing phase N(dt/2) after the last pass of
+// the last step of a call.
+gpe_status real_step(gpe_ctx *c, void *const K[3], double tau_pre, double tau_post) {
+  const int na = n_axes(c);
+  for (int i = 0; i < na; ++i) {
+    const int ax = order_axis(c, i);
+    gpe::PassArgs a = base_args(c, ax);
+    a.mid = gpe::MID_TABLE;
+    a.mtab = K[ax];
+    if (i == 0) {
+      a.pre = gpe::PH_REAL;
+      a.tau_pre = tau_pre;
+    }
+    if (i == na - 1 && tau_post != 0) {
+      a.post = gpe::PH_REAL;
+      a.tau_post = tau_post;
+    }
+    gpe_status st = launch_pass(c, a);
+    if (st != GPE_OK) return st;
+  }
+  return GPE_OK;
+}
+
+// One imaginary-time step: the pending scale and N(dt/2) before the first
+// pass, N(dt/2) and the norm reduction after the last; the finalize kernel
+// turns the reduction into the next scale.
+gpe_status imag_step(gpe_ctx *c, void *const K[3], double dt) {
+  const int na = n_axes(c);
+  for (int i = 0; i < na; ++i) {
+    const int ax = order_axis(c, i);
+    gpe::PassArgs a = base_args(c, ax);
+    a.mid = gpe::MID_TABLE;
+    a.mtab = K[ax];
+    if (i == 0) {
+      a.scale = c->scale;
+      a.pre = gpe::PH_IMAG;
+      a.tau_pre = dt / 2;
+    }
+    if (i == na - 1) {
+      a.post = gpe::PH_IMAG;
+      a.tau_post = dt / 2;
+      a.red = gpe::RED_NORM_OUT;
+      a.partial = c->partial;
+    }
+    gpe_status st = launch_pass(c, a);
+    if (st != GPE_OK) return st;
+    if (i == na - 1) {
+      const gpe::PassShape sh = gpe::pass_shape(c->prec, c->n3, ax, c->wreq[ax], c->plan[ax]);
+      HIPCHK(c, gpe::launch_finalize(c->partial, sh.blocks, c->sums + 3 * gpe::kRedSlots,
+                                     c->scale, c->desc.norm_target, c->dV, c->stream, c->fin),
+             "finalize launch");
+    }
+  }
+  return GPE_OK;
+}
+
+bool graphs_allowed(const gpe_ctx *c) { return !c->timing && c->sites <= kGraphSites; }
+
+// A graph of len identical steady-state steps (real: N(dt) first, no closing
+// phase; imaginary: every step), cached per (mode, dt, len).  Null if the
+// context stream cannot be captured; the caller then launches directly.
+hipGraphExec_t step_graph(gpe_ctx *c, int mode, double dt, int len, void *const K[3]) {
+  const auto key = std::make_tuple(mode, dt, len);
+  auto it = c->step_graphs.find(key);
   if (it != c->step_graphs.end()) return it->second;
   if (c->step_graphs.size() >= kMaxStepGraphs) drop_step_graphs(c);
   hipGraph_t g = nullptr;
   hipGraphExec_t ge = nullptr;
+  const std::string err = c->err;  // a failed capture leaves no error behind
   if (hipStreamBeginCapture(c->stream, hipStreamCaptureModeThreadLocal) != hipSuccess) {
     (void)hipGetLastError();
     return nullptr;
   }
   bool ok = true;
-  for (int s = 0; s < kGraphSteps && ok; ++s)
-    for (int i = 0; i < n_axes(c) && ok; ++i) {
-      const int ax = order_axis(c, i);
-      gpe::PassArgs a = base_args(c, ax);
-      a.mid = gpe::MID_TABLE;
-      a.mtab = K[ax];
-      if (i == 0) {
-        a.pre = gpe::PH_REAL;
-        a.tau_pre = dt;
-      }
-      ok = gpe::launch_axis_pass(c->prec, a, c->stream) == hipSuccess;
-    }
+  for (int s = 0; s < len && ok; ++s)
+    ok = (mode == 0 ? real_step(c, K, dt, 0.0) : imag_step(c, K, dt)) == GPE_OK;
   const bool ended = hipStreamEndCapture(c->stream, &g) == hipSuccess;
   if (ok && ended && g) ok = hipGraphInstantiate(&ge, g, nullptr, nullptr, 0) == hipSuccess;
   if (g) (void)hipGraphDestroy(g);
   if (!(ok && ended) || !ge) {
     (void)hipGetLastError();
+    c->err = err;
     return nullptr;
   }
-  c->step_graphs[dt] = ge;
+  c->step_graphs[key] = ge;
   return ge;
+}
+
+// Run n steady-state steps: whole graphs of len steps where they fit and
+// graphs are allowed, single launches for the rest.
+gpe_status steady_steps(gpe_ctx *c, int mode, double dt, int64_t n, int len, void *const K[3]) {
+  if (graphs_allowed(c) && n >= len && len >= 2) {
+    if (hipGraphExec_t ge = step_graph(c, mode, dt, len, K)) {
+      for (; n >= len; n -= len) HIPCHK(c, hipGraphLaunch(ge, c->stream), "step graph launch");
+    }
+  }
+  for (; n > 0; --n) {
+    gpe_status st = mode == 0 ? real_step(c, K, dt, 0.0) : imag_step(c, K, dt);
+    if (st != GPE_OK) return st;
+  }
+  return GPE_OK;
 }
 
 void drop_step_graphs(gpe_ctx *c) {
@@ -774,49 +841,19 @@ gpe_status gpe_evolve(gpe_ctx *c, double dt, int64_t nsteps) {
   if (!std::isfinite(dt) || dt == 0) return fail(c, GPE_EINVAL, "dt must be finite and nonzero");
   if (nsteps < 0) return fail(c, GPE_EINVAL, "nsteps must be >= 0");
   if (nsteps == 0) return GPE_OK;
-  const int na = n_axes(c);
   void *K[3] = {nullptr, nullptr, nullptr};
-  for (int i = 0; i < na; ++i) {
+  for (int i = 0; i < n_axes(c); ++i) {
     const int ax = order_axis(c, i);
     gpe_status st = get_table(c, ax, TB_KREAL, dt, &K[ax]);
     if (st != GPE_OK) return st;
   }
-  // Steps 1 .. nsteps-2 are identical; on small grids whole runs of them
-  // replay from the graph (the same launches, so the same results).
-  int64_t graph_from = nsteps, graph_reps = 0;
-  if (!c->timing && c->sites <= kGraphSites && nsteps >= 2 + kGraphSteps) {
-    if (hipGraphExec_t ge = step_graph(c, dt, K)) {
-      graph_reps = (nsteps - 2) / kGraphSteps;
-      graph_from = 1;
-      (void)ge;
-    }
-  }
-  for (int64_t s = 0; s < nsteps; ++s) {
-    if (s == graph_from && graph_reps > 0) {
-      hipGraphExec_t ge = c->step_graphs[dt];
-      for (int64_t r = 0; r < graph_reps; ++r)
-        HIPCHK(c, hipGraphLaunch(ge, c->stream), "step graph launch");
-      s += graph_reps * kGraphSteps - 1;
-      continue;
-    }
-    for (int i = 0; i < na; ++i) {
-      const int ax = order_axis(c, i);
-      gpe::PassArgs a = base_args(c, ax);
-      a.mid = gpe::MID_TABLE;
-      a.mtab = K[ax];
-      if (i == 0) {
-        a.pre = gpe::PH_REAL;
-        a.tau_pre = s == 0 ? dt / 2 : dt;
-      }
-      if (i == na - 1 && s == nsteps - 1) {
-        a.post = gpe::PH_REAL;
-        a.tau_post = dt / 2;
-      }
-      gpe_status st = launch_pass(c, a);
-      if (st != GPE_OK) return st;
-    }
-  }
-  return GPE_OK;
+  // Adjacent half-steps of N are fused: the first step opens with N(dt/2),
+  // the others with N(dt), and the last closes with N(dt/2).
+  if (nsteps == 1) return real_step(c, K, dt / 2, dt / 2);
+  gpe_status st = real_step(c, K, dt / 2, 0.0);
+  if (st == GPE_OK) st = steady_steps(c, 0, dt, nsteps - 2, kGraphSteps, K);
+  if (st == GPE_OK) st = real_step(c, K, dt, dt / 2);
+  return st;
 }
 
 gpe_status gpe_evolve_record(gpe_ctx *c, double dt, int64_t nsteps, int32_t every,
@@ -866,9 +903,8 @@ gpe_status gpe_ground_state(gpe_ctx *c, double dt, double tol, int32_t check_eve
   if (!(std::isfinite(dt) && dt > 0)) return fail(c, GPE_EINVAL, "dt must be positive");
   if (check_every < 0 || max_steps < 0) return fail(c, GPE_EINVAL, "negative count");
   if (check_every > 0 && !(tol >= 0)) return fail(c, GPE_EINVAL, "tol must be >= 0");
-  const int na = n_axes(c);
   void *K[3] = {nullptr, nullptr, nullptr};
-  for (int i = 0; i < na; ++i) {
+  for (int i = 0; i < n_axes(c); ++i) {
     const int ax = order_axis(c, i);
     gpe_status st = get_table(c, ax, TB_KIMAG, dt, &K[ax]);
     if (st != GPE_OK) return st;
@@ -884,37 +920,19 @@ gpe_status gpe_ground_state(gpe_ctx *c, double dt, double tol, int32_t check_eve
     e_prev = o.energy;
   }
   gpe_status result = check_every > 0 ? GPE_ENOTCONV : GPE_OK;
+  // Steps between two checks are identical; on small grids they replay from
+  // a graph of check_every steps (32 without checks or when checks are rare).
+  const int len = (check_every >= 2 && check_every <= 64) ? check_every : kGraphSteps;
   int64_t s = 0;
   while (s < max_steps) {
-    for (int i = 0; i < na; ++i) {
-      const int ax = order_axis(c, i);
-      gpe::PassArgs a = base_args(c, ax);
-      a.mid = gpe::MID_TABLE;
-      a.mtab = K[ax];
-      if (i == 0) {
-        a.scale = c->scale;
-        a.pre = gpe::PH_IMAG;
-        a.tau_pre = dt / 2;
-      }
-      if (i == na - 1) {
-        a.post = gpe::PH_IMAG;
-        a.tau_post = dt / 2;
-        a.red = gpe::RED_NORM_OUT;
-        a.partial = c->partial;
-      }
-      gpe_status st = launch_pass(c, a);
-      if (st != GPE_OK) return st;
-      if (i == na - 1) {
-        const gpe::PassShape sh = gpe::pass_shape(c->prec, c->n3, ax, c->wreq[ax], c->plan[ax]);
-        HIPCHK(c, gpe::launch_finalize(c->partial, sh.blocks, c->sums + 3 * gpe::kRedSlots,
-                                       c->scale, c->desc.norm_target, c->dV, c->stream, c->fin),
-               "finalize launch");
-      }
-    }
-    ++s;
+    int64_t run = max_steps - s;
+    if (check_every > 0) run = std::min<int64_t>(run, check_every - s % check_every);
+    gpe_status st = steady_steps(c, 1, dt, run, len, K);
+    if (st != GPE_OK) return st;
+    s += run;
     if (check_every > 0 && s % check_every == 0) {
       gpe_obs o;
-      gpe_status st = compute_obs(c, c->scale, &o);
+      st = compute_obs(c, c->scale, &o);
       if (st != GPE_OK) return st;
       e_last = o.energy;
       const bool done = std::fabs(o.energy - e_prev) < tol;

@@ -5,6 +5,7 @@
 #include <hip/hip_runtime.h>
 
 #include <map>
+#include <tuple>
 #include <string>
 #include <vector>
 
@@ -55,9 +56,10 @@ struct gpe_ctx {
   void *tw[3] = {nullptr, nullptr, nullptr};  // per axis (3D view) twiddles
   double *kw[3] = {nullptr, nullptr, nullptr};  // k^2/N weights per axis
   std::map<std::pair<int, std::pair<int, double>>, void *> tables;  // (axis,(kind,dt))
-  // Small grids: steady-state real-time steps replayed from a HIP graph, per
-  // dt (rebuilt when the potential changes).
-  std::map<double, hipGraphExec_t> step_graphs;
+  // Small grids: steady-state steps replayed from HIP graphs, per
+  // (mode 0 real / 1 imaginary, dt, steps per graph); rebuilt when the
+  // potential changes.
+  std::map<std::tuple<int, double, int>, hipGraphExec_t> step_graphs;
   size_t dev_bytes = 0;
 
   bool timing = false;

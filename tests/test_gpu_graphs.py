@@ -1,5 +1,6 @@
-"""Small single-context grids replay their steady-state real-time steps from a
-HIP graph.  The graph holds the same launches as the direct path (which runs
+"""Small single-context grids replay runs of identical steps (real time
+between the opening and closing half-steps, imaginary time between two
+checks) from HIP graphs.  The graph holds the same launches as the direct path (which runs
 when per-pass timing is on), so both must give the same bits; the oracle
 checks the step itself (the 128^2 runs of the parity tests use the graph)."""
 import sys
@@ -29,19 +30,25 @@ def setup(shape, seed=3):
     return lo, hi, I.noisy_gaussian(shape, lo, hi, seed=seed, amp=0.05)
 
 
-def run(shape, calls, timing, prec="fp64", trap=None):
+def run(shape, calls, timing, prec="fp64", trap=None, with_log=False):
     lo, hi, psi0 = setup(shape)
     trap = trap or [1.0] * len(shape)
     with gpe.Context(shape, lo, hi, 20.0, precision=prec, harmonic=trap) as ctx:
         if timing:
             ctx.timing(True)
         ctx.set_state(psi0)
+        out = []
         for call in calls:
             if call[0] == "evolve":
                 ctx.evolve(call[1], call[2])
+            elif call[0] == "imag":
+                ctx.imag_steps(call[1], call[2])
+            elif call[0] == "ground":
+                out.append(ctx.ground_state(call[1], tol=call[2], check_every=call[3],
+                                            max_steps=call[4]))
             else:
                 ctx.set_potential(harmonic=call[1])
-        return ctx.get_state()
+        return (ctx.get_state(), out) if with_log else ctx.get_state()
 
 
 @pytest.mark.parametrize("prec", ["fp64", "fp32", "fp32s"])
@@ -78,3 +85,28 @@ def test_many_time_steps_and_table_eviction():
     a = run(shape, calls, timing=False)
     b = run(shape, calls, timing=True)
     assert np.array_equal(a, b)
+
+
+@pytest.mark.parametrize("prec", ["fp64", "fp32", "fp32s"])
+@pytest.mark.parametrize("shape", [(64, 64), (32, 32, 32)])
+def test_imaginary_time_graphs_are_bitwise_direct(shape, prec):
+    calls = [("imag", 1e-3, n) for n in (31, 32, 33, 65, 100, 1)]
+    calls += [("ground", 1e-3, 0.0, 10, 95), ("ground", 2e-3, 0.0, 100, 250),
+              ("ground", 1e-3, 0.0, 7, 50), ("ground", 1e-3, 1e-5, 10, 20000)]
+    say("imag graph vs direct", shape, prec)
+    a, la = run(shape, calls, timing=False, prec=prec, with_log=True)
+    b, lb = run(shape, calls, timing=True, prec=prec, with_log=True)
+    assert np.array_equal(a, b)
+    assert la == lb
+    steps, energy, ok = la[-1]
+    assert [x[0] for x in la[:3]] == [95, 250, 50] and not any(x[2] for x in la[:3])
+    assert ok and 0 < steps < 20000 and steps % 10 == 0
+
+
+def test_imaginary_time_graph_against_oracle():
+    shape = (64, 64)
+    lo, hi, psi0 = setup(shape)
+    V = I.harmonic(shape, lo, hi, [1.0, 1.0])
+    ref = oracle.tssp_imag(psi0, lo, hi, V, 20.0, 1e-3, 200)
+    got = run(shape, [("imag", 1e-3, 200)], timing=False)
+    assert rel(got, ref) < 1e-10
