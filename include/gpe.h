@@ -229,7 +229,8 @@ typedef struct {
 /* Time the real-time step of this shape class on the current device for
  * every radix plan, width and tile order of each axis, then for every pass order
  * (coordinate descent from the current entry or the defaults; `steps` timed
- * steps per candidate, the minimum of two runs), record the fastest in the
+ * steps per candidate, the minimum of three runs; a candidate must be more
+ * than 1% faster than the incumbent to replace it), record the result in the
  * table and copy it to *out (nullable).  Allocates a scratch context of the
  * class for the duration of the call.  g, box and norm_target of desc are not
  * used. */

@@ -718,7 +718,6 @@ namespace gpe_host {
 
 // Small grids are launch-bound: runs of identical steps replay from graphs.
 constexpr long long kGraphSites = 1LL << 20;
-constexpr int kGraphSteps = 32;        // steps per graph unless checks set it
 constexpr size_t kMaxStepGraphs = 8;   // graphs kept per context
 
 // One real-time step: phase N(tau_pre) before the first pass, the kinetic

@@ -92,6 +92,11 @@ gpe::PassArgs base_args(gpe_ctx *c, int vaxis);
 gpe_status launch_pass(gpe_ctx *c, const gpe::PassArgs &a);
 gpe_status set_potential(gpe_ctx *c, const double *V_host, const gpe_harmonic *V_an);
 void drop_step_graphs(gpe_ctx *c);
+// Steps per step graph unless convergence checks set the length.
+constexpr int kGraphSteps = 32;
+// n identical steady-state steps (mode 0: real time with N(dt) first and no
+// closing phase; 1: imaginary time), from graphs of len steps where allowed.
+gpe_status steady_steps(gpe_ctx *c, int mode, double dt, int64_t n, int len, void *const K[3]);
 gpe_status compute_obs(gpe_ctx *c, const double *scale, gpe_obs *o);
 int n_axes(const gpe_ctx *c);
 int order_axis(const gpe_ctx *c, int i);

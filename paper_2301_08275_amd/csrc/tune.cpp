@@ -231,12 +231,25 @@ bool int_array(const JVal *v, int n, int *out) {
 }
 
 // Time `steps` real-time steps of ctx (min over two runs), in ms per step.
+// A candidate replaces the incumbent only when it is faster by more than
+// this fraction: run-to-run noise must not move a class off its defaults.
+constexpr double kMargin = 0.01;
+
+// Best of three timed runs of the steady-state real-time step (phase N(dt)
+// and the kinetic factor; the opening and closing half-steps of a call are
+// left out: they would weigh the last pass of the order), ms per step.
 double time_steps(gpe_ctx *c, int steps, hipEvent_t e0, hipEvent_t e1) {
-  if (gpe_evolve(c, 1e-3, 2) != GPE_OK) return -1;
+  const double dt = 1e-3;
+  void *K[3] = {nullptr, nullptr, nullptr};
+  for (int i = 0; i < n_axes(c); ++i) {
+    const int ax = order_axis(c, i);
+    if (get_table(c, ax, TB_KREAL, dt, &K[ax]) != GPE_OK) return -1;
+  }
+  if (steady_steps(c, 0, dt, 2, 2, K) != GPE_OK) return -1;
   double best = -1;
-  for (int r = 0; r < 2; ++r) {
+  for (int r = 0; r < 3; ++r) {
     if (hipEventRecord(e0, c->stream) != hipSuccess) return -1;
-    if (gpe_evolve(c, 1e-3, steps) != GPE_OK) return -1;
+    if (steady_steps(c, 0, dt, steps, kGraphSteps, K) != GPE_OK) return -1;
     if (hipEventRecord(e1, c->stream) != hipSuccess || hipEventSynchronize(e1) != hipSuccess)
       return -1;
     float ms = 0;
@@ -425,6 +438,7 @@ gpe_status gpe_autotune(const gpe_desc *desc, int32_t steps, gpe_tuning *out) {
       c->pass_order[j] = o[j];
       c->plan[j] = p[j];
     }
+    drop_step_graphs(c);  // cached step graphs hold the previous shapes
   };
   int bw[3], bx[3], bo[3], bp[3];
   std::memcpy(bw, w0, sizeof(bw));
@@ -454,7 +468,7 @@ gpe_status gpe_autotune(const gpe_desc *desc, int32_t steps, gpe_tuning *out) {
           tp[ax] = pl;
           apply(tw, tx, bo, tp);
           const double t = time_steps(c, steps, e0, e1);
-          if (t > 0 && t < best) {
+          if (t > 0 && t < best * (1 - kMargin)) {
             best = t;
             std::memcpy(bw, tw, sizeof(bw));
             std::memcpy(bx, tx, sizeof(bx));
@@ -477,7 +491,7 @@ gpe_status gpe_autotune(const gpe_desc *desc, int32_t steps, gpe_tuning *out) {
     if (std::equal(to, to + 3, bo) || best <= 0) continue;
     apply(bw, bx, to, bp);
     const double t = time_steps(c, steps, e0, e1);
-    if (t > 0 && t < best) {
+    if (t > 0 && t < best * (1 - kMargin)) {
       best = t;
       std::memcpy(bo, to, sizeof(bo));
     }

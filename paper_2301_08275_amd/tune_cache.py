@@ -32,7 +32,10 @@ def main(out):
     for shape, prec in CLASSES:
         t0 = time.time()
         d = gpe.make_desc(shape, 0.0, 1.0, 1.0, prec)
-        steps = 5 if shape[0] >= 256 and len(shape) == 3 else 20
+        sites = 1
+        for n in shape:
+            sites *= n
+        steps = 4 if sites >= 1 << 30 else 10 if sites >= 1 << 24 else 64
         t = gpe.gpe_autotune(d, steps=steps)
         print("%-16s %s %s (%.1f s)" % ("x".join(map(str, shape)), prec, t, time.time() - t0),
               flush=True)
