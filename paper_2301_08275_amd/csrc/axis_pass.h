@@ -405,9 +405,22 @@ __device__ __forceinline__ double site_potential(const PassArgs &a, int vkind, c
 // in three parts (the first two with 33 significant bits, so n * part is exact
 // for |n| < 2^20), then the Taylor series of sin and cos on |r| <= pi/4 up to
 // degree 17 and 18 (truncation below 1e-19).  Arguments beyond 1e6 go to the
-// library routine.
+// library routine.  Small arguments (|x| < 2^-6: the phase of a step in a
+// weakly interacting or untrapped region) need no reduction and only the
+// series up to degree 7 and 6 (truncation below 1e-19 relative); the choice is
+// per site, so a result never depends on its neighbours.
 __device__ __forceinline__ void sincos_phase(double x, double *s, double *c) {
 #if GPE_FAST_SINCOS
+  if (fabs(x) < 0x1p-6) {
+    const double r2 = x * x;
+    double ps = fma(r2, -0.0001984126984126984, 0.008333333333333333);
+    ps = fma(ps, r2, -0.16666666666666666);
+    *s = fma(ps * r2, x, x);
+    double pc = fma(r2, -0.001388888888888889, 0.041666666666666664);
+    pc = fma(pc, r2, -0.5);
+    *c = fma(pc, r2, 1.0);
+    return;
+  }
   if (!(fabs(x) < 1.0e6)) {
     sincos(x, s, c);
     return;
