@@ -524,6 +524,9 @@ enum PassMode : int {
   MODE_POST_IMAG_RED = 4,  // forward, table, inverse, imaginary-time phase, norm sum
   MODE_SLOTS_REAL = 5,     // batched real-time class: operations from each block's slot
   MODE_SLOTS_IMAG = 6,     // batched imaginary-time class
+  MODE_FWD = 7,            // forward only, spectrum stored in natural order
+  MODE_DERIV = 8,          // forward, table, inverse, combine with the re-read
+                           // state (PH_DERIV), forward again, store
 };
 
 // Storage type of the state in HBM, converted on load and store: the
@@ -544,13 +547,16 @@ axis_pass_kernel(const PassArgs a) {
   constexpr bool G = MODE == MODE_GENERIC;
   constexpr bool SLI = MODE == MODE_SLOTS_IMAG;
   constexpr bool SL = MODE == MODE_SLOTS_REAL || SLI;
+  constexpr bool FWD = MODE == MODE_FWD, DER = MODE == MODE_DERIV;
   const int forward = G ? a.forward : 1;
-  const int inverse = G ? a.inverse : 1;
+  const int inverse = G ? a.inverse : (FWD ? 0 : 1);
   const int store = G ? a.store : 1;
   int pre = G ? a.pre
               : (MODE == MODE_PRE_REAL ? PH_REAL : MODE == MODE_PRE_IMAG ? PH_IMAG : PH_NONE);
-  int post = G ? a.post : (MODE == MODE_POST_IMAG_RED ? PH_IMAG : PH_NONE);
-  const int mid = G ? a.mid : MID_TABLE;
+  int post = G ? a.post
+               : (MODE == MODE_POST_IMAG_RED ? PH_IMAG : DER ? PH_DERIV : PH_NONE);
+  const int mid = G ? a.mid : (FWD ? MID_NONE : MID_TABLE);
+  const bool refwd = G ? a.refwd != 0 : DER;
   int red = G ? a.red : (MODE == MODE_POST_IMAG_RED ? RED_NORM_OUT : RED_NONE);
   bool has_scale = G ? a.scale != nullptr : MODE == MODE_PRE_IMAG;
   // Per-block parameters: from the arguments, or (batched) from this block's slot.
@@ -727,7 +733,7 @@ axis_pass_kernel(const PassArgs a) {
           v[b * R0 + d] = u;
         }
     }
-    if (G && a.refwd) {
+    if (refwd) {
       // transform the post-op result forward along this axis (the LDS was
       // last read by the inverse stages, so the first exchange waits)
       forward_fft<PL, W, STRIDED>(v, t, c, lre, lim, tw, false);
@@ -799,6 +805,14 @@ void launch_mode(const PassArgs &a, int mode, dim3 grid, dim3 block, hipStream_t
     case MODE_SLOTS_IMAG:
       hipLaunchKernelGGL((axis_pass_kernel<T, PL, W, STRIDED, MODE_SLOTS_IMAG, SX>), grid, block,
                          0, s, a);
+      break;
+    case MODE_FWD:
+      hipLaunchKernelGGL((axis_pass_kernel<T, PL, W, STRIDED, MODE_FWD, SX>), grid, block, 0, s,
+                         a);
+      break;
+    case MODE_DERIV:
+      hipLaunchKernelGGL((axis_pass_kernel<T, PL, W, STRIDED, MODE_DERIV, SX>), grid, block, 0, s,
+                         a);
       break;
     default:
       hipLaunchKernelGGL((axis_pass_kernel<T, PL, W, STRIDED, MODE_GENERIC, SX>), grid, block, 0,

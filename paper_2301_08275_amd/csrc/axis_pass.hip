@@ -25,12 +25,19 @@ int tpl_of(int N, int plan) {
 
 namespace {
 
-// The specialised kernels assume full tiles and the standard hot-pass layout
-// (forward, per-frequency table, inverse, store); anything else runs generic.
+// The specialised kernels assume full tiles and one of the standard pass
+// layouts (the step passes: forward, per-frequency table, inverse, store;
+// forward-only transforms; the spectral-derivative pass); anything else runs
+// generic.
 int pick_mode(const PassArgs &a, const PassShape &sh) {
   if (a.slots) return a.slot_imag ? MODE_SLOTS_IMAG : MODE_SLOTS_REAL;
   const bool full = sh.strided || ((long long)a.n[0] * a.n[1]) % sh.W == 0;
-  if (!full || !a.forward || !a.inverse || !a.store || a.mid != MID_TABLE) return MODE_GENERIC;
+  if (!full || !a.forward || !a.store) return MODE_GENERIC;
+  const bool bare = !a.scale && a.pre == PH_NONE && a.red == RED_NONE;
+  if (!a.inverse)
+    return bare && a.mid == MID_NONE && a.post == PH_NONE && !a.refwd ? MODE_FWD : MODE_GENERIC;
+  if (a.mid != MID_TABLE) return MODE_GENERIC;
+  if (a.refwd) return bare && a.post == PH_DERIV ? MODE_DERIV : MODE_GENERIC;
   if (a.pre == PH_NONE && a.post == PH_NONE && a.red == RED_NONE && !a.scale) return MODE_PLAIN;
   if (a.pre == PH_REAL && a.post == PH_NONE && a.red == RED_NONE && !a.scale) return MODE_PRE_REAL;
   if (a.pre == PH_IMAG && a.post == PH_NONE && a.red == RED_NONE && a.scale) return MODE_PRE_IMAG;

@@ -490,6 +490,9 @@ gpe_status compute_spectra(gpe_ctx *c, gpe_spectra *spec) {
     a.mtab = deriv_tab[ax];
     a.post = gpe::PH_DERIV;
     a.refwd = 1;  // Z_j leaves this pass already transformed along axis j
+    // With FP64 arithmetic this pass needs more registers than a 16-column
+    // tile of 1024 threads allows (measured: 8 columns are faster there).
+    if (!gpe::math_f32(c->prec)) a.wreq = 8;
     st = launch_pass(c, a);
     if (st != GPE_OK) return st;
     st = forward_all(c, c->work[j], c->work[j], ax);
