@@ -1,13 +1,14 @@
-// |k|-shell spectra (feature list: particle-number, compressible and
-// incompressible kinetic-energy spectra).
+// |k|-shell spectra: particle number, compressible and incompressible kinetic
+// energy, and the quantum-pressure part.
 //
 // The spectra of Z_j = u_j + i w_j (two real fields packed in one complex FFT)
 // are unpacked per wavenumber from Z_j(k) and Z_j(-k):
 //   U_j(k) = (Z_j(k) + conj(Z_j(-k))) / 2,  W_j(k) = (Z_j(k) - conj(Z_j(-k))) / (2i),
 // U is split into k (k.U)/|k|^2 (compressible) and the rest (incompressible;
 // k = 0 belongs there), and |.|^2 is summed per shell round(|k|/dk).  Each
-// workgroup keeps its histogram in LDS (FP64 atomics) and writes it out; a
-// second kernel adds the workgroup histograms in a fixed order.
+// workgroup keeps its histogram in LDS (FP64 atomics, one per run of equal
+// shells in a wavefront) and writes it out; a second kernel adds the
+// workgroup histograms in a fixed order.
 #include "gpe_kernels.h"
 
 namespace gpe {
@@ -15,79 +16,163 @@ namespace {
 
 constexpr int kShellThreads = 256;
 constexpr int kShellMaxBlocks = 1024;
+constexpr int kShellU0 = 4, kShellU1 = 2;  // sites per thread per iteration (kind 0, 1)
 
 template <typename T>
 struct alignas(2 * sizeof(T)) cxs {
   T x, y;
 };
 
-__device__ __forceinline__ long mode_of(int i, int n) { return i < n / 2 ? i : i - n; }
+__device__ __forceinline__ int mode_of(int i, int n) { return i < n / 2 ? i : i - n; }
 
-template <typename T>
+__device__ __forceinline__ int log2_of(int n) { return 31 - __clz(n); }
+
+// Inclusive sum of x over the run of equal keys that ends at this lane (runs
+// of a key are contiguous in lane order): a segmented Hillis-Steele scan.
+__device__ __forceinline__ double run_sum(double x, int key, int lane) {
+#pragma unroll
+  for (int d = 1; d < 64; d *= 2) {
+    const double y = __shfl_up(x, d, 64);
+    const int ky = __shfl_up(key, d, 64);
+    if (lane >= d && ky == key) x += y;
+  }
+  return x;
+}
+
+// Site geometry: indices, wavevector, shell and run key (see shell_kernel).
+struct ShellSite {
+  long long s, ms;
+  int i2, bin, key;
+  bool on, pairs;
+  double k[3], kk;
+};
+
+template <int KIND>
+__device__ __forceinline__ ShellSite shell_site(const ShellArgs &a, long long s, long long sites,
+                                                int l1, int l2) {
+  const int n0 = a.n[0], n1 = a.n[1], n2 = a.n[2];
+  ShellSite q;
+  q.s = s;
+  q.i2 = (int)(s & (n2 - 1));
+  const long long r = s >> l2;
+  const int i1 = (int)(r & (n1 - 1)), i0 = (int)(r >> l1);
+  // Kind 1: the decomposed energies at the mirror site (index -i) equal
+  // those at i when the mirror's wavevector is -k (u and w are transforms
+  // of real fields); that fails only on a Nyquist index (n/2 is its own
+  // mirror with the same k) of a used axis.  Such pairs count once from the
+  // half i2 <= n2/2, twice for 0 < i2 < n2/2; other sites count once.
+  q.pairs = (2 * i0 != n0 || a.kscale[0] == 0) && (2 * i1 != n1 || a.kscale[1] == 0);
+  q.on = s < sites && !(KIND != 0 && q.pairs && 2 * q.i2 > n2);
+  const int m0 = mode_of(i0, n0), m1 = mode_of(i1, n1), m2 = mode_of(q.i2, n2);
+  q.k[0] = a.kscale[0] * m0;
+  q.k[1] = a.kscale[1] * m1;
+  q.k[2] = a.kscale[2] * m2;
+  q.kk = q.k[0] * q.k[0] + q.k[1] * q.k[1] + q.k[2] * q.k[2];
+  int bin;
+  if (a.integer_shells) {
+    const long long M = (long long)m0 * m0 + (long long)m1 * m1 + (long long)m2 * m2;
+    long long t = (long long)sqrt((double)M);
+    while ((2 * t + 1) * (2 * t + 1) <= 4 * M) ++t;
+    while (t > 0 && 4 * M < (2 * t - 1) * (2 * t - 1)) --t;
+    bin = (int)t;
+  } else {
+    bin = (int)floor(sqrt(q.kk) / a.dk + 0.5);
+  }
+  q.bin = bin < a.nbins ? bin : a.nbins - 1;  // the clamp is unreachable for the shell count used
+  q.key = q.on ? (int)(((r & 0x3fff) << 13) | ((2 * q.i2 >= n2) ? 1 << 12 : 0) | q.bin) : -1;
+  q.ms = ((((long long)((n0 - i0) & (n0 - 1)) * n1 + ((n1 - i1) & (n1 - 1))) * n2) +
+          ((n2 - q.i2) & (n2 - 1)));
+  return q;
+}
+
+// Every lane of a wavefront runs the same number of iterations (the shuffles
+// need them all); a lane past the end or with nothing to add carries key -1.
+// Within a wavefront the sites are consecutive: within one row (fixed i0, i1)
+// and one half of the last axis the shell index is monotone in i2, so equal
+// bins form contiguous runs keyed by (row, half, bin); each run is summed
+// across lanes in fixed order and added to the LDS histogram by its last lane
+// (a few atomics per wavefront instead of one per site).  Each iteration
+// takes U blocks of sites and issues all their loads before any arithmetic.
+template <typename T, int KIND, int U>
 __global__ void __launch_bounds__(kShellThreads) shell_kernel(const ShellArgs a) {
   extern __shared__ double hist[];  // 4 * nbins
   const int nb = a.nbins;
   for (int i = threadIdx.x; i < 4 * nb; i += blockDim.x) hist[i] = 0;
   __syncthreads();
-  const int n0 = a.n[0], n1 = a.n[1], n2 = a.n[2];
-  const long long sites = (long long)n0 * n1 * n2;
-  const cxs<T> *f0 = static_cast<const cxs<T> *>(a.f[0]);
-  const cxs<T> *f1 = static_cast<const cxs<T> *>(a.f[1]);
-  const cxs<T> *f2 = static_cast<const cxs<T> *>(a.f[2]);
-  for (long long s = (long long)blockIdx.x * blockDim.x + threadIdx.x; s < sites;
-       s += (long long)gridDim.x * blockDim.x) {
-    const int i2 = (int)(s % n2);
-    const long long r = s / n2;
-    const int i1 = (int)(r % n1), i0 = (int)(r / n1);
-    const long m0 = mode_of(i0, n0), m1 = mode_of(i1, n1), m2 = mode_of(i2, n2);
-    const double k0 = a.kscale[0] * m0, k1 = a.kscale[1] * m1, k2 = a.kscale[2] * m2;
-    const double kk = k0 * k0 + k1 * k1 + k2 * k2;
-    int bin;
-    if (a.integer_shells) {
-      const long M = m0 * m0 + m1 * m1 + m2 * m2;
-      long q = (long)sqrt((double)M);
-      while ((2 * q + 1) * (2 * q + 1) <= 4 * M) ++q;
-      while (q > 0 && 4 * M < (2 * q - 1) * (2 * q - 1)) --q;
-      bin = (int)q;
-    } else {
-      bin = (int)floor(sqrt(kk) / a.dk + 0.5);
-    }
-    if (bin >= nb) bin = nb - 1;  // unreachable for the shell count used
-    if (a.kind == 0) {
-      const cxs<T> v = f0[s];
-      atomicAdd(&hist[bin], a.w * ((double)v.x * v.x + (double)v.y * v.y));
-    } else {
-      const long long ms = (((long long)((n0 - i0) % n0) * n1 + (n1 - i1) % n1) * n2 + (n2 - i2) % n2);
-      const double kv[3] = {k0, k1, k2};
-      const cxs<T> *fs[3] = {f0, f1, f2};
-      double ur[3] = {0, 0, 0}, ui[3] = {0, 0, 0}, qsum = 0;
+  const int l1 = log2_of(a.n[1]), l2 = log2_of(a.n[2]), n2 = a.n[2];
+  const long long sites = (long long)a.n[0] * a.n[1] * a.n[2];
+  const int lane = threadIdx.x & 63;
+  constexpr int NF = KIND == 0 ? 1 : 3;
+  const cxs<T> *fs[3] = {static_cast<const cxs<T> *>(a.f[0]),
+                         static_cast<const cxs<T> *>(a.f[1]),
+                         static_cast<const cxs<T> *>(a.f[2])};
+  const long long step = (long long)gridDim.x * blockDim.x * U;
+  for (long long s0 = (long long)blockIdx.x * blockDim.x * U; s0 < sites; s0 += step) {
+    ShellSite q[U];
+    cxs<T> zp[U][NF], zm[U][NF];
 #pragma unroll
-      for (int j = 0; j < 3; ++j) {
-        if (!fs[j]) continue;
-        const cxs<T> zp = fs[j][s], zm = fs[j][ms];
-        ur[j] = 0.5 * ((double)zp.x + (double)zm.x);
-        ui[j] = 0.5 * ((double)zp.y - (double)zm.y);
-        const double wr = 0.5 * ((double)zp.y + (double)zm.y);
-        const double wi = -0.5 * ((double)zp.x - (double)zm.x);
-        qsum += wr * wr + wi * wi;
-      }
-      double csum = 0, isum = 0;
-      if (kk > 0) {
-        const double pr = (kv[0] * ur[0] + kv[1] * ur[1] + kv[2] * ur[2]) / kk;
-        const double pi = (kv[0] * ui[0] + kv[1] * ui[1] + kv[2] * ui[2]) / kk;
+    for (int u = 0; u < U; ++u) {
+      q[u] = shell_site<KIND>(a, s0 + (long long)u * blockDim.x + threadIdx.x, sites, l1, l2);
 #pragma unroll
-        for (int j = 0; j < 3; ++j) {
-          const double cr = kv[j] * pr, ci = kv[j] * pi;
-          csum += cr * cr + ci * ci;
-          isum += (ur[j] - cr) * (ur[j] - cr) + (ui[j] - ci) * (ui[j] - ci);
+      for (int j = 0; j < NF; ++j) {
+        zp[u][j] = cxs<T>{0, 0};
+        zm[u][j] = cxs<T>{0, 0};
+        if (q[u].on && fs[j]) {
+          zp[u][j] = fs[j][q[u].s];
+          if (KIND != 0) zm[u][j] = fs[j][q[u].ms];
         }
-      } else {
-#pragma unroll
-        for (int j = 0; j < 3; ++j) isum += ur[j] * ur[j] + ui[j] * ui[j];
       }
-      atomicAdd(&hist[nb + bin], 0.5 * a.w * csum);
-      atomicAdd(&hist[2 * nb + bin], 0.5 * a.w * isum);
-      atomicAdd(&hist[3 * nb + bin], 0.5 * a.w * qsum);
+    }
+#pragma unroll
+    for (int u = 0; u < U; ++u) {
+      const int key_next = __shfl_down(q[u].key, 1, 64);
+      const bool last = q[u].on && (lane == 63 || key_next != q[u].key);
+      if constexpr (KIND == 0) {
+        const double e = run_sum(
+            a.w * ((double)zp[u][0].x * zp[u][0].x + (double)zp[u][0].y * zp[u][0].y), q[u].key,
+            lane);
+        if (last) atomicAdd(&hist[q[u].bin], e);
+      } else {
+        double csum = 0, isum = 0, qsum = 0;
+        if (q[u].on) {
+          const int i2 = q[u].i2;
+          const double wgt = (q[u].pairs && i2 != 0 && 2 * i2 != n2) ? a.w : 0.5 * a.w;
+          double ur[3], ui[3];
+#pragma unroll
+          for (int j = 0; j < 3; ++j) {
+            ur[j] = 0.5 * ((double)zp[u][j].x + (double)zm[u][j].x);
+            ui[j] = 0.5 * ((double)zp[u][j].y - (double)zm[u][j].y);
+            const double wr = 0.5 * ((double)zp[u][j].y + (double)zm[u][j].y);
+            const double wi = -0.5 * ((double)zp[u][j].x - (double)zm[u][j].x);
+            qsum += wr * wr + wi * wi;
+          }
+          const double *kv = q[u].k, kk = q[u].kk;
+          if (kk > 0) {
+            const double pr = (kv[0] * ur[0] + kv[1] * ur[1] + kv[2] * ur[2]) / kk;
+            const double pi = (kv[0] * ui[0] + kv[1] * ui[1] + kv[2] * ui[2]) / kk;
+#pragma unroll
+            for (int j = 0; j < 3; ++j) {
+              const double cr = kv[j] * pr, ci = kv[j] * pi;
+              csum += cr * cr + ci * ci;
+              isum += (ur[j] - cr) * (ur[j] - cr) + (ui[j] - ci) * (ui[j] - ci);
+            }
+          } else {
+#pragma unroll
+            for (int j = 0; j < 3; ++j) isum += ur[j] * ur[j] + ui[j] * ui[j];
+          }
+          csum *= wgt;
+          isum *= wgt;
+          qsum *= wgt;
+        }
+        csum = run_sum(csum, q[u].key, lane);
+        isum = run_sum(isum, q[u].key, lane);
+        qsum = run_sum(qsum, q[u].key, lane);
+        if (last) {
+          atomicAdd(&hist[nb + q[u].bin], csum);
+          atomicAdd(&hist[2 * nb + q[u].bin], isum);
+          atomicAdd(&hist[3 * nb + q[u].bin], qsum);
+        }
+      }
     }
   }
   __syncthreads();
@@ -95,13 +180,27 @@ __global__ void __launch_bounds__(kShellThreads) shell_kernel(const ShellArgs a)
   for (int i = threadIdx.x; i < 4 * nb; i += blockDim.x) out[i] = hist[i];
 }
 
-__global__ void sum_columns_kernel(const double *__restrict__ partial, long long count, int len,
-                                   double *__restrict__ out) {
-  const int i = blockIdx.x * blockDim.x + threadIdx.x;
-  if (i >= len) return;
+// Column sums of a [count][len] array in fixed order: a block of 64 columns
+// x 16 row groups; group g adds rows g, g + 16, ... in order, then the 16
+// group sums are added in order.
+constexpr int kSumCols = 64, kSumGroups = 16;
+
+__global__ void __launch_bounds__(kSumCols * kSumGroups)
+sum_columns_kernel(const double *__restrict__ partial, long long count, int len,
+                   double *__restrict__ out) {
+  __shared__ double part[kSumGroups][kSumCols];
+  const int c = threadIdx.x % kSumCols, g = threadIdx.x / kSumCols;
+  const int i = blockIdx.x * kSumCols + c;
   double s = 0;
-  for (long long b = 0; b < count; ++b) s += partial[b * len + i];
-  out[i] = s;
+  if (i < len)
+    for (long long b = g; b < count; b += kSumGroups) s += partial[b * len + i];
+  part[g][c] = s;
+  __syncthreads();
+  if (g == 0 && i < len) {
+    double t = part[0][c];
+    for (int k = 1; k < kSumGroups; ++k) t += part[k][c];
+    out[i] = t;
+  }
 }
 
 }  // namespace
@@ -116,17 +215,29 @@ hipError_t launch_shells(int precision, const ShellArgs &a, hipStream_t s) {
   const int blocks = shell_blocks(sites);
   const size_t lds = 4 * (size_t)a.nbins * sizeof(double);
   if (lds > 64 * 1024) return hipErrorInvalidValue;
-  if (state_f32(precision))  // the packed fields are stored like the state
-    hipLaunchKernelGGL(shell_kernel<float>, dim3(blocks), dim3(kShellThreads), lds, s, a);
-  else
-    hipLaunchKernelGGL(shell_kernel<double>, dim3(blocks), dim3(kShellThreads), lds, s, a);
+  // the packed fields are stored like the state
+  if (state_f32(precision)) {
+    if (a.kind == 0)
+      hipLaunchKernelGGL((shell_kernel<float, 0, kShellU0>), dim3(blocks), dim3(kShellThreads), lds,
+                         s, a);
+    else
+      hipLaunchKernelGGL((shell_kernel<float, 1, kShellU1>), dim3(blocks), dim3(kShellThreads), lds,
+                         s, a);
+  } else {
+    if (a.kind == 0)
+      hipLaunchKernelGGL((shell_kernel<double, 0, kShellU0>), dim3(blocks), dim3(kShellThreads),
+                         lds, s, a);
+    else
+      hipLaunchKernelGGL((shell_kernel<double, 1, kShellU1>), dim3(blocks), dim3(kShellThreads),
+                         lds, s, a);
+  }
   return hipGetLastError();
 }
 
 hipError_t launch_sum_columns(const double *partial, long long count, int len, double *out,
                               hipStream_t s) {
-  hipLaunchKernelGGL(sum_columns_kernel, dim3((len + 255) / 256), dim3(256), 0, s, partial, count,
-                     len, out);
+  hipLaunchKernelGGL(sum_columns_kernel, dim3((len + kSumCols - 1) / kSumCols),
+                     dim3(kSumCols * kSumGroups), 0, s, partial, count, len, out);
   return hipGetLastError();
 }
 
