@@ -527,6 +527,8 @@ enum PassMode : int {
   MODE_FWD = 7,            // forward only, spectrum stored in natural order
   MODE_DERIV = 8,          // forward, table, inverse, combine with the re-read
                            // state (PH_DERIV), forward again, store
+  MODE_OBS = 9,            // forward only, kinetic sum, nothing stored
+  MODE_OBS_REAL = 10,      // the same plus the real-space sums of the input
 };
 
 // Storage type of the state in HBM, converted on load and store: the
@@ -548,17 +550,22 @@ axis_pass_kernel(const PassArgs a) {
   constexpr bool SLI = MODE == MODE_SLOTS_IMAG;
   constexpr bool SL = MODE == MODE_SLOTS_REAL || SLI;
   constexpr bool FWD = MODE == MODE_FWD, DER = MODE == MODE_DERIV;
+  constexpr bool OBS = MODE == MODE_OBS || MODE == MODE_OBS_REAL;
   const int forward = G ? a.forward : 1;
-  const int inverse = G ? a.inverse : (FWD ? 0 : 1);
-  const int store = G ? a.store : 1;
+  const int inverse = G ? a.inverse : (FWD || OBS ? 0 : 1);
+  const int store = G ? a.store : (OBS ? 0 : 1);
   int pre = G ? a.pre
               : (MODE == MODE_PRE_REAL ? PH_REAL : MODE == MODE_PRE_IMAG ? PH_IMAG : PH_NONE);
   int post = G ? a.post
                : (MODE == MODE_POST_IMAG_RED ? PH_IMAG : DER ? PH_DERIV : PH_NONE);
-  const int mid = G ? a.mid : (FWD ? MID_NONE : MID_TABLE);
+  const int mid = G ? a.mid : (FWD || OBS ? MID_NONE : MID_TABLE);
   const bool refwd = G ? a.refwd != 0 : DER;
-  int red = G ? a.red : (MODE == MODE_POST_IMAG_RED ? RED_NORM_OUT : RED_NONE);
-  bool has_scale = G ? a.scale != nullptr : MODE == MODE_PRE_IMAG;
+  int red = G ? a.red
+              : (MODE == MODE_POST_IMAG_RED ? RED_NORM_OUT
+                 : MODE == MODE_OBS         ? RED_KIN
+                 : MODE == MODE_OBS_REAL    ? (RED_KIN | RED_REAL)
+                                            : RED_NONE);
+  bool has_scale = G || OBS ? a.scale != nullptr : MODE == MODE_PRE_IMAG;
   // Per-block parameters: from the arguments, or (batched) from this block's slot.
   const void *psrc = a.src;
   void *pdst = a.dst;
@@ -813,6 +820,14 @@ void launch_mode(const PassArgs &a, int mode, dim3 grid, dim3 block, hipStream_t
     case MODE_DERIV:
       hipLaunchKernelGGL((axis_pass_kernel<T, PL, W, STRIDED, MODE_DERIV, SX>), grid, block, 0, s,
                          a);
+      break;
+    case MODE_OBS:
+      hipLaunchKernelGGL((axis_pass_kernel<T, PL, W, STRIDED, MODE_OBS, SX>), grid, block, 0, s,
+                         a);
+      break;
+    case MODE_OBS_REAL:
+      hipLaunchKernelGGL((axis_pass_kernel<T, PL, W, STRIDED, MODE_OBS_REAL, SX>), grid, block, 0,
+                         s, a);
       break;
     default:
       hipLaunchKernelGGL((axis_pass_kernel<T, PL, W, STRIDED, MODE_GENERIC, SX>), grid, block, 0,

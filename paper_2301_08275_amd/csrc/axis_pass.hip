@@ -27,12 +27,19 @@ namespace {
 
 // The specialised kernels assume full tiles and one of the standard pass
 // layouts (the step passes: forward, per-frequency table, inverse, store;
-// forward-only transforms; the spectral-derivative pass); anything else runs
-// generic.
+// forward-only transforms; the spectral-derivative pass; the observables'
+// forward passes); anything else runs generic.
 int pick_mode(const PassArgs &a, const PassShape &sh) {
   if (a.slots) return a.slot_imag ? MODE_SLOTS_IMAG : MODE_SLOTS_REAL;
   const bool full = sh.strided || ((long long)a.n[0] * a.n[1]) % sh.W == 0;
-  if (!full || !a.forward || !a.store) return MODE_GENERIC;
+  if (!full || !a.forward) return MODE_GENERIC;
+  if (!a.store) {
+    const bool obs = !a.inverse && a.mid == MID_NONE && a.pre == PH_NONE &&
+                     a.post == PH_NONE && !a.refwd;
+    if (obs && a.red == RED_KIN) return MODE_OBS;
+    if (obs && a.red == (RED_KIN | RED_REAL)) return MODE_OBS_REAL;
+    return MODE_GENERIC;
+  }
   const bool bare = !a.scale && a.pre == PH_NONE && a.red == RED_NONE;
   if (!a.inverse)
     return bare && a.mid == MID_NONE && a.post == PH_NONE && !a.refwd ? MODE_FWD : MODE_GENERIC;
