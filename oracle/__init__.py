@@ -46,11 +46,13 @@ def _load():
     lib.orc_ground_state.argtypes = [dp, c_int, ip, dp, dp, dp, c_double, c_double,
                                      c_double, c_int, c_long, c_double, lp, dp]
     lib.orc_observables.argtypes = [dp, c_int, ip, dp, dp, dp, c_double, dp]
+    lib.orc_nonlinear_real.argtypes = [dp, c_int, ip, dp, dp, dp, c_double, c_double]
+    lib.orc_kinetic_real.argtypes = [dp, c_int, ip, dp, dp, c_double]
     lib.orc_spectra_bins.argtypes = [c_int, ip, dp, dp, dp]
     lib.orc_spectra.argtypes = [dp, c_int, ip, dp, dp, c_int, dp, dp, dp, dp]
     for f in (lib.orc_fft, lib.orc_fft_axis, lib.orc_tssp_real, lib.orc_tssp_imag,
               lib.orc_ground_state, lib.orc_observables, lib.orc_spectra_bins,
-              lib.orc_spectra):
+              lib.orc_spectra, lib.orc_nonlinear_real, lib.orc_kinetic_real):
         f.restype = c_int
     _lib = lib
     return lib
@@ -124,6 +126,53 @@ def tssp_real(psi, lo, hi, V, g, dt, nsteps):
     _check(lib.orc_tssp_real(_dptr(out), dim, n, _dptr(lo), _dptr(hi),
                              _dptr(V) if V is not None else None,
                              float(g), float(dt), int(nsteps)), "tssp_real")
+    return out
+
+
+def separable_potential(shape, lo, hi, w=None, center=None, quartic=None, lattice=None,
+                        q=None, phase=None):
+    """V(r) = sum_j v_j(x_j) with v_j(x) = 1/2 w_j^2 (x - c_j)^2 + a_j (x - c_j)^4
+    + s_j sin^2(q_j x + phi_j) on the grid x_j = lo_j + i h_j (the anharmonic
+    traps and optical lattices of the feature list, in the form this
+    implementation reads them; parameters not given are zero)."""
+    dim = len(shape)
+    lo, hi = _box(lo, hi, dim)
+
+    def par(v, j):
+        return 0.0 if v is None else float(v[j])
+
+    V = np.zeros(shape)
+    for j in range(dim):
+        x = lo[j] + np.arange(shape[j]) * (hi[j] - lo[j]) / shape[j]
+        d = x - par(center, j)
+        v = (0.5 * par(w, j) ** 2 * d ** 2 + par(quartic, j) * d ** 4
+             + par(lattice, j) * np.sin(par(q, j) * x + par(phase, j)) ** 2)
+        V += v.reshape([shape[j] if k == j else 1 for k in range(dim)])
+    return V
+
+
+def tssp_real_tdep(psi, lo, hi, Vfun, g, dt, nsteps, t0=0.0):
+    """Real-time Strang steps with a time-dependent potential Vfun(t) (an
+    array of psi's shape).  Step s covers [t_s, t_s + dt], t_s = t0 + s dt:
+    N(dt/2) with V at the midpoint t_s + dt/4 of its interval, K(dt), N(dt/2)
+    with V at t_s + 3 dt/4 (an N substep holds |psi| fixed, so its exact
+    solution integrates V over the interval; the midpoint rule keeps second
+    order).  Unfused, in the order of the scheme."""
+    lib = _load()
+    out = _state(psi)
+    dim, n = _shape(out)
+    lo, hi = _box(lo, hi, dim)
+    for s in range(int(nsteps)):
+        ts = t0 + s * dt
+        for t_mid in (ts + dt / 4, None, ts + 3 * dt / 4):
+            if t_mid is None:
+                _check(lib.orc_kinetic_real(_dptr(out), dim, n, _dptr(lo), _dptr(hi), float(dt)),
+                       "kinetic_real")
+                continue
+            V = _pot(Vfun(t_mid), out.shape)
+            _check(lib.orc_nonlinear_real(_dptr(out), dim, n, _dptr(lo), _dptr(hi),
+                                          _dptr(V) if V is not None else None, float(g),
+                                          float(dt) / 2), "nonlinear_real")
     return out
 
 

@@ -405,6 +405,25 @@ int orc_tssp_real(double *psi, int dim, const int *n, const double *lo,
   return 0;
 }
 
+int orc_nonlinear_real(double *psi, int dim, const int *n, const double *lo,
+                       const double *hi, const double *V, double g, double tau) {
+  Grid G;
+  if (!psi || !make_grid(dim, n, lo, hi, G)) return -1;
+  nonlinear_real(reinterpret_cast<cplx *>(psi), G, V, g, tau);
+  return 0;
+}
+
+int orc_kinetic_real(double *psi, int dim, const int *n, const double *lo,
+                     const double *hi, double dt) {
+  Grid G;
+  if (!psi || !make_grid(dim, n, lo, hi, G)) return -1;
+  cplx *p = reinterpret_cast<cplx *>(psi);
+  fft_all(p, G, false);
+  kinetic_real(p, G, dt);
+  fft_all(p, G, true);
+  return 0;
+}
+
 int orc_tssp_imag(double *psi, int dim, const int *n, const double *lo,
                   const double *hi, const double *V, double g, double dt,
                   long nsteps, double norm_target) {

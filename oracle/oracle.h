@@ -42,6 +42,14 @@ int orc_tssp_real(double *psi, int dim, const int *n, const double *lo,
                   const double *hi, const double *V, double g, double dt,
                   long nsteps);
 
+/* The two real-time substeps, for schedules built by the caller (the
+ * time-dependent potential): N(tau) psi = exp(-i (V + g|psi|^2) tau) psi, and
+ * K(dt) = forward transform, exp(-i |k|^2 dt / 2), inverse transform. */
+int orc_nonlinear_real(double *psi, int dim, const int *n, const double *lo,
+                       const double *hi, const double *V, double g, double tau);
+int orc_kinetic_real(double *psi, int dim, const int *n, const double *lo,
+                     const double *hi, double dt);
+
 /* nsteps imaginary-time steps, each renormalised to norm_target. */
 int orc_tssp_imag(double *psi, int dim, const int *n, const double *lo,
                   const double *hi, const double *V, double g, double dt,

@@ -341,3 +341,119 @@ def test_phase_field_is_irrotational():
     ek = s["e_comp"].sum() + s["e_incomp"].sum() + s["e_qp"].sum()
     assert s["e_incomp"].sum() < 1e-10 * ek
     assert s["e_qp"].sum() < 1e-10 * ek
+
+
+# ------------------------------------------- separable and time-dependent V ---
+# The feature list names anharmonic traps, optical lattices and time-dependent
+# potentials V(r, t) (Eq. 2) without formulas; the oracle's family is
+# v_j(x) = 1/2 w^2 (x - c)^2 + a (x - c)^4 + s sin^2(q x + phi) per axis.
+
+
+def test_lattice_ground_state_is_the_mathieu_value():
+    """g = 0, V = s sin^2(q x) on a box of whole lattice periods: with z = q x
+    the eigenproblem is Mathieu's equation y'' + (A - 2 Q cos 2z) y = 0 with
+    Q = s/(2 q^2), so E0 = s/2 + (q^2/2) a_0(Q) (scipy's characteristic value);
+    a second, lattice-free axis adds nothing."""
+    from scipy.special import mathieu_a
+
+    s, q = 2.0, 1.0
+    e_ref = s / 2 + q * q / 2 * mathieu_a(0, s / (2 * q * q))
+    for shape, lo, hi in [((128,), (0.0,), (2 * math.pi,)),
+                          ((64, 16), (0.0, -3.0), (2 * math.pi, 3.0))]:
+        V = oracle.separable_potential(shape, lo, hi, lattice=[s, 0.0], q=[q, 0.0])
+        psi0 = np.ones(shape, complex)
+        _, _, E, conv = oracle.ground_state(psi0, lo, hi, V, 0.0, 1e-3, tol=1e-14,
+                                            max_steps=200000)
+        assert conv
+        assert abs(E - e_ref) < 1e-9, (shape, E, e_ref)
+
+
+def quartic_ground_energy(w, a, nbasis=160):
+    """Lowest eigenvalue of 1/2 p^2 + 1/2 w^2 x^2 + a x^4 in the basis of the
+    w = 1 oscillator (x = (b + b^dagger)/sqrt 2), a dense symmetric eigenproblem
+    independent of any time stepping."""
+    m = nbasis + 8
+    k = np.arange(1, m)
+    X = np.diag(np.sqrt(k / 2), 1) + np.diag(np.sqrt(k / 2), -1)
+    X2 = X @ X
+    H = np.diag(np.arange(m) + 0.5) + 0.5 * (w * w - 1) * X2 + a * (X2 @ X2)
+    return np.linalg.eigvalsh(H[:nbasis, :nbasis])[0]
+
+
+def test_anharmonic_ground_state_matches_basis_diagonalisation():
+    shape, lo, hi = (256,), (-8.0,), (8.0,)
+    w, a = 1.0, 0.5
+    V = oracle.separable_potential(shape, lo, hi, w=[w], quartic=[a])
+    x = lo[0] + np.arange(shape[0]) * (hi[0] - lo[0]) / shape[0]
+    psi0 = np.exp(-x * x / 2) + 0j
+    _, _, E, conv = oracle.ground_state(psi0, lo, hi, V, 0.0, 1e-3, tol=1e-14,
+                                        max_steps=200000)
+    assert conv
+    assert abs(E - quartic_ground_energy(w, a)) < 1e-9
+
+
+def test_separable_potential_centre_and_phase():
+    """A shifted trap is the centred one translated by whole grid cells, and a
+    lattice phase of pi/2 turns sin^2 into cos^2."""
+    shape, lo, hi = (32, 16), (-4.0, -2.0), (4.0, 2.0)
+    h = 8.0 / 32
+    V0 = oracle.separable_potential(shape, lo, hi, w=[1.5, 0.5])
+    V1 = oracle.separable_potential(shape, lo, hi, w=[1.5, 0.5], center=[3 * h, 0.0])
+    assert np.allclose(V1[3:], V0[:-3], rtol=0, atol=1e-13)
+    x = lo[0] + np.arange(32) * h
+    Vl = oracle.separable_potential(shape, lo, hi, lattice=[0.7, 0.0], q=[2.0, 0.0],
+                                    phase=[math.pi / 2, 0.0])
+    assert np.allclose(Vl[:, 0], 0.7 * np.cos(2.0 * x) ** 2, rtol=0, atol=1e-14)
+
+
+def test_moving_trap_centre_of_mass_follows_kohn():
+    """Harmonic trap whose centre moves as c(t) = A sin(W t): for any g the
+    centre of mass obeys X'' = -w^2 (X - c(t)) exactly (interactions exert no
+    net force), so from rest at the origin
+    X(t) = A w^2 / (w^2 - W^2) (sin W t - (W/w) sin w t).  The splitting and
+    the midpoint rule are second order; a midpoint off by a quarter step
+    would leave an O(dt) error, far above the bar."""
+    shape, lo, hi = (64, 64), (-8.0, -8.0), (8.0, 8.0)
+    A, W, w, g, dt = 0.5, 2.0, 1.0, 5.0, 1e-3
+
+    def Vfun(t):
+        return oracle.separable_potential(shape, lo, hi, w=[w, 1.0],
+                                          center=[A * math.sin(W * t), 0.0])
+
+    psi = I.gaussian(shape, lo, hi)
+    x = lo[0] + np.arange(shape[0]) * (hi[0] - lo[0]) / shape[0]
+    worst = 0.0
+    for k in range(4):
+        psi = oracle.tssp_real_tdep(psi, lo, hi, Vfun, g, dt, 500, t0=k * 500 * dt)
+        t = (k + 1) * 500 * dt
+        rho = np.abs(psi) ** 2
+        X = float(np.sum(x[:, None] * rho) / np.sum(rho))
+        Xk = A * w * w / (w * w - W * W) * (math.sin(W * t) - W / w * math.sin(w * t))
+        worst = max(worst, abs(X - Xk))
+    assert worst < 1e-6
+
+
+def test_uniform_time_dependent_shift_is_a_global_phase():
+    """V(r, t) = f(t) everywhere multiplies the V = 0 solution by
+    exp(-i int_0^T f); with f = 0.3 sin^2(3t) the integral is closed form."""
+    shape, lo, hi = (64, 64), (-8.0, -8.0), (8.0, 8.0)
+    g, dt, n = 5.0, 1e-3, 400
+
+    def f(t):
+        return 0.3 * math.sin(3 * t) ** 2
+
+    psi0 = I.gaussian(shape, lo, hi)
+    a = oracle.tssp_real_tdep(psi0, lo, hi, lambda t: np.full(shape, f(t)), g, dt, n)
+    b = oracle.tssp_real(psi0, lo, hi, None, g, dt, n)
+    T = n * dt
+    F = 0.3 * (T / 2 - math.sin(6 * T) / 12)
+    assert np.max(np.abs(a - b * np.exp(-1j * F))) < 1e-7
+
+
+def test_time_dependent_stepper_with_a_constant_potential_is_the_plain_one():
+    shape, lo, hi = (32, 32), (-6.0, -6.0), (6.0, 6.0)
+    V = I.harmonic(shape, lo, hi, [1.0, 2.0])
+    psi0 = I.noisy_gaussian(shape, lo, hi, seed=1)
+    a = oracle.tssp_real(psi0, lo, hi, V, 5.0, 1e-3, 20)
+    b = oracle.tssp_real_tdep(psi0, lo, hi, lambda t: V, 5.0, 1e-3, 20)
+    assert np.max(np.abs(a - b)) < 1e-15
