@@ -123,9 +123,49 @@ gpe_status gpe_create(const gpe_desc *desc, const double *V_host,
                       const gpe_harmonic *V_an, void *hip_stream,
                       gpe_ctx **out);
 
-/* Replace the potential (same rules as gpe_create). */
+/* Replace the potential (same rules as gpe_create).  Removes a separable or
+ * time-dependent potential. */
 gpe_status gpe_set_potential(gpe_ctx *ctx, const double *V_host,
                              const gpe_harmonic *V_an);
+
+/* Separable analytic potential.  The feature list of the paper names
+ * anharmonic traps, optical lattices and time-dependent potentials (the
+ * V(r, t) of Eq. 2) without formulas; this is the family provided:
+ *   V(r) = sum_j v_j(x_j),
+ *   v_j(x) = 1/2 w_j^2 (x - c_j)^2 + a_j (x - c_j)^4 + s_j sin^2(q_j x + phi_j),
+ * j < dim (later entries are ignored).  The passes read V as three per-axis
+ * tables of n_j values: no per-site memory traffic. */
+typedef struct {
+  double w[3];        /* harmonic frequency w_j */
+  double center[3];   /* trap centre c_j */
+  double quartic[3];  /* anharmonic coefficient a_j */
+  double lattice[3];  /* lattice depth s_j */
+  double q[3];        /* lattice wavenumber q_j */
+  double phase[3];    /* lattice phase phi_j */
+} gpe_separable;
+
+/* Static separable potential; replaces any earlier potential.  V NULL or a
+ * non-finite entry: GPE_EINVAL. */
+gpe_status gpe_set_separable(gpe_ctx *ctx, const gpe_separable *V);
+
+/* Time-dependent separable potential V(r, t).  fn(t, out, user) fills the
+ * parameters at time t; it runs on the calling host thread during library
+ * calls and must not call the library for this context.  An N substep over
+ * the time interval [ta, tb] applies exp(-i (V(r, (ta + tb)/2) + g|psi|^2)
+ * (tb - ta)) (the midpoint rule keeps the splitting second order); two
+ * fused half-steps apply the mean of their two midpoint potentials over the
+ * full step, which equals the two half-steps applied one after the other.
+ * Real time advances the context clock (gpe_evolve: t += nsteps dt); the
+ * ground-state method and the observables use V at the current clock.
+ * Non-finite parameters from fn stop the call with GPE_EINVAL.  fn = NULL
+ * removes the potential (V = 0).  Replaces any earlier potential. */
+typedef void (*gpe_potential_fn)(double t, gpe_separable *out, void *user);
+gpe_status gpe_set_potential_fn(gpe_ctx *ctx, gpe_potential_fn fn, void *user);
+
+/* The context clock: 0 at creation; real-time steps advance it by dt.  It
+ * only matters for a time-dependent potential. */
+gpe_status gpe_set_time(gpe_ctx *ctx, double t);
+gpe_status gpe_get_time(const gpe_ctx *ctx, double *t);
 
 /* Copy a host FP64 state in (interleaved complex, n sites); synchronous. */
 gpe_status gpe_set_state(gpe_ctx *ctx, const double *psi_host);

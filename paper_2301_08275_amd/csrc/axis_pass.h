@@ -398,6 +398,7 @@ __device__ __forceinline__ double site_potential(const PassArgs &a, int vkind, c
                                                  int j0, int j1, int j2) {
   if (vkind == V_NONE) return 0.0;
   if (vkind == V_ARRAY) return a.V[((long long)j0 * a.n[1] + j1) * a.n[2] + j2];
+  if (vkind == V_TABLES) return a.vtab[j0] + a.vtab[a.n[0] + j1] + a.vtab[a.n[0] + a.n[1] + j2];
   return harmonic_potential(a.lo, a.h, hv, j0, j1, j2);
 }
 

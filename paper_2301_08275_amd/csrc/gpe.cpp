@@ -177,8 +177,10 @@ gpe::PassArgs base_args(gpe_ctx *c, int vaxis) {
   a.plan = c->plan[vaxis];
   a.xcd_remap = (vaxis != 2 && c->xcd_remap[vaxis]) ? 1 : 0;
   a.vkind = c->V ? gpe::V_ARRAY
+                 : c->vtab_on ? gpe::V_TABLES
                  : ((c->hv[0] != 0 || c->hv[1] != 0 || c->hv[2] != 0) ? gpe::V_HARMONIC
                                                                       : gpe::V_NONE);
+  a.vtab = c->vtab;
   a.forward = 1;
   a.inverse = 1;
   a.store = 1;
@@ -312,6 +314,9 @@ gpe_status set_potential(gpe_ctx *c, const double *V_host, const gpe_harmonic *V
   if (V_host && V_an) return fail(c, GPE_EINVAL, "give V_host or V_an, not both");
   drop_step_graphs(c);  // their launches carry the old potential
   for (int j = 0; j < 3; ++j) c->hv[j] = 0;
+  c->vtab_on = false;
+  c->vfn = nullptr;
+  c->vfn_user = nullptr;
   if (V_an) {
     for (int j = 0; j < c->dim; ++j) {
       if (!std::isfinite(V_an->w[j])) return fail(c, GPE_EINVAL, "trap frequency not finite");
@@ -334,11 +339,56 @@ gpe_status set_potential(gpe_ctx *c, const double *V_host, const gpe_harmonic *V
   return GPE_OK;
 }
 
+// Separable potential parameters on the view axes (hw = w^2 / 2); false if
+// any used entry is not finite.
+bool sep_params(const gpe_ctx *c, const gpe_separable &u, gpe::SepParams *P) {
+  *P = gpe::SepParams{};
+  for (int j = 0; j < c->dim; ++j) {
+    const int v = view_axis(c, j);
+    const double vals[6] = {u.w[j], u.center[j], u.quartic[j], u.lattice[j], u.q[j], u.phase[j]};
+    for (double x : vals)
+      if (!std::isfinite(x)) return false;
+    P->hw[v] = 0.5 * u.w[j] * u.w[j];
+    P->c[v] = u.center[j];
+    P->a[v] = u.quartic[j];
+    P->s[v] = u.lattice[j];
+    P->q[v] = u.q[j];
+    P->ph[v] = u.phase[j];
+  }
+  return true;
+}
+
+gpe_status alloc_vtab(gpe_ctx *c) {
+  if (c->vtab) return GPE_OK;
+  return dalloc(c, (void **)&c->vtab, (c->n3[0] + c->n3[1] + c->n3[2]) * sizeof(double),
+                "potential table allocation");
+}
+
+// Rewrite the tables of a time-dependent potential with the weighted sum of
+// V(ta) (weight wa) and V(tb) (weight wb; skipped when 0); a static
+// potential needs nothing.  Enqueued on the context stream, so passes
+// already enqueued read the previous tables.
+gpe_status vtables_at(gpe_ctx *c, const VAt &at) {
+  if (!c->vfn) return GPE_OK;
+  gpe_separable u[2] = {};
+  gpe::SepParams P[2];
+  c->vfn(at.ta, &u[0], c->vfn_user);
+  if (at.wb != 0) c->vfn(at.tb, &u[1], c->vfn_user);
+  if (!sep_params(c, u[0], &P[0]) || (at.wb != 0 && !sep_params(c, u[1], &P[1])))
+    return fail(c, GPE_EINVAL, "the potential callback returned a non-finite parameter");
+  if (at.wb == 0) P[1] = P[0];
+  HIPCHK(c, gpe::launch_vtables(P[0], at.wa, P[1], at.wb, c->n3, c->lo3, c->h3, c->vtab,
+                                c->stream), "potential table launch");
+  return GPE_OK;
+}
+
 // Read-only observation passes: per axis a forward transform with the
 // kinetic-weight sum; the first also takes the real-space sums.  scale (device,
 // nullable) multiplies the state on the fly.  Enqueues the finalized sums,
 // 3 x kRedSlots doubles, at sums_dev (device); no host wait.
 gpe_status enqueue_observe(gpe_ctx *c, const double *scale, double *sums_dev) {
+  gpe_status vst = vtables_at(c, VAt{c->time, 1.0, 0.0, 0.0});  // E_pot at the clock
+  if (vst != GPE_OK) return vst;
   for (int i = 0; i < n_axes(c); ++i) {
     const int ax = order_axis(c, i);
     gpe::PassArgs a = base_args(c, ax);
@@ -663,6 +713,44 @@ gpe_status gpe_set_potential(gpe_ctx *c, const double *V_host, const gpe_harmoni
   return set_potential(c, V_host, V_an);
 }
 
+gpe_status gpe_set_separable(gpe_ctx *c, const gpe_separable *V) {
+  if (!c) return GPE_EINVAL;
+  if (!V) return fail(c, GPE_EINVAL, "V is NULL");
+  gpe::SepParams P;
+  if (!sep_params(c, *V, &P)) return fail(c, GPE_EINVAL, "potential parameter not finite");
+  gpe_status st = set_potential(c, nullptr, nullptr);
+  if (st == GPE_OK) st = alloc_vtab(c);
+  if (st != GPE_OK) return st;
+  HIPCHK(c, gpe::launch_vtables(P, 1.0, P, 0.0, c->n3, c->lo3, c->h3, c->vtab, c->stream),
+         "potential table launch");
+  c->vtab_on = true;
+  return GPE_OK;
+}
+
+gpe_status gpe_set_potential_fn(gpe_ctx *c, gpe_potential_fn fn, void *user) {
+  if (!c) return GPE_EINVAL;
+  gpe_status st = set_potential(c, nullptr, nullptr);
+  if (st != GPE_OK || !fn) return st;
+  if ((st = alloc_vtab(c)) != GPE_OK) return st;
+  c->vfn = fn;
+  c->vfn_user = user;
+  c->vtab_on = true;
+  return GPE_OK;
+}
+
+gpe_status gpe_set_time(gpe_ctx *c, double t) {
+  if (!c) return GPE_EINVAL;
+  if (!std::isfinite(t)) return fail(c, GPE_EINVAL, "t must be finite");
+  c->time = t;
+  return GPE_OK;
+}
+
+gpe_status gpe_get_time(const gpe_ctx *c, double *t) {
+  if (!c || !t) return GPE_EINVAL;
+  *t = c->time;
+  return GPE_OK;
+}
+
 gpe_status gpe_set_state(gpe_ctx *c, const double *psi_host) {
   if (!c) return GPE_EINVAL;
   if (!psi_host) return fail(c, GPE_EINVAL, "psi_host is NULL");
@@ -726,10 +814,15 @@ constexpr size_t kMaxStepGraphs = 8;   // graphs kept per context
 // One real-time step: phase N(tau_pre) before the first pass, the kinetic
 // factor K in every pass, and a closing phase N(dt/2) after the last pass of
 // the last step of a call.
-gpe_status real_step(gpe_ctx *c, void *const K[3], double tau_pre, double tau_post) {
+gpe_status real_step(gpe_ctx *c, void *const K[3], double tau_pre, double tau_post,
+                     const VAt *pre, const VAt *post) {
   const int na = n_axes(c);
   for (int i = 0; i < na; ++i) {
     const int ax = order_axis(c, i);
+    gpe_status vst = GPE_OK;
+    if (i == 0 && pre) vst = vtables_at(c, *pre);
+    if (i == na - 1 && tau_post != 0 && post) vst = vtables_at(c, *post);
+    if (vst != GPE_OK) return vst;
     gpe::PassArgs a = base_args(c, ax);
     a.mid = gpe::MID_TABLE;
     a.mtab = K[ax];
@@ -799,7 +892,7 @@ hipGraphExec_t step_graph(gpe_ctx *c, int mode, double dt, int len, void *const 
   }
   bool ok = true;
   for (int s = 0; s < len && ok; ++s)
-    ok = (mode == 0 ? real_step(c, K, dt, 0.0) : imag_step(c, K, dt)) == GPE_OK;
+    ok = (mode == 0 ? real_step(c, K, dt, 0.0, nullptr, nullptr) : imag_step(c, K, dt)) == GPE_OK;
   const bool ended = hipStreamEndCapture(c->stream, &g) == hipSuccess;
   if (ok && ended && g) ok = hipGraphInstantiate(&ge, g, nullptr, nullptr, 0) == hipSuccess;
   if (g) (void)hipGraphDestroy(g);
@@ -821,7 +914,7 @@ gpe_status steady_steps(gpe_ctx *c, int mode, double dt, int64_t n, int len, voi
     }
   }
   for (; n > 0; --n) {
-    gpe_status st = mode == 0 ? real_step(c, K, dt, 0.0) : imag_step(c, K, dt);
+    gpe_status st = mode == 0 ? real_step(c, K, dt, 0.0, nullptr, nullptr) : imag_step(c, K, dt);
     if (st != GPE_OK) return st;
   }
   return GPE_OK;
@@ -851,10 +944,27 @@ gpe_status gpe_evolve(gpe_ctx *c, double dt, int64_t nsteps) {
   }
   // Adjacent half-steps of N are fused: the first step opens with N(dt/2),
   // the others with N(dt), and the last closes with N(dt/2).
-  if (nsteps == 1) return real_step(c, K, dt / 2, dt / 2);
-  gpe_status st = real_step(c, K, dt / 2, 0.0);
-  if (st == GPE_OK) st = steady_steps(c, 0, dt, nsteps - 2, kGraphSteps, K);
-  if (st == GPE_OK) st = real_step(c, K, dt, dt / 2);
+  const double t0 = c->time;
+  gpe_status st = GPE_OK;
+  if (c->vfn) {
+    // Time-dependent potential: step s covers [t_s, t_s + dt]; its N
+    // half-steps take V at the midpoints t_s + dt/4 and t_s + 3 dt/4, and a
+    // fused N(dt) the mean of the two midpoints it joins.
+    const VAt close{t0 + nsteps * dt - dt / 4, 1.0, 0.0, 0.0};
+    for (int64_t s = 0; s < nsteps && st == GPE_OK; ++s) {
+      const double ts = t0 + s * dt;
+      const VAt open = s == 0 ? VAt{t0 + dt / 4, 1.0, 0.0, 0.0}
+                              : VAt{ts - dt / 4, 0.5, ts + dt / 4, 0.5};
+      st = real_step(c, K, s == 0 ? dt / 2 : dt, s == nsteps - 1 ? dt / 2 : 0.0, &open, &close);
+    }
+  } else if (nsteps == 1) {
+    st = real_step(c, K, dt / 2, dt / 2, nullptr, nullptr);
+  } else {
+    st = real_step(c, K, dt / 2, 0.0, nullptr, nullptr);
+    if (st == GPE_OK) st = steady_steps(c, 0, dt, nsteps - 2, kGraphSteps, K);
+    if (st == GPE_OK) st = real_step(c, K, dt, dt / 2, nullptr, nullptr);
+  }
+  if (st == GPE_OK) c->time = t0 + nsteps * dt;
   return st;
 }
 
@@ -911,6 +1021,10 @@ gpe_status gpe_ground_state(gpe_ctx *c, double dt, double tol, int32_t check_eve
     gpe_status st = get_table(c, ax, TB_KIMAG, dt, &K[ax]);
     if (st != GPE_OK) return st;
   }
+  // a time-dependent potential enters at the current clock (imaginary time
+  // does not advance it)
+  gpe_status vst = vtables_at(c, VAt{c->time, 1.0, 0.0, 0.0});
+  if (vst != GPE_OK) return vst;
   const double one = 1.0;
   HIPCHK(c, hipMemcpyAsync(c->scale, &one, sizeof(double), hipMemcpyHostToDevice, c->stream),
          "scale reset");
@@ -1046,6 +1160,7 @@ void gpe_destroy(gpe_ctx *c) {
   if (c->hist_partial) (void)hipFree(c->hist_partial);
   if (c->hist) (void)hipFree(c->hist);
   if (c->V) (void)hipFree(c->V);
+  if (c->vtab) (void)hipFree(c->vtab);
   if (c->partial) (void)hipFree(c->partial);
   if (c->sums) (void)hipFree(c->sums);
   if (c->scale) (void)hipFree(c->scale);

@@ -48,6 +48,14 @@ struct gpe_ctx {
   double *hist = nullptr;          // 8 x nbins finalized shell sums
   double *V = nullptr;         // FP64 potential array (device) or null
   double hv[3] = {0, 0, 0};    // analytic V coefficients (3D view)
+  // Separable potential: per-view-axis tables (n3[0] + n3[1] + n3[2] doubles)
+  // of v_j, or, for a time-dependent potential, of its mean over the
+  // midpoints of the N substep about to run (rewritten before each use).
+  double *vtab = nullptr;
+  bool vtab_on = false;
+  gpe_potential_fn vfn = nullptr;
+  void *vfn_user = nullptr;
+  double time = 0.0;           // context clock (real time)
   double *partial = nullptr;   // per-workgroup partials, 3 regions
   long long partial_region = 0;  // doubles per region
   double *sums = nullptr;      // finalized sums, 4 x kRedSlots
@@ -91,6 +99,11 @@ gpe_status get_table(gpe_ctx *c, int vaxis, int kind, double dt, void **out);
 gpe::PassArgs base_args(gpe_ctx *c, int vaxis);
 gpe_status launch_pass(gpe_ctx *c, const gpe::PassArgs &a);
 gpe_status set_potential(gpe_ctx *c, const double *V_host, const gpe_harmonic *V_an);
+// Times and weights of a time-dependent potential's table: wa V(ta) + wb V(tb).
+struct VAt {
+  double ta, wa, tb, wb;
+};
+gpe_status vtables_at(gpe_ctx *c, const VAt &at);
 void drop_step_graphs(gpe_ctx *c);
 // Steps per step graph unless convergence checks set the length.
 constexpr int kGraphSteps = 32;

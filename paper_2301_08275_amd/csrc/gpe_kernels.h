@@ -33,7 +33,7 @@ enum RedFlag : int {
 constexpr int kRedSlots = 8;  // partial[wg * kRedSlots + slot]
 constexpr int kSlotNormOut = 0, kSlotKin = 1, kSlotReal = 2;
 
-enum VKind : int { V_NONE = 0, V_ARRAY = 1, V_HARMONIC = 2 };
+enum VKind : int { V_NONE = 0, V_ARRAY = 1, V_HARMONIC = 2, V_TABLES = 3 };
 
 // One request of a batched shape class (device-resident).  Batched passes
 // launch one grid row (blockIdx.y) per slot; a slot whose mode is SLOT_FREE or
@@ -72,6 +72,7 @@ struct PassArgs {
   int xcd_remap;      // strided axes: give each XCD a contiguous run of tiles
   const double *V;    // FP64 potential per site, or null
   double hv[3];       // analytic V = sum_j hv[j] x_j^2 when V is null
+  const double *vtab; // V_TABLES: V = t[j0] + t[n0 + j1] + t[n0 + n1 + j2] (view axes)
   double lo[3], h[3]; // coordinates x_j = lo[j] + i h[j] (3D indexing)
   const void *tw;     // twiddles exp(-2 pi i j / N), j < N, complex T
   const void *mtab;   // mid table (complex T, N entries) for MID_TABLE
@@ -190,6 +191,18 @@ hipError_t launch_map_write(int *dst, const SlotMap &m, hipStream_t s);
 
 // Fill a state with index-hashed values in [-1, 1) (for timing runs).
 hipError_t launch_fill_noise(int precision, void *psi, long long sites, hipStream_t s);
+
+// Parameters of a separable analytic potential on the 3D view axes:
+// v_j(x) = hw[j] (x - c[j])^2 + a[j] (x - c[j])^4 + s[j] sin^2(q[j] x + ph[j]).
+struct SepParams {
+  double hw[3], c[3], a[3], s[3], q[3], ph[3];
+};
+// out[off_j + i] = wA v_j(x_{j,i}; A) + wB v_j(x_{j,i}; B) for every view axis j
+// and i < n[j] (off_0 = 0, off_1 = n[0], off_2 = n[0] + n[1]),
+// x_{j,i} = lo[j] + i h[j].
+hipError_t launch_vtables(const SepParams &A, double wA, const SepParams &B, double wB,
+                          const int n[3], const double lo[3], const double h[3], double *out,
+                          hipStream_t s);
 
 // Precision conversion copies (device to device).
 hipError_t launch_convert(int src_prec, const void *src, int dst_prec, void *dst,

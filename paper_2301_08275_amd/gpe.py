@@ -9,6 +9,7 @@ PyTorch ships its own HIP runtime with the same soname as the system one.
 When torch shares the process, import torch (and touch its device) before the
 first call here, so that libgpe.so binds to the runtime torch already loaded.
 """
+import contextlib
 import ctypes
 import os
 
@@ -72,6 +73,32 @@ class gpe_timing(ctypes.Structure):
                 ("bytes", ctypes.c_double * GPE_TIMING_KINDS)]
 
 
+SEPARABLE_FIELDS = ("w", "center", "quartic", "lattice", "q", "phase")
+
+
+class gpe_separable(ctypes.Structure):
+    _fields_ = [(f, ctypes.c_double * 3) for f in SEPARABLE_FIELDS]
+
+
+# void (*)(double t, gpe_separable *out, void *user)
+POTENTIAL_FN = ctypes.CFUNCTYPE(None, ctypes.c_double, ctypes.POINTER(gpe_separable),
+                                ctypes.c_void_p)
+
+
+def fill_separable(out, params):
+    """Write a dict of per-axis sequences (keys from SEPARABLE_FIELDS; missing
+    keys are zero) into a gpe_separable."""
+    unknown = set(params) - set(SEPARABLE_FIELDS)
+    if unknown:
+        raise ValueError("unknown potential parameters: %s" % sorted(unknown))
+    for f in SEPARABLE_FIELDS:
+        vals = params.get(f)
+        arr = getattr(out, f)
+        for j in range(3):
+            arr[j] = float(vals[j]) if vals is not None and j < len(vals) else 0.0
+    return out
+
+
 class gpe_request(ctypes.Structure):
     _fields_ = [("desc", gpe_desc), ("trap", gpe_harmonic),
                 ("psi0", ctypes.POINTER(ctypes.c_double)), ("mode", ctypes.c_int32),
@@ -109,6 +136,10 @@ SIGNATURES = {
     "gpe_create": (_I32, [ctypes.POINTER(gpe_desc), _DP, ctypes.POINTER(gpe_harmonic), _P,
                           ctypes.POINTER(_P)]),
     "gpe_set_potential": (_I32, [_P, _DP, ctypes.POINTER(gpe_harmonic)]),
+    "gpe_set_separable": (_I32, [_P, ctypes.POINTER(gpe_separable)]),
+    "gpe_set_potential_fn": (_I32, [_P, POTENTIAL_FN, _P]),
+    "gpe_set_time": (_I32, [_P, _D]),
+    "gpe_get_time": (_I32, [_P, _DP]),
     "gpe_set_state": (_I32, [_P, _DP]),
     "gpe_set_state_device": (_I32, [_P, _P, _I32]),
     "gpe_get_state": (_I32, [_P, _DP]),
@@ -201,6 +232,26 @@ def gpe_create(desc, V_host=None, V_an=None, hip_stream=None):
 def gpe_set_potential(ctx, V_host=None, V_an=None):
     return _check(load_library().gpe_set_potential(
         ctx, _dptr(V_host), ctypes.byref(V_an) if V_an is not None else None), ctx)
+
+
+def gpe_set_separable(ctx, sep):
+    return _check(load_library().gpe_set_separable(ctx, ctypes.byref(sep)), ctx)
+
+
+def gpe_set_potential_fn(ctx, fn, user=None):
+    """fn: a POTENTIAL_FN (or None); the caller keeps it alive while set."""
+    return _check(load_library().gpe_set_potential_fn(
+        ctx, fn if fn is not None else POTENTIAL_FN(), user), ctx)
+
+
+def gpe_set_time(ctx, t):
+    return _check(load_library().gpe_set_time(ctx, float(t)), ctx)
+
+
+def gpe_get_time(ctx):
+    t = _D(0)
+    _check(load_library().gpe_get_time(ctx, ctypes.byref(t)), ctx)
+    return t.value
 
 
 def gpe_set_state(ctx, psi_host):
@@ -428,6 +479,7 @@ class Context:
             for j in range(dim):
                 an.w[j] = float(harmonic[j])
         self._ctx = None
+        self._vfn = None  # (callback object, exceptions it caught)
         self._ctx = gpe_create(d, Vh, an, ctypes.c_void_p(stream) if stream else None)
 
     @property
@@ -459,6 +511,55 @@ class Context:
             for j in range(self.dim):
                 an.w[j] = float(harmonic[j])
         gpe_set_potential(self._ctx, Vh, an)
+        self._vfn = None
+
+    def set_separable(self, **params):
+        """Static separable potential: keyword arrays w, center, quartic,
+        lattice, q, phase (per axis; missing ones are zero)."""
+        gpe_set_separable(self._ctx, fill_separable(gpe_separable(), params))
+        self._vfn = None
+
+    def set_potential_fn(self, fn):
+        """Time-dependent separable potential: fn(t) returns a dict of the
+        set_separable keywords at time t (None removes the potential).  An
+        exception in fn stops the library call that ran it and is re-raised."""
+        if fn is None:
+            gpe_set_potential_fn(self._ctx, None)
+            self._vfn = None
+            return
+        errors = []
+
+        def trampoline(t, out, user):
+            try:
+                fill_separable(out.contents, fn(t))
+            except BaseException as e:  # reported through a non-finite entry
+                errors.append(e)
+                out.contents.w[0] = float("nan")
+
+        cb = POTENTIAL_FN(trampoline)
+        gpe_set_potential_fn(self._ctx, cb)
+        self._vfn = (cb, errors)
+
+    @contextlib.contextmanager
+    def _callbacks(self):
+        """Re-raise an exception of the potential callback in place of the
+        library error it caused."""
+        try:
+            yield
+        except GpeError as err:
+            if self._vfn and self._vfn[1]:
+                e = self._vfn[1][-1]
+                self._vfn[1].clear()
+                raise e from err
+            raise
+
+    @property
+    def time(self):
+        return gpe_get_time(self._ctx)
+
+    @time.setter
+    def time(self, t):
+        gpe_set_time(self._ctx, t)
 
     def set_state(self, psi):
         p = np.ascontiguousarray(psi, dtype=np.complex128)
@@ -485,30 +586,35 @@ class Context:
         gpe_get_state_device(self._ctx, ctypes.c_void_p(tensor.data_ptr()), dst)
 
     def evolve(self, dt, nsteps):
-        gpe_evolve(self._ctx, dt, nsteps)
+        with self._callbacks():
+            gpe_evolve(self._ctx, dt, nsteps)
 
     def evolve_record(self, dt, nsteps, every):
         """Evolve and return the observables after every `every` steps (list of dicts)."""
         cap = (int(nsteps) + int(every) - 1) // int(every)
         series = (gpe_obs * max(cap, 1))()
         count = _I64(0)
-        st = load_library().gpe_evolve_record(self._ctx, float(dt), int(nsteps), int(every),
-                                              series, cap, ctypes.byref(count))
-        _check(st, self._ctx)
+        with self._callbacks():
+            st = load_library().gpe_evolve_record(self._ctx, float(dt), int(nsteps), int(every),
+                                                  series, cap, ctypes.byref(count))
+            _check(st, self._ctx)
         return [dict(zip(OBS_KEYS, [o.norm, o.energy, o.mu, o.e_kin, o.e_pot, o.e_int,
                                     o.sigma[0], o.sigma[1], o.sigma[2], o.r_rms]))
                 for o in series[:count.value]]
 
     def ground_state(self, dt, tol=1e-10, check_every=10, max_steps=1000000):
-        st, steps, energy = gpe_ground_state(self._ctx, dt, tol, check_every, max_steps)
+        with self._callbacks():
+            st, steps, energy = gpe_ground_state(self._ctx, dt, tol, check_every, max_steps)
         return steps, energy, st == GPE_OK
 
     def imag_steps(self, dt, nsteps):
-        gpe_ground_state(self._ctx, dt, 0.0, 0, nsteps)
+        with self._callbacks():
+            gpe_ground_state(self._ctx, dt, 0.0, 0, nsteps)
 
     def observables(self):
         o = gpe_obs()
-        gpe_observables(self._ctx, o, None)
+        with self._callbacks():
+            gpe_observables(self._ctx, o, None)
         vals = [o.norm, o.energy, o.mu, o.e_kin, o.e_pot, o.e_int,
                 o.sigma[0], o.sigma[1], o.sigma[2], o.r_rms]
         return dict(zip(OBS_KEYS, vals))
@@ -525,7 +631,8 @@ class Context:
         s.e_incomp = _dptr(arrs["e_incomp"])
         s.e_qp = _dptr(arrs["e_qp"])
         o = gpe_obs()
-        gpe_observables(self._ctx, o, s)
+        with self._callbacks():
+            gpe_observables(self._ctx, o, s)
         arrs["dk"] = s.dk
         if with_obs:
             return arrs, dict(zip(OBS_KEYS, [o.norm, o.energy, o.mu, o.e_kin, o.e_pot, o.e_int,

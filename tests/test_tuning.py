@@ -119,3 +119,12 @@ def test_malformed_files_are_rejected_whole(tmp_path, text):
 def test_load_missing_file(tmp_path):
     with pytest.raises(gpe.GpeError):
         gpe.gpe_tuning_load(str(tmp_path / "none.json"))
+
+
+def test_separable_parameters_marshal_by_name():
+    """Host-side packing of the separable-potential parameters (no device)."""
+    s = gpe.fill_separable(gpe.gpe_separable(), dict(w=[1.0, 2.0], lattice=[0.5, 0.0, 3.0]))
+    assert list(s.w) == [1.0, 2.0, 0.0] and list(s.lattice) == [0.5, 0.0, 3.0]
+    assert list(s.center) == [0.0, 0.0, 0.0] and list(s.phase) == [0.0, 0.0, 0.0]
+    with pytest.raises(ValueError):
+        gpe.fill_separable(gpe.gpe_separable(), dict(omega=[1.0]))
