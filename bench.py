@@ -25,6 +25,7 @@ for scaling the FETCH_SIZE / WRITE_SIZE counters) and exits.
 import argparse
 import hashlib
 import json
+import math
 import os
 import sys
 import time
@@ -189,6 +190,43 @@ def ground_state_bench(torch):
                                              for r in series) / abs(series[0]["energy"])}}
 
 
+def potentials_bench(torch, dev, n, lo, hi, g, dt, steps=50):
+    """The real-time step at n^3 with V = 0, with a static separable potential
+    (trap, quartic, lattice on every axis: read from per-axis tables), and
+    with a time-dependent one (a shaken lattice: parameters from a Python
+    callback at every N-substep midpoint, tables rebuilt each step).  Device
+    time of `steps` steps from HIP events on the context stream."""
+    from paper_2301_08275_amd import gpe
+
+    stream = torch.cuda.current_stream()
+    L = hi[0] - lo[0]
+    static = dict(w=[0.3] * 3, center=[L / 2] * 3, quartic=[1e-3] * 3, lattice=[1.0] * 3,
+                  q=[2.0] * 3, phase=[0.0] * 3)
+
+    def shaken(t):
+        return dict(lattice=[1.0 + 0.5 * math.sin(10 * t)] * 3, q=[2.0] * 3,
+                    phase=[0.3 * t, 0.0, 0.0])
+
+    out = {"workload": "%d^3 turbulence state, FP64, dt = %g, %d steps per case" % (n, dt, steps)}
+    with gpe.Context((n,) * 3, lo, hi, g, stream=stream.cuda_stream,
+                     norm_target=L ** 3) as ctx:
+        for name, setup in (("no_potential", lambda: ctx.set_potential()),
+                            ("static_separable", lambda: ctx.set_separable(**static)),
+                            ("time_dependent", lambda: ctx.set_potential_fn(shaken))):
+            setup()
+            ctx.set_state_device(dev)
+            ctx.evolve(dt, 5)
+            e0 = torch.cuda.Event(enable_timing=True)
+            e1 = torch.cuda.Event(enable_timing=True)
+            torch.cuda.synchronize()
+            e0.record(stream)
+            ctx.evolve(dt, steps)
+            e1.record(stream)
+            torch.cuda.synchronize()
+            out[name + "_ms_per_step"] = e0.elapsed_time(e1) / steps
+    return out
+
+
 def serving_bench(nreq, max_slots, chunk):
     """The serving mix: requests arrive on a seeded Poisson stream (mean
     200/s); continuous batching through the request server against the same
@@ -271,6 +309,8 @@ def main():
     ap.add_argument("--no-ground-state", action="store_true",
                     help="skip the 256^3 ground state + trap-switch dynamics timing")
     ap.add_argument("--serving-chunk", type=int, default=16)
+    ap.add_argument("--no-potentials", action="store_true",
+                    help="skip the separable / time-dependent potential timing")
     args = ap.parse_args()
     if args.gpus != 1:
         print("bench.py measures one GPU: this build has no multi-GPU path "
@@ -324,6 +364,10 @@ def main():
         results[prec] = dict(ms=ms, kinds=kinds, nspec=nspec, dom=dominant(kinds))
         ctx.close()
         torch.cuda.synchronize()
+    potentials = None
+    if not args.no_potentials:
+        log("separable and time-dependent potentials")
+        potentials = potentials_bench(torch, dev, n, lo, hi, g, dt)
     del dev
     torch.cuda.empty_cache()
 
@@ -386,6 +430,8 @@ def main():
                              "frac": achs / HBM_PEAK_GBS,
                              "kernels": kernel_table(rs["kinds"]),
                              "tuning": tuning["fp32s"]}
+    if potentials is not None:
+        out["potentials"] = potentials
     if not args.no_ground_state:
         log("256^3 ground state and dynamics")
         out["ground_state_256"] = ground_state_bench(torch)
