@@ -227,6 +227,50 @@ def potentials_bench(torch, dev, n, lo, hi, g, dt, steps=50):
     return out
 
 
+def dynamics_validation_bench(n=256, dt=1e-3, t_end=4.0, every=10):
+    """The dynamics-validation run of the Results section: the 3D Gaussian
+    exp(-(x^2 + 2 y^2 + 4 z^2)/(2 eps1)), eps1 = 0.25, in
+    V = (x^2 + 4 y^2 + 16 z^2)/2 on [-8,8) x [-6,6) x [-4,4), n^3 points,
+    sigma_x,y,z recorded every `every` steps to t_end; g = 0.1 (the figure's
+    case) and g = 0 (closed form per axis: the largest deviation of sigma^2
+    is reported).  Wall time per step with the records (device-resident)."""
+    from paper_2301_08275_amd import gpe
+    from paper_2301_08275_amd import inputs as I
+
+    gam, eps1 = (1.0, 2.0, 4.0), 0.25
+    lo, hi = (-8.0, -6.0, -4.0), (8.0, 6.0, 4.0)
+    shape = (n,) * 3
+    nsteps = int(round(t_end / dt))
+    psi0 = I.gaussian(shape, lo, hi, widths=list(gam), eps=eps1)
+    out = {"workload": "%d^3 on [-8,8)x[-6,6)x[-4,4), gamma = (1, 2, 4), eps1 = 0.25, "
+                       "dt = %g, %d steps, sigma every %d" % (n, dt, nsteps, every)}
+    for g in (0.1, 0.0):
+        with gpe.Context(shape, lo, hi, g, harmonic=list(gam)) as ctx:
+            ctx.set_state(psi0)
+            ctx.synchronize()
+            t0 = time.perf_counter()
+            series = ctx.evolve_record(dt, nsteps, every)
+            t1 = time.perf_counter()
+        if g > 0:
+            per = max(1, len(series) // 4)
+            out["g0.1"] = {"ms_per_step": (t1 - t0) * 1e3 / nsteps,
+                           "sigma_at_t": {"%.1f" % ((k + 1) * every * dt):
+                                          [series[k]["sigma_x"], series[k]["sigma_y"],
+                                           series[k]["sigma_z"]]
+                                          for k in range(per - 1, len(series), per)}}
+        else:
+            worst = 0.0
+            for k, o in enumerate(series):
+                t = (k + 1) * every * dt
+                for a, key in enumerate(("sigma_x", "sigma_y", "sigma_z")):
+                    s2 = (eps1 / (2 * gam[a]) * math.cos(gam[a] * t) ** 2
+                          + 1 / (2 * eps1 * gam[a]) * math.sin(gam[a] * t) ** 2)
+                    worst = max(worst, abs(o[key] ** 2 - s2))
+            out["g0_closed_form_max_abs_error_sigma2"] = worst
+            out["g0_ms_per_step"] = (t1 - t0) * 1e3 / nsteps
+    return out
+
+
 def serving_bench(nreq, max_slots, chunk):
     """The serving mix: requests arrive on a seeded Poisson stream (mean
     200/s); continuous batching through the request server against the same
@@ -309,6 +353,8 @@ def main():
     ap.add_argument("--no-ground-state", action="store_true",
                     help="skip the 256^3 ground state + trap-switch dynamics timing")
     ap.add_argument("--serving-chunk", type=int, default=16)
+    ap.add_argument("--no-dynamics", action="store_true",
+                    help="skip the dynamics-validation (Gaussian breathing) timing")
     ap.add_argument("--no-potentials", action="store_true",
                     help="skip the separable / time-dependent potential timing")
     args = ap.parse_args()
@@ -432,6 +478,9 @@ def main():
                              "tuning": tuning["fp32s"]}
     if potentials is not None:
         out["potentials"] = potentials
+    if not args.no_dynamics:
+        log("dynamics-validation run")
+        out["dynamics_validation"] = dynamics_validation_bench()
     if not args.no_ground_state:
         log("256^3 ground state and dynamics")
         out["ground_state_256"] = ground_state_bench(torch)
