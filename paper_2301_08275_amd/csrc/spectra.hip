@@ -23,7 +23,9 @@ struct alignas(2 * sizeof(T)) cxs {
   T x, y;
 };
 
-__device__ __forceinline__ int mode_of(int i, int n) { return i < n / 2 ? i : i - n; }
+// Signed mode of index i on an n-point axis (the Nyquist index n/2 is
+// negative; an axis of one point, a missing axis of the 3D view, is mode 0).
+__device__ __forceinline__ int mode_of(int i, int n) { return i < (n + 1) / 2 ? i : i - n; }
 
 __device__ __forceinline__ int log2_of(int n) { return 31 - __clz(n); }
 

@@ -200,6 +200,7 @@ SPECTRA_CASES = [
     ((32, 32, 32), (0.0,) * 3, (2 * np.pi,) * 3),
     ((16, 8, 32), (0.0, -1.0, 0.0), (4.0, 1.0, 3.0)),
     ((64, 32), (-3.0, -2.0), (3.0, 2.0)),
+    ((32, 32), (-3.0, -3.0), (3.0, 3.0)),     # 2D with integer shells
     ((8, 8, 8), (0.0,) * 3, (2 * np.pi,) * 3),
 ]
 
