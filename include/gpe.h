@@ -4,14 +4,14 @@
  *
  *     i d/dt psi = -1/2 lap psi + V psi + g |psi|^2 psi
  *
- * on a periodic box, in 2D or 3D, with real-time dynamics and the
+ * on a periodic box, in 1D, 2D or 3D, with real-time dynamics and the
  * imaginary-time ground-state method of the same section.
  *
  * Conventions shared by every call
  * --------------------------------
  *  - Grid: x_{j,i} = lo[j] + i*h_j, h_j = (hi[j]-lo[j])/n[j], periodic.  Every
- *    n[j] is a power of two in [8, 1024].  dim is 2 or 3; for dim = 2 only
- *    n[0], n[1], lo[0..1], hi[0..1] are read.
+ *    n[j] is a power of two in [8, 1024].  dim is 1, 2 or 3; only the first
+ *    dim entries of n, lo and hi are read.
  *  - Layout: row-major over (n[0], n[1][, n[2]]), last axis contiguous,
  *    interleaved complex (re, im).  Host state buffers are FP64 whatever the
  *    context precision.
@@ -161,6 +161,22 @@ gpe_status gpe_set_separable(gpe_ctx *ctx, const gpe_separable *V);
  * removes the potential (V = 0).  Replaces any earlier potential. */
 typedef void (*gpe_potential_fn)(double t, gpe_separable *out, void *user);
 gpe_status gpe_set_potential_fn(gpe_ctx *ctx, gpe_potential_fn fn, void *user);
+
+/* The imaginary-time nonlinear substep of the ground-state method.  The
+ * paper gives no formula; GPE_IMAG_FROZEN (the default) applies
+ * exp(-(V + g|psi|^2) tau) with the density held at its value at the start
+ * of the substep (this reproduces the paper's Table 1 values at its dt; the
+ * chemical potential then carries an O(dt) bias).  GPE_IMAG_EXACT applies
+ * the exact solution of d psi/d tau = -(V + g|psi|^2) psi, a Bernoulli
+ * equation for |psi|^2:
+ *   psi <- psi e^{-V tau} / sqrt(1 + g |psi|^2 (1 - e^{-2 V tau}) / V)
+ * (2 tau in place of the fraction where V = 0), which leaves the splitting
+ * error O(dt^2) in mu as well.  With g < 0 the exact substep has no solution
+ * once g |psi|^2 (1 - e^{-2 V tau}) / V <= -1: the state turns non-finite.
+ * Other values: GPE_EINVAL.  Batched server requests use the default. */
+#define GPE_IMAG_FROZEN 0
+#define GPE_IMAG_EXACT 1
+gpe_status gpe_set_imag_method(gpe_ctx *ctx, int32_t method);
 
 /* The context clock: 0 at creation; real-time steps advance it by dt.  It
  * only matters for a time-dependent potential. */
@@ -336,7 +352,8 @@ gpe_status gpe_server_create(uint64_t hbm_budget_bytes, int32_t max_slots, int32
                              int32_t chunk_steps, gpe_server **out);
 
 /* Queue a request (validated now; GPE_EINVAL etc. on bad input, GPE_ENOMEM if
- * it could never fit the budget).  The initial state is copied.  *id names it. */
+ * it could never fit the budget, GPE_EUNSUPPORTED for dim = 1: the batched
+ * classes are 2D and 3D).  The initial state is copied.  *id names it. */
 gpe_status gpe_server_submit(gpe_server *srv, const gpe_request *req, uint64_t *id);
 
 /* GPE_EBUSY while the request is queued or running; otherwise fills *out and,

@@ -42,9 +42,10 @@ def _load():
     lib.orc_fft_axis.argtypes = [dp, c_int, ip, c_int, c_int]
     lib.orc_tssp_real.argtypes = [dp, c_int, ip, dp, dp, dp, c_double, c_double, c_long]
     lib.orc_tssp_imag.argtypes = [dp, c_int, ip, dp, dp, dp, c_double, c_double,
-                                  c_long, c_double]
+                                  c_long, c_double, c_int]
+    lib.orc_nonlinear_imag.argtypes = [dp, c_int, ip, dp, dp, dp, c_double, c_double, c_int]
     lib.orc_ground_state.argtypes = [dp, c_int, ip, dp, dp, dp, c_double, c_double,
-                                     c_double, c_int, c_long, c_double, lp, dp]
+                                     c_double, c_int, c_long, c_double, c_int, lp, dp]
     lib.orc_observables.argtypes = [dp, c_int, ip, dp, dp, dp, c_double, dp]
     lib.orc_nonlinear_real.argtypes = [dp, c_int, ip, dp, dp, dp, c_double, c_double]
     lib.orc_kinetic_real.argtypes = [dp, c_int, ip, dp, dp, c_double]
@@ -52,7 +53,8 @@ def _load():
     lib.orc_spectra.argtypes = [dp, c_int, ip, dp, dp, c_int, dp, dp, dp, dp]
     for f in (lib.orc_fft, lib.orc_fft_axis, lib.orc_tssp_real, lib.orc_tssp_imag,
               lib.orc_ground_state, lib.orc_observables, lib.orc_spectra_bins,
-              lib.orc_spectra, lib.orc_nonlinear_real, lib.orc_kinetic_real):
+              lib.orc_spectra, lib.orc_nonlinear_real, lib.orc_kinetic_real,
+              lib.orc_nonlinear_imag):
         f.restype = c_int
     _lib = lib
     return lib
@@ -176,7 +178,9 @@ def tssp_real_tdep(psi, lo, hi, Vfun, g, dt, nsteps, t0=0.0):
     return out
 
 
-def tssp_imag(psi, lo, hi, V, g, dt, nsteps, norm_target=1.0):
+def tssp_imag(psi, lo, hi, V, g, dt, nsteps, norm_target=1.0, exact=False):
+    """nsteps imaginary-time steps; exact: solve each N substep exactly
+    instead of holding the density at its start value."""
     lib = _load()
     out = _state(psi)
     dim, n = _shape(out)
@@ -184,13 +188,27 @@ def tssp_imag(psi, lo, hi, V, g, dt, nsteps, norm_target=1.0):
     V = _pot(V, out.shape)
     _check(lib.orc_tssp_imag(_dptr(out), dim, n, _dptr(lo), _dptr(hi),
                              _dptr(V) if V is not None else None,
-                             float(g), float(dt), int(nsteps), float(norm_target)),
+                             float(g), float(dt), int(nsteps), float(norm_target),
+                             int(bool(exact))),
            "tssp_imag")
     return out
 
 
+def nonlinear_imag(psi, lo, hi, V, g, tau, exact=False):
+    """One imaginary-time N(tau) substep."""
+    lib = _load()
+    out = _state(psi)
+    dim, n = _shape(out)
+    lo, hi = _box(lo, hi, dim)
+    V = _pot(V, out.shape)
+    _check(lib.orc_nonlinear_imag(_dptr(out), dim, n, _dptr(lo), _dptr(hi),
+                                  _dptr(V) if V is not None else None, float(g), float(tau),
+                                  int(bool(exact))), "nonlinear_imag")
+    return out
+
+
 def ground_state(psi, lo, hi, V, g, dt, tol=1e-10, check_every=10,
-                 max_steps=1000000, norm_target=1.0):
+                 max_steps=1000000, norm_target=1.0, exact=False):
     """Returns (psi, steps_done, energy, converged)."""
     lib = _load()
     out = _state(psi)
@@ -202,7 +220,7 @@ def ground_state(psi, lo, hi, V, g, dt, tol=1e-10, check_every=10,
     rc = _check(lib.orc_ground_state(_dptr(out), dim, n, _dptr(lo), _dptr(hi),
                                      _dptr(V) if V is not None else None,
                                      float(g), float(dt), float(tol), int(check_every),
-                                     int(max_steps), float(norm_target),
+                                     int(max_steps), float(norm_target), int(bool(exact)),
                                      ctypes.byref(steps), ctypes.byref(energy)),
                 "ground_state")
     return out, steps.value, energy.value, rc == 0

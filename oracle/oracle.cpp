@@ -245,6 +245,25 @@ void nonlinear_imag(cplx *psi, const Grid &G, const double *V, double g,
   });
 }
 
+/* Imaginary-time N(tau) solved exactly (the "exact" substep, an option: the
+ * paper does not fix the substep) for the potential V - shift:
+ * d psi/d tau = -(v + g|psi|^2) psi keeps the phase, and rho = |psi|^2 obeys
+ * the Bernoulli equation
+ *   d rho/d tau = -2 v rho - 2 g rho^2,
+ * whose solution through 1/rho gives
+ *   rho(tau) = rho0 e^{-2 v tau} / (1 + g rho0 (1 - e^{-2 v tau}) / v),
+ * with (1 - e^{-2 v tau}) / v -> 2 tau at v = 0. */
+void nonlinear_imag_exact(cplx *psi, const Grid &G, const double *V, double g,
+                          double tau, double shift) {
+  for_sites(G, [&](long s) {
+    double rho = std::norm(psi[s]);
+    double v = (V ? V[s] : 0.0) - shift;
+    double e = v != 0.0 ? -std::expm1(-2.0 * v * tau) / v : 2.0 * tau;
+    double rho_t = rho * std::exp(-2.0 * v * tau) / (1.0 + g * rho * e);
+    psi[s] *= (rho > 0.0 ? std::sqrt(rho_t / rho) : 0.0);
+  });
+}
+
 /* Imaginary-time K(dt): psi_hat <- exp(-|k|^2 dt / 2) psi_hat. */
 void kinetic_imag(cplx *psih, const Grid &G, double dt) {
   for_sites(G, [&](long s) { psih[s] *= std::exp(-k_squared(G, s) * dt / 2); });
@@ -264,16 +283,31 @@ void real_step(cplx *psi, const Grid &G, const double *V, double g, double dt) {
 }
 
 /* One imaginary-time step, then renormalisation to norm_target (the
- * wavefunction is normalised at every step of the ground-state method). */
+ * wavefunction is normalised at every step of the ground-state method).
+ * exact: the N substeps are solved exactly for V - mu, with mu a running
+ * estimate of the chemical potential (0 at the first step of a run, then
+ * mu += log(c) / dt from each step's renormalisation factor c): the norm then
+ * stays near its target inside a step, so the second substep sees the
+ * density of a normalised state; without the shift the state's decay within
+ * the step biases mu at first order in dt. */
 void imag_step(cplx *psi, const Grid &G, const double *V, double g, double dt,
-               double norm_target) {
-  nonlinear_imag(psi, G, V, g, dt / 2);
+               double norm_target, int exact, double *mu) {
+  if (exact) {
+    nonlinear_imag_exact(psi, G, V, g, dt / 2, *mu);
+  } else {
+    nonlinear_imag(psi, G, V, g, dt / 2);
+  }
   fft_all(psi, G, false);
   kinetic_imag(psi, G, dt);
   fft_all(psi, G, true);
-  nonlinear_imag(psi, G, V, g, dt / 2);
+  if (exact) {
+    nonlinear_imag_exact(psi, G, V, g, dt / 2, *mu);
+  } else {
+    nonlinear_imag(psi, G, V, g, dt / 2);
+  }
   double c = std::sqrt(norm_target / norm_of(psi, G));
   for_sites(G, [&](long s) { psi[s] *= c; });
+  if (exact) *mu += std::log(c) / dt;
 }
 
 /* ---------------------------------------------------------------------------
@@ -426,19 +460,33 @@ int orc_kinetic_real(double *psi, int dim, const int *n, const double *lo,
 
 int orc_tssp_imag(double *psi, int dim, const int *n, const double *lo,
                   const double *hi, const double *V, double g, double dt,
-                  long nsteps, double norm_target) {
+                  long nsteps, double norm_target, int exact) {
   Grid G;
   if (!psi || !make_grid(dim, n, lo, hi, G) || nsteps < 0 || !(norm_target > 0))
     return -1;
   cplx *p = reinterpret_cast<cplx *>(psi);
-  for (long t = 0; t < nsteps; ++t) imag_step(p, G, V, g, dt, norm_target);
+  double mu = 0.0;
+  for (long t = 0; t < nsteps; ++t) imag_step(p, G, V, g, dt, norm_target, exact, &mu);
+  return 0;
+}
+
+int orc_nonlinear_imag(double *psi, int dim, const int *n, const double *lo,
+                       const double *hi, const double *V, double g, double tau,
+                       int exact) {
+  Grid G;
+  if (!psi || !make_grid(dim, n, lo, hi, G)) return -1;
+  if (exact) {
+    nonlinear_imag_exact(reinterpret_cast<cplx *>(psi), G, V, g, tau, 0.0);
+  } else {
+    nonlinear_imag(reinterpret_cast<cplx *>(psi), G, V, g, tau);
+  }
   return 0;
 }
 
 int orc_ground_state(double *psi, int dim, const int *n, const double *lo,
                      const double *hi, const double *V, double g, double dt,
                      double tol, int check_every, long max_steps,
-                     double norm_target, long *steps_done, double *energy) {
+                     double norm_target, int exact, long *steps_done, double *energy) {
   Grid G;
   if (!psi || !make_grid(dim, n, lo, hi, G) || check_every < 1 || max_steps < 0 ||
       !(norm_target > 0))
@@ -447,8 +495,9 @@ int orc_ground_state(double *psi, int dim, const int *n, const double *lo,
   double e_prev = observe(p, G, V, g).energy;
   long t = 0;
   int rc = 1;
+  double mu = 0.0;
   while (t < max_steps) {
-    imag_step(p, G, V, g, dt, norm_target);
+    imag_step(p, G, V, g, dt, norm_target, exact, &mu);
     ++t;
     if (t % check_every == 0) {
       double e = observe(p, G, V, g).energy;

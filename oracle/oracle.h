@@ -50,10 +50,19 @@ int orc_nonlinear_real(double *psi, int dim, const int *n, const double *lo,
 int orc_kinetic_real(double *psi, int dim, const int *n, const double *lo,
                      const double *hi, double dt);
 
-/* nsteps imaginary-time steps, each renormalised to norm_target. */
+/* nsteps imaginary-time steps, each renormalised to norm_target.  exact = 0:
+ * the N substeps hold the density at its start value (frozen); 1: they solve
+ * d psi/d tau = -(V - mu + g|psi|^2) psi exactly, mu a running estimate of the
+ * chemical potential (0 at the start of the call, then += log(c)/dt after
+ * each step's renormalisation by c). */
 int orc_tssp_imag(double *psi, int dim, const int *n, const double *lo,
                   const double *hi, const double *V, double g, double dt,
-                  long nsteps, double norm_target);
+                  long nsteps, double norm_target, int exact);
+
+/* One imaginary-time N(tau) substep (exact as above, with mu = 0). */
+int orc_nonlinear_imag(double *psi, int dim, const int *n, const double *lo,
+                       const double *hi, const double *V, double g, double tau,
+                       int exact);
 
 /* Imaginary-time ground state: step until the energy, evaluated every
  * check_every steps, changes by less than tol (absolute) from the previous
@@ -62,7 +71,7 @@ int orc_tssp_imag(double *psi, int dim, const int *n, const double *lo,
 int orc_ground_state(double *psi, int dim, const int *n, const double *lo,
                      const double *hi, const double *V, double g, double dt,
                      double tol, int check_every, long max_steps,
-                     double norm_target, long *steps_done, double *energy);
+                     double norm_target, int exact, long *steps_done, double *energy);
 
 /* out[0..10] = norm, energy, mu, e_kin, e_pot, e_int, sigma_0, sigma_1,
  * sigma_2, r_rms, (unused axes give sigma 0). */

@@ -470,6 +470,12 @@ __device__ __forceinline__ cx<T> apply_phase(int op, cx<T> v, double V, double g
     sincos_phase(th, &s, &c);
     return {(T)(re * c + im * s), (T)(im * c - re * s)};
   }
+  if (op == PH_IMAG_EXACT) {
+    // rho = |psi|^2 obeys the Bernoulli equation d rho/d tau = -2 (V + g rho) rho
+    const double E = V != 0.0 ? -expm1(-2.0 * V * tau) / V : 2.0 * tau;
+    const double f = exp(-V * tau) / sqrt(1.0 + g * (re * re + im * im) * E);
+    return {(T)(re * f), (T)(im * f)};
+  }
   const double f = exp(-th);
   return {(T)(re * f), (T)(im * f)};
 }
@@ -555,10 +561,10 @@ axis_pass_kernel(const PassArgs a) {
   const int forward = G ? a.forward : 1;
   const int inverse = G ? a.inverse : (FWD || OBS ? 0 : 1);
   const int store = G ? a.store : (OBS ? 0 : 1);
-  int pre = G ? a.pre
-              : (MODE == MODE_PRE_REAL ? PH_REAL : MODE == MODE_PRE_IMAG ? PH_IMAG : PH_NONE);
-  int post = G ? a.post
-               : (MODE == MODE_POST_IMAG_RED ? PH_IMAG : DER ? PH_DERIV : PH_NONE);
+  // (the imaginary-time modes take the substep form, frozen-density or
+  // exact, from the arguments)
+  int pre = G || MODE == MODE_PRE_IMAG ? a.pre : (MODE == MODE_PRE_REAL ? PH_REAL : PH_NONE);
+  int post = G || MODE == MODE_POST_IMAG_RED ? a.post : (DER ? PH_DERIV : PH_NONE);
   const int mid = G ? a.mid : (FWD || OBS ? MID_NONE : MID_TABLE);
   const bool refwd = G ? a.refwd != 0 : DER;
   int red = G ? a.red
@@ -663,6 +669,7 @@ axis_pass_kernel(const PassArgs a) {
       }
     if (has_scale || pre != PH_NONE || (red & RED_REAL)) {
       const double sc = has_scale ? *pscale : 1.0;
+      const double mus = pre == PH_IMAG_EXACT && a.mu_shift ? *a.mu_shift : 0.0;
 #pragma unroll
       for (int b = 0; b < E / R0; ++b)
 #pragma unroll
@@ -684,7 +691,7 @@ axis_pass_kernel(const PassArgs a) {
             acc[kSlotReal + 4] += x1 * x1 * rho;
             acc[kSlotReal + 5] += x2 * x2 * rho;
           }
-          if (pre != PH_NONE) u = apply_phase(pre, u, V, g, tau_pre);
+          if (pre != PH_NONE) u = apply_phase(pre, u, V - mus, g, tau_pre);
           v[b * R0 + d] = u;
         }
     }
@@ -735,7 +742,8 @@ axis_pass_kernel(const PassArgs a) {
           } else if (post != PH_NONE) {
             const int k0 = axis == 0 ? p : j0, k1 = axis == 1 ? p : j1, k2 = axis == 2 ? p : j2;
             const double V = valid ? site_potential(a, vkind, hv, k0, k1, k2) : 0.0;
-            u = apply_phase(post, u, V, g, tau_post);
+            const double mus = post == PH_IMAG_EXACT && a.mu_shift ? *a.mu_shift : 0.0;
+            u = apply_phase(post, u, V - mus, g, tau_post);
           }
           if (red & RED_NORM_OUT) acc[kSlotNormOut] += (double)u.x * u.x + (double)u.y * u.y;
           v[b * R0 + d] = u;

@@ -47,8 +47,10 @@ int pick_mode(const PassArgs &a, const PassShape &sh) {
   if (a.refwd) return bare && a.post == PH_DERIV ? MODE_DERIV : MODE_GENERIC;
   if (a.pre == PH_NONE && a.post == PH_NONE && a.red == RED_NONE && !a.scale) return MODE_PLAIN;
   if (a.pre == PH_REAL && a.post == PH_NONE && a.red == RED_NONE && !a.scale) return MODE_PRE_REAL;
-  if (a.pre == PH_IMAG && a.post == PH_NONE && a.red == RED_NONE && a.scale) return MODE_PRE_IMAG;
-  if (a.pre == PH_NONE && a.post == PH_IMAG && a.red == RED_NORM_OUT && !a.scale)
+  const bool im_pre = a.pre == PH_IMAG || a.pre == PH_IMAG_EXACT;
+  const bool im_post = a.post == PH_IMAG || a.post == PH_IMAG_EXACT;
+  if (im_pre && a.post == PH_NONE && a.red == RED_NONE && a.scale) return MODE_PRE_IMAG;
+  if (a.pre == PH_NONE && im_post && a.red == RED_NORM_OUT && !a.scale)
     return MODE_POST_IMAG_RED;
   return MODE_GENERIC;
 }

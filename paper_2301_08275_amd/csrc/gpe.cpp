@@ -280,9 +280,9 @@ int order_axis(const gpe_ctx *c, int i) {
 
 gpe_status validate_desc(const gpe_desc *d, std::string &msg) {
   if (!d) { msg = "desc is NULL"; return GPE_EINVAL; }
-  if (d->dim != 2 && d->dim != 3) {
-    msg = "dim must be 2 or 3";
-    return d->dim == 1 ? GPE_EUNSUPPORTED : GPE_EINVAL;
+  if (d->dim < 1 || d->dim > 3) {
+    msg = "dim must be 1, 2 or 3";
+    return GPE_EINVAL;
   }
   for (int j = 0; j < d->dim; ++j) {
     if (d->n[j] < 1 || (d->n[j] & (d->n[j] - 1)) != 0) {
@@ -592,7 +592,7 @@ uint64_t context_bytes(const gpe_desc &d, bool with_state) {
   }
   return (with_state ? (uint64_t)sites * es : 0) +
          (uint64_t)gpe::kFinBlocks * gpe::kRedSlots * sizeof(double) + 3 * (uint64_t)maxb * gpe::kRedSlots * sizeof(double) +
-         4 * gpe::kRedSlots * sizeof(double) + sizeof(double) + tables;
+         4 * gpe::kRedSlots * sizeof(double) + 2 * sizeof(double) + tables;
 }
 
 }  // namespace gpe_host
@@ -682,7 +682,7 @@ gpe_status create_context(const gpe_desc *desc, const double *V_host, const gpe_
                    "partials allocation")) != GPE_OK) return bail(st);
   if ((st = dalloc(c, (void **)&c->sums, 4 * gpe::kRedSlots * sizeof(double),
                    "sums allocation")) != GPE_OK) return bail(st);
-  if ((st = dalloc(c, (void **)&c->scale, sizeof(double), "scale allocation")) != GPE_OK)
+  if ((st = dalloc(c, (void **)&c->scale, 2 * sizeof(double), "scale allocation")) != GPE_OK)
     return bail(st);
   if ((st = dalloc(c, (void **)&c->fin, gpe::kFinBlocks * gpe::kRedSlots * sizeof(double),
                    "finalize scratch allocation")) != GPE_OK)
@@ -735,6 +735,15 @@ gpe_status gpe_set_potential_fn(gpe_ctx *c, gpe_potential_fn fn, void *user) {
   c->vfn = fn;
   c->vfn_user = user;
   c->vtab_on = true;
+  return GPE_OK;
+}
+
+gpe_status gpe_set_imag_method(gpe_ctx *c, int32_t method) {
+  if (!c) return GPE_EINVAL;
+  if (method != GPE_IMAG_FROZEN && method != GPE_IMAG_EXACT)
+    return fail(c, GPE_EINVAL, "method must be GPE_IMAG_FROZEN or GPE_IMAG_EXACT");
+  drop_step_graphs(c);  // cached imaginary-time graphs hold the other substep
+  c->imag_method = method;
   return GPE_OK;
 }
 
@@ -850,13 +859,16 @@ gpe_status imag_step(gpe_ctx *c, void *const K[3], double dt) {
     gpe::PassArgs a = base_args(c, ax);
     a.mid = gpe::MID_TABLE;
     a.mtab = K[ax];
+    const bool exact = c->imag_method == GPE_IMAG_EXACT;
+    const int op = exact ? gpe::PH_IMAG_EXACT : gpe::PH_IMAG;
+    if (exact) a.mu_shift = c->scale + 1;
     if (i == 0) {
       a.scale = c->scale;
-      a.pre = gpe::PH_IMAG;
+      a.pre = op;
       a.tau_pre = dt / 2;
     }
     if (i == na - 1) {
-      a.post = gpe::PH_IMAG;
+      a.post = op;
       a.tau_post = dt / 2;
       a.red = gpe::RED_NORM_OUT;
       a.partial = c->partial;
@@ -866,7 +878,8 @@ gpe_status imag_step(gpe_ctx *c, void *const K[3], double dt) {
     if (i == na - 1) {
       const gpe::PassShape sh = gpe::pass_shape(c->prec, c->n3, ax, c->wreq[ax], c->plan[ax]);
       HIPCHK(c, gpe::launch_finalize(c->partial, sh.blocks, c->sums + 3 * gpe::kRedSlots,
-                                     c->scale, c->desc.norm_target, c->dV, c->stream, c->fin),
+                                     c->scale, c->desc.norm_target, c->dV, c->stream, c->fin,
+                                     exact ? dt : 0.0),
              "finalize launch");
     }
   }
@@ -1025,8 +1038,9 @@ gpe_status gpe_ground_state(gpe_ctx *c, double dt, double tol, int32_t check_eve
   // does not advance it)
   gpe_status vst = vtables_at(c, VAt{c->time, 1.0, 0.0, 0.0});
   if (vst != GPE_OK) return vst;
-  const double one = 1.0;
-  HIPCHK(c, hipMemcpyAsync(c->scale, &one, sizeof(double), hipMemcpyHostToDevice, c->stream),
+  // scale c = 1 and, for the exact substep, the chemical-potential shift 0
+  const double init[2] = {1.0, 0.0};
+  HIPCHK(c, hipMemcpyAsync(c->scale, init, sizeof(init), hipMemcpyHostToDevice, c->stream),
          "scale reset");
   double e_prev = NAN, e_last = NAN;
   if (check_every > 0) {

@@ -56,6 +56,7 @@ struct gpe_ctx {
   gpe_potential_fn vfn = nullptr;
   void *vfn_user = nullptr;
   double time = 0.0;           // context clock (real time)
+  int imag_method = GPE_IMAG_FROZEN;  // imaginary-time N substep
   double *partial = nullptr;   // per-workgroup partials, 3 regions
   long long partial_region = 0;  // doubles per region
   double *sums = nullptr;      // finalized sums, 4 x kRedSlots

@@ -15,6 +15,9 @@ enum PhaseOp : int {
   PH_IMAG = 2,  // psi <- exp(-(V + g|psi|^2) tau) psi   (pre: after psi <- c psi)
   PH_DERIV = 3, // post only: d = result, p = src at the site:
                 //   out = (Im(conj(p) d) + i Re(conj(p) d)) / |p|  (0 where p = 0)
+  PH_IMAG_EXACT = 4,  // the exact solution of d psi/d tau = -(V + g|psi|^2) psi:
+                      //   psi <- psi e^{-V tau} / sqrt(1 + g|psi|^2 E),
+                      //   E = (1 - e^{-2 V tau}) / V  (2 tau at V = 0)
 };
 
 enum MidOp : int {
@@ -78,6 +81,7 @@ struct PassArgs {
   const void *mtab;   // mid table (complex T, N entries) for MID_TABLE
   const double *kw;   // RED_KIN weights per frequency (N doubles)
   const double *scale;  // PH_IMAG pre: psi <- (*scale) psi (null: 1)
+  const double *mu_shift;  // PH_IMAG_EXACT: the substeps use V - *mu_shift (null: 0)
   double *partial;      // reductions, kRedSlots doubles per workgroup
   // batched shape class (MODE_SLOTS): per-slot state and operations
   Slot *slots;
@@ -109,14 +113,16 @@ hipError_t launch_axis_pass(int precision, const PassArgs &a, hipStream_t s);
 
 // Sum `count` partial blocks of kRedSlots doubles in fixed order into
 // out[kRedSlots] (device), optionally deriving the imaginary-time scale:
-// if scale_out != null: *scale_out = sqrt(norm_target / (dV * sum slot 0)).
+// if scale_out != null: scale_out[0] = c = sqrt(norm_target / (dV * sum slot 0)),
+// and if shift_dt != 0 also scale_out[1] += log(c) / shift_dt (the running
+// chemical-potential shift of the exact imaginary-time substep).
 // With scratch (>= kFinBlocks * kRedSlots doubles, device) and many blocks,
 // the sum runs in two fixed-order stages (kFinBlocks workgroups over fixed
 // row ranges, then one over their results): same determinism, less latency.
 constexpr int kFinBlocks = 64;
 hipError_t launch_finalize(const double *partial, long long count, double *out,
                            double *scale_out, double norm_target, double dV,
-                           hipStream_t s, double *scratch = nullptr);
+                           hipStream_t s, double *scratch = nullptr, double shift_dt = 0.0);
 
 // psi <- c psi (c read from device), precision 0/1; sets *c = 1 afterwards.
 hipError_t launch_scale(int precision, void *psi, long long sites, double *c,

@@ -16,7 +16,7 @@ constexpr int kFinThreads = 256;
 __global__ void __launch_bounds__(kFinThreads)
 finalize_kernel(const double *__restrict__ partial, long long count,
                 double *__restrict__ out, double *__restrict__ scale_out,
-                double norm_target, double dV) {
+                double norm_target, double dV, double shift_dt) {
   __shared__ double s[kRedSlots][kFinThreads];
   const int tid = threadIdx.x;
   double acc[kRedSlots];
@@ -37,7 +37,11 @@ finalize_kernel(const double *__restrict__ partial, long long count,
     __syncthreads();
   }
   if (tid < kRedSlots) out[tid] = s[tid][0];
-  if (tid == 0 && scale_out) scale_out[0] = sqrt(norm_target / (dV * s[0][0]));
+  if (tid == 0 && scale_out) {
+    const double c = sqrt(norm_target / (dV * s[0][0]));
+    scale_out[0] = c;
+    if (shift_dt != 0.0) scale_out[1] += log(c) / shift_dt;
+  }
 }
 
 // First stage of a two-stage finalize: workgroup b adds rows
@@ -147,18 +151,18 @@ unsigned grid_for(long long n, int threads) {
 
 hipError_t launch_finalize(const double *partial, long long count, double *out,
                            double *scale_out, double norm_target, double dV,
-                           hipStream_t s, double *scratch) {
+                           hipStream_t s, double *scratch, double shift_dt) {
   if (scratch && count > 4 * kFinThreads) {
     const long long chunk = (count + kFinBlocks - 1) / kFinBlocks;
     const int blocks = (int)((count + chunk - 1) / chunk);
     hipLaunchKernelGGL(finalize_part_kernel, dim3(blocks), dim3(kFinThreads), 0, s, partial,
                        count, chunk, scratch);
     hipLaunchKernelGGL(finalize_kernel, dim3(1), dim3(kFinThreads), 0, s, scratch,
-                       (long long)blocks, out, scale_out, norm_target, dV);
+                       (long long)blocks, out, scale_out, norm_target, dV, shift_dt);
     return hipGetLastError();
   }
   hipLaunchKernelGGL(finalize_kernel, dim3(1), dim3(kFinThreads), 0, s, partial, count,
-                     out, scale_out, norm_target, dV);
+                     out, scale_out, norm_target, dV, shift_dt);
   return hipGetLastError();
 }
 

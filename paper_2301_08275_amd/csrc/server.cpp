@@ -743,6 +743,7 @@ gpe_status gpe_server_create(uint64_t hbm_budget_bytes, int32_t max_slots, int32
 gpe_status gpe_server_submit(gpe_server *s, const gpe_request *req, uint64_t *id) {
   if (!s || !req || !id || !req->psi0) return GPE_EINVAL;
   const gpe_desc &d = req->desc;
+  if (d.dim == 1) return GPE_EUNSUPPORTED;  // batched classes are 2D and 3D
   if (d.dim != 2 && d.dim != 3) return GPE_EINVAL;
   for (int j = 0; j < d.dim; ++j) {
     if (d.n[j] < 8 || d.n[j] > 1024 || (d.n[j] & (d.n[j] - 1))) return GPE_EUNSUPPORTED;
@@ -826,7 +827,8 @@ gpe_status gpe_server_wait_idle(gpe_server *s) {
 
 gpe_status gpe_request_bytes(const gpe_desc *desc, int32_t max_slots, uint64_t *class_b,
                              uint64_t *slot_b) {
-  if (!desc || max_slots < 1 || (desc->dim != 2 && desc->dim != 3)) return GPE_EINVAL;
+  if (!desc || max_slots < 1 || desc->dim < 1 || desc->dim > 3) return GPE_EINVAL;
+  if (desc->dim == 1) return GPE_EUNSUPPORTED;
   for (int j = 0; j < desc->dim; ++j)
     if (desc->n[j] < 8 || desc->n[j] > 1024 || (desc->n[j] & (desc->n[j] - 1)))
       return GPE_EUNSUPPORTED;

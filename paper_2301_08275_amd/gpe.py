@@ -139,6 +139,7 @@ SIGNATURES = {
     "gpe_set_separable": (_I32, [_P, ctypes.POINTER(gpe_separable)]),
     "gpe_set_potential_fn": (_I32, [_P, POTENTIAL_FN, _P]),
     "gpe_set_time": (_I32, [_P, _D]),
+    "gpe_set_imag_method": (_I32, [_P, _I32]),
     "gpe_get_time": (_I32, [_P, _DP]),
     "gpe_set_state": (_I32, [_P, _DP]),
     "gpe_set_state_device": (_I32, [_P, _P, _I32]),
@@ -242,6 +243,14 @@ def gpe_set_potential_fn(ctx, fn, user=None):
     """fn: a POTENTIAL_FN (or None); the caller keeps it alive while set."""
     return _check(load_library().gpe_set_potential_fn(
         ctx, fn if fn is not None else POTENTIAL_FN(), user), ctx)
+
+
+GPE_IMAG_FROZEN, GPE_IMAG_EXACT = 0, 1
+IMAG_METHODS = {"frozen": GPE_IMAG_FROZEN, "exact": GPE_IMAG_EXACT}
+
+
+def gpe_set_imag_method(ctx, method):
+    return _check(load_library().gpe_set_imag_method(ctx, int(method)), ctx)
 
 
 def gpe_set_time(ctx, t):
@@ -552,6 +561,14 @@ class Context:
                 self._vfn[1].clear()
                 raise e from err
             raise
+
+    def set_imag_method(self, method):
+        """Imaginary-time nonlinear substep: "frozen" (density held at the
+        substep's start, the default) or "exact" (Bernoulli solution with a
+        running chemical-potential shift; mu then has no first-order dt bias)."""
+        if method not in IMAG_METHODS:
+            raise ValueError("method must be one of %s" % sorted(IMAG_METHODS))
+        gpe_set_imag_method(self._ctx, IMAG_METHODS[method])
 
     @property
     def time(self):

@@ -457,3 +457,70 @@ def test_time_dependent_stepper_with_a_constant_potential_is_the_plain_one():
     a = oracle.tssp_real(psi0, lo, hi, V, 5.0, 1e-3, 20)
     b = oracle.tssp_real_tdep(psi0, lo, hi, lambda t: V, 5.0, 1e-3, 20)
     assert np.max(np.abs(a - b)) < 1e-15
+
+
+# ------------------------------------------- exact imaginary-time substep ---
+
+
+def test_exact_imaginary_substep_solves_the_bernoulli_equation():
+    """The exact N substep against an adaptive high-order ODE integration of
+    d rho/d tau = -2 (V + g rho) rho at sites with V of both signs, tiny and
+    large; the phase is unchanged."""
+    from scipy.integrate import solve_ivp
+
+    Vs = np.array([0.0, 0.5, 3.0, -0.2, 1e-9, 7.0, 0.01, -1.0])
+    rho0 = np.array([0.8, 1.5, 0.3, 2.0, 1.1, 0.05, 3.0, 0.2])
+    g, tau = 2.5, 0.05
+    psi = np.sqrt(rho0) * np.exp(1j * np.arange(8))
+    out = oracle.nonlinear_imag(psi, (0.0,), (1.0,), Vs, g, tau, exact=True)
+    for k in range(8):
+        sol = solve_ivp(lambda t, r: -2 * (Vs[k] + g * r) * r, (0, tau), [rho0[k]],
+                        rtol=1e-13, atol=1e-16, method="DOP853")
+        assert abs(abs(out[k]) ** 2 / sol.y[0, -1] - 1) < 1e-12, k
+        assert abs(np.angle(out[k] * np.exp(-1j * k))) < 1e-14
+
+
+def scf_chemical_potential(n, L, g):
+    """mu of the discrete stationary GPE -1/2 psi'' + (x^2/2 + g|psi|^2) psi =
+    mu psi (Fourier-grid kinetic matrix, the same discretisation as the
+    spectral step) by damped self-consistent-field iteration with a dense
+    eigensolver: no time stepping involved."""
+    h = L / n
+    x = -L / 2 + np.arange(n) * h
+    k = 2 * np.pi * np.fft.fftfreq(n, d=h)
+    F = np.fft.fft(np.eye(n), axis=0)
+    T = (np.conj(F).T @ np.diag(0.5 * k * k) @ F).real / n
+    V = 0.5 * x * x
+    rho = np.exp(-x * x) / np.sqrt(np.pi)
+    for _ in range(5000):
+        u = np.linalg.eigh(T + np.diag(V + g * rho))[1][:, 0]
+        new = u * u / (np.sum(u * u) * h)
+        if np.max(np.abs(new - rho)) < 1e-14:
+            break
+        rho = 0.9 * rho + 0.1 * new
+    psi = np.sqrt(rho)
+    return float(psi @ (T + np.diag(V + g * rho)) @ psi / np.sum(rho))
+
+
+def test_exact_substep_removes_the_first_order_mu_bias():
+    """Reading of the imaginary-time substep: the frozen-density substep leaves
+    mu biased at first order in dt (quarter dt, quarter bias); the exact
+    substep with the running chemical-potential shift converges to the
+    stationary state of the discrete GPE (self-consistent-field reference)
+    up to a small second-order error."""
+    n, L, g = 128, 20.0, 10.0
+    lo, hi = (-L / 2,), (L / 2,)
+    x = lo[0] + np.arange(n) * L / n
+    V = 0.5 * x * x
+    psi0 = np.exp(-x * x / 2) + 0j
+    mu_ref = scf_chemical_potential(n, L, g)
+    bias = {}
+    for exact in (False, True):
+        for dt in (4e-3, 1e-3):
+            psi, _, _, conv = oracle.ground_state(psi0, lo, hi, V, g, dt, tol=1e-15,
+                                                  max_steps=400000, exact=exact)
+            assert conv
+            bias[exact, dt] = oracle.observables(psi, lo, hi, V, g)["mu"] - mu_ref
+    assert bias[False, 4e-3] > 1e-3
+    assert abs(bias[False, 4e-3] / bias[False, 1e-3] - 4) < 0.4
+    assert abs(bias[True, 4e-3]) < 1e-6 and abs(bias[True, 1e-3]) < 3e-7
