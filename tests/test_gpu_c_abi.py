@@ -30,3 +30,42 @@ def test_c_program_through_the_abi(tmp_path):
     # Table 1, 2D, g = 12.5484: mu = 2.25609 (this scheme at dt = 1e-3: 2.25610)
     assert abs(float(mu) / 2.25609 - 1) < 1e-4
     assert abs(float(norm) - 1) < 1e-12
+
+
+def test_c_program_with_potentials_and_the_exact_substep(tmp_path):
+    """A C program using the time-dependent potential callback (1D moving
+    trap: Kohn's closed form), the exact imaginary-time substep (mu against
+    the oracle) and a static lattice (Mathieu ground-state energy)."""
+    import math
+
+    import numpy as np
+    from scipy.special import mathieu_a
+
+    import oracle
+
+    exe = str(tmp_path / "potentials_demo")
+    libdir = os.path.dirname(gpe.LIB_PATH)
+    cmd = ["gcc", "-std=c99", "-O2", os.path.join(ROOT, "tests", "c", "potentials_demo.c"),
+           "-I", os.path.join(ROOT, "include"), "-L", libdir, "-lgpe",
+           "-Wl,-rpath," + libdir, "-lm", "-o", exe]
+    r = subprocess.run(cmd, capture_output=True, text=True)
+    assert r.returncode == 0, r.stderr
+    print("running", exe, flush=True)
+    r = subprocess.run([exe], capture_output=True, text=True, timeout=120)
+    assert r.returncode == 0, (r.stdout, r.stderr)
+    lines = r.stdout.split("\n")
+    X, Xk = map(float, lines[0].split())
+    mu_exact = float(lines[1])
+    e_lattice = float(lines[2])
+    assert abs(X - Xk) < 1e-6
+    n, lo, hi = 128, (-10.0,), (10.0,)
+    x = lo[0] + np.arange(n) * 20.0 / n
+    psi, _, _, _ = oracle.ground_state(np.exp(-x * x / 2) + 0j, lo, hi, 0.5 * x * x, 10.0,
+                                       4e-3, tol=1e-15, max_steps=400000, exact=True)
+    mu_ref = oracle.observables(psi, lo, hi, 0.5 * x * x, 10.0)["mu"]
+    # both stop once E changes by < 1e-15 between checks; E is quadratic in the
+    # state's error but mu is linear in it, so stopping a few checks apart
+    # leaves ~1e-8 between the two mu values
+    assert abs(mu_exact - mu_ref) < 2e-8
+    assert abs(e_lattice - (1.0 + 0.5 * mathieu_a(0, 1.0))) < 1e-9
+    assert math.isfinite(e_lattice)
