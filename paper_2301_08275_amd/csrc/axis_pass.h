@@ -536,6 +536,8 @@ enum PassMode : int {
                            // state (PH_DERIV), forward again, store
   MODE_OBS = 9,            // forward only, kinetic sum, nothing stored
   MODE_OBS_REAL = 10,      // the same plus the real-space sums of the input
+  MODE_PRE_IMAG_EXACT = 11,       // MODE_PRE_IMAG with the exact substep
+  MODE_POST_IMAG_RED_EXACT = 12,  // MODE_POST_IMAG_RED with the exact substep
 };
 
 // Storage type of the state in HBM, converted on load and store: the
@@ -561,18 +563,20 @@ axis_pass_kernel(const PassArgs a) {
   const int forward = G ? a.forward : 1;
   const int inverse = G ? a.inverse : (FWD || OBS ? 0 : 1);
   const int store = G ? a.store : (OBS ? 0 : 1);
-  // (the imaginary-time modes take the substep form, frozen-density or
-  // exact, from the arguments)
-  int pre = G || MODE == MODE_PRE_IMAG ? a.pre : (MODE == MODE_PRE_REAL ? PH_REAL : PH_NONE);
-  int post = G || MODE == MODE_POST_IMAG_RED ? a.post : (DER ? PH_DERIV : PH_NONE);
+  constexpr bool PRE_IM = MODE == MODE_PRE_IMAG || MODE == MODE_PRE_IMAG_EXACT;
+  constexpr bool POST_IM = MODE == MODE_POST_IMAG_RED || MODE == MODE_POST_IMAG_RED_EXACT;
+  constexpr bool EXACT = MODE == MODE_PRE_IMAG_EXACT || MODE == MODE_POST_IMAG_RED_EXACT;
+  constexpr int IM_OP = EXACT ? PH_IMAG_EXACT : PH_IMAG;
+  int pre = G ? a.pre : (MODE == MODE_PRE_REAL ? PH_REAL : PRE_IM ? IM_OP : PH_NONE);
+  int post = G ? a.post : (POST_IM ? IM_OP : DER ? PH_DERIV : PH_NONE);
   const int mid = G ? a.mid : (FWD || OBS ? MID_NONE : MID_TABLE);
   const bool refwd = G ? a.refwd != 0 : DER;
   int red = G ? a.red
-              : (MODE == MODE_POST_IMAG_RED ? RED_NORM_OUT
+              : (POST_IM                    ? RED_NORM_OUT
                  : MODE == MODE_OBS         ? RED_KIN
                  : MODE == MODE_OBS_REAL    ? (RED_KIN | RED_REAL)
                                             : RED_NONE);
-  bool has_scale = G || OBS ? a.scale != nullptr : MODE == MODE_PRE_IMAG;
+  bool has_scale = G || OBS ? a.scale != nullptr : PRE_IM;
   // Per-block parameters: from the arguments, or (batched) from this block's slot.
   const void *psrc = a.src;
   void *pdst = a.dst;
@@ -669,7 +673,8 @@ axis_pass_kernel(const PassArgs a) {
       }
     if (has_scale || pre != PH_NONE || (red & RED_REAL)) {
       const double sc = has_scale ? *pscale : 1.0;
-      const double mus = pre == PH_IMAG_EXACT && a.mu_shift ? *a.mu_shift : 0.0;
+      const double mus =
+          (G || EXACT) && pre == PH_IMAG_EXACT && a.mu_shift ? *a.mu_shift : 0.0;
 #pragma unroll
       for (int b = 0; b < E / R0; ++b)
 #pragma unroll
@@ -742,7 +747,8 @@ axis_pass_kernel(const PassArgs a) {
           } else if (post != PH_NONE) {
             const int k0 = axis == 0 ? p : j0, k1 = axis == 1 ? p : j1, k2 = axis == 2 ? p : j2;
             const double V = valid ? site_potential(a, vkind, hv, k0, k1, k2) : 0.0;
-            const double mus = post == PH_IMAG_EXACT && a.mu_shift ? *a.mu_shift : 0.0;
+            const double mus =
+                (G || EXACT) && post == PH_IMAG_EXACT && a.mu_shift ? *a.mu_shift : 0.0;
             u = apply_phase(post, u, V - mus, g, tau_post);
           }
           if (red & RED_NORM_OUT) acc[kSlotNormOut] += (double)u.x * u.x + (double)u.y * u.y;
@@ -833,6 +839,14 @@ void launch_mode(const PassArgs &a, int mode, dim3 grid, dim3 block, hipStream_t
     case MODE_OBS:
       hipLaunchKernelGGL((axis_pass_kernel<T, PL, W, STRIDED, MODE_OBS, SX>), grid, block, 0, s,
                          a);
+      break;
+    case MODE_PRE_IMAG_EXACT:
+      hipLaunchKernelGGL((axis_pass_kernel<T, PL, W, STRIDED, MODE_PRE_IMAG_EXACT, SX>), grid,
+                         block, 0, s, a);
+      break;
+    case MODE_POST_IMAG_RED_EXACT:
+      hipLaunchKernelGGL((axis_pass_kernel<T, PL, W, STRIDED, MODE_POST_IMAG_RED_EXACT, SX>),
+                         grid, block, 0, s, a);
       break;
     case MODE_OBS_REAL:
       hipLaunchKernelGGL((axis_pass_kernel<T, PL, W, STRIDED, MODE_OBS_REAL, SX>), grid, block, 0,

@@ -49,9 +49,10 @@ int pick_mode(const PassArgs &a, const PassShape &sh) {
   if (a.pre == PH_REAL && a.post == PH_NONE && a.red == RED_NONE && !a.scale) return MODE_PRE_REAL;
   const bool im_pre = a.pre == PH_IMAG || a.pre == PH_IMAG_EXACT;
   const bool im_post = a.post == PH_IMAG || a.post == PH_IMAG_EXACT;
-  if (im_pre && a.post == PH_NONE && a.red == RED_NONE && a.scale) return MODE_PRE_IMAG;
+  if (im_pre && a.post == PH_NONE && a.red == RED_NONE && a.scale)
+    return a.pre == PH_IMAG ? MODE_PRE_IMAG : MODE_PRE_IMAG_EXACT;
   if (a.pre == PH_NONE && im_post && a.red == RED_NORM_OUT && !a.scale)
-    return MODE_POST_IMAG_RED;
+    return a.post == PH_IMAG ? MODE_POST_IMAG_RED : MODE_POST_IMAG_RED_EXACT;
   return MODE_GENERIC;
 }
 
