@@ -538,6 +538,7 @@ enum PassMode : int {
   MODE_OBS_REAL = 10,      // the same plus the real-space sums of the input
   MODE_PRE_IMAG_EXACT = 11,       // MODE_PRE_IMAG with the exact substep
   MODE_POST_IMAG_RED_EXACT = 12,  // MODE_POST_IMAG_RED with the exact substep
+  MODE_POST_REAL = 13,     // forward, table, inverse, closing real-time phase
 };
 
 // Storage type of the state in HBM, converted on load and store: the
@@ -568,7 +569,8 @@ axis_pass_kernel(const PassArgs a) {
   constexpr bool EXACT = MODE == MODE_PRE_IMAG_EXACT || MODE == MODE_POST_IMAG_RED_EXACT;
   constexpr int IM_OP = EXACT ? PH_IMAG_EXACT : PH_IMAG;
   int pre = G ? a.pre : (MODE == MODE_PRE_REAL ? PH_REAL : PRE_IM ? IM_OP : PH_NONE);
-  int post = G ? a.post : (POST_IM ? IM_OP : DER ? PH_DERIV : PH_NONE);
+  int post = G ? a.post
+               : (POST_IM ? IM_OP : DER ? PH_DERIV : MODE == MODE_POST_REAL ? PH_REAL : PH_NONE);
   const int mid = G ? a.mid : (FWD || OBS ? MID_NONE : MID_TABLE);
   const bool refwd = G ? a.refwd != 0 : DER;
   int red = G ? a.red
@@ -847,6 +849,10 @@ void launch_mode(const PassArgs &a, int mode, dim3 grid, dim3 block, hipStream_t
     case MODE_POST_IMAG_RED_EXACT:
       hipLaunchKernelGGL((axis_pass_kernel<T, PL, W, STRIDED, MODE_POST_IMAG_RED_EXACT, SX>),
                          grid, block, 0, s, a);
+      break;
+    case MODE_POST_REAL:
+      hipLaunchKernelGGL((axis_pass_kernel<T, PL, W, STRIDED, MODE_POST_REAL, SX>), grid, block,
+                         0, s, a);
       break;
     case MODE_OBS_REAL:
       hipLaunchKernelGGL((axis_pass_kernel<T, PL, W, STRIDED, MODE_OBS_REAL, SX>), grid, block, 0,

@@ -26,7 +26,8 @@ int tpl_of(int N, int plan) {
 namespace {
 
 // The specialised kernels assume full tiles and one of the standard pass
-// layouts (the step passes: forward, per-frequency table, inverse, store;
+// layouts (the step passes: forward, per-frequency table, inverse, store,
+// with the opening or closing phase;
 // forward-only transforms; the spectral-derivative pass; the observables'
 // forward passes); anything else runs generic.
 int pick_mode(const PassArgs &a, const PassShape &sh) {
@@ -47,6 +48,7 @@ int pick_mode(const PassArgs &a, const PassShape &sh) {
   if (a.refwd) return bare && a.post == PH_DERIV ? MODE_DERIV : MODE_GENERIC;
   if (a.pre == PH_NONE && a.post == PH_NONE && a.red == RED_NONE && !a.scale) return MODE_PLAIN;
   if (a.pre == PH_REAL && a.post == PH_NONE && a.red == RED_NONE && !a.scale) return MODE_PRE_REAL;
+  if (a.pre == PH_NONE && a.post == PH_REAL && a.red == RED_NONE && !a.scale) return MODE_POST_REAL;
   const bool im_pre = a.pre == PH_IMAG || a.pre == PH_IMAG_EXACT;
   const bool im_post = a.post == PH_IMAG || a.post == PH_IMAG_EXACT;
   if (im_pre && a.post == PH_NONE && a.red == RED_NONE && a.scale)
