@@ -279,12 +279,15 @@ typedef struct {
   int32_t plan[3];        /* radix plan per axis: 0 default; 1 the alternative (1024
                              points only: stages 8, 8, 8, 2 with 8 points per thread
                              instead of 16, 8, 8 with 16) */
+  int32_t stream[3];      /* per axis: 1 = the step passes load and store with the
+                             non-temporal (streaming) cache policy */
   double ms_per_step;     /* measured real-time step (gpe_autotune), else 0 */
 } gpe_tuning;             /* entries beyond dim (and width/xcd_remap of the last axis) are 0 */
 
 /* Time the real-time step of this shape class on the current device for
- * every radix plan, width and tile order of each axis, then for every pass order
- * (coordinate descent from the current entry or the defaults; `steps` timed
+ * every radix plan, width and tile order of each axis, then for every pass
+ * order, then the streaming flag of each axis (coordinate descent from the
+ * current entry or the defaults; `steps` timed
  * steps per candidate, the minimum of three runs; a candidate must be more
  * than 1% faster than the incumbent to replace it), record the result in the
  * table and copy it to *out (nullable).  Allocates a scratch context of the

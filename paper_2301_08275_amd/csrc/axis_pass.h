@@ -52,6 +52,21 @@ struct alignas(2 * sizeof(T)) cx {
   T x, y;
 };
 
+// Non-temporal (streaming) element load and store: the cache policy of a
+// pass that touches each element once; the values are unchanged.
+template <typename S>
+__device__ __forceinline__ cx<S> load_stream(const cx<S> *p) {
+  typedef S v2 __attribute__((ext_vector_type(2)));
+  const v2 w = __builtin_nontemporal_load(reinterpret_cast<const v2 *>(p));
+  return cx<S>{w.x, w.y};
+}
+template <typename S>
+__device__ __forceinline__ void store_stream(cx<S> *p, cx<S> v) {
+  typedef S v2 __attribute__((ext_vector_type(2)));
+  const v2 w = {v.x, v.y};
+  __builtin_nontemporal_store(w, reinterpret_cast<v2 *>(p));
+}
+
 // Table entries: FP64 tables hold the complex factor.  FP32 tables hold it as
 // a hi + lo pair of FP32 complex numbers (x, y = hi; z, w = lo), and the
 // product is formed by one chain of FMAs before a single rounding, so every
@@ -539,7 +554,13 @@ enum PassMode : int {
   MODE_PRE_IMAG_EXACT = 11,       // MODE_PRE_IMAG with the exact substep
   MODE_POST_IMAG_RED_EXACT = 12,  // MODE_POST_IMAG_RED with the exact substep
   MODE_POST_REAL = 13,     // forward, table, inverse, closing real-time phase
+  MODE_PLAIN_STREAM = 14,     // MODE_PLAIN with streaming loads and stores
+  MODE_PRE_REAL_STREAM = 15,  // MODE_PRE_REAL with streaming loads and stores
 };
+
+__host__ __device__ constexpr int base_mode(int m) {
+  return m == MODE_PLAIN_STREAM ? MODE_PLAIN : m == MODE_PRE_REAL_STREAM ? MODE_PRE_REAL : m;
+}
 
 // Storage type of the state in HBM, converted on load and store: the
 // arithmetic type T, or FP32 storage with FP64 arithmetic (SX = float,
@@ -549,9 +570,11 @@ __device__ __forceinline__ cx<T> cvt(const cx<SX> &u) {
   return {(T)u.x, (T)u.y};
 }
 
-template <typename T, class PL, int W, bool STRIDED, int MODE, typename SX = T>
+template <typename T, class PL, int W, bool STRIDED, int MODE_ARG, typename SX = T>
 __global__ void __launch_bounds__(PL::TPL * W)
 axis_pass_kernel(const PassArgs a) {
+  constexpr int MODE = base_mode(MODE_ARG);
+  constexpr bool STREAM = MODE != MODE_ARG;  // streaming loads and stores
   constexpr int N = PL::N, E = PL::E, TPL = PL::TPL;
   using L = Lds<N, W, STRIDED>;
   __shared__ T lre[PL::M > 1 ? L::size : 1], lim[PL::M > 1 ? L::size : 1];
@@ -671,7 +694,8 @@ axis_pass_kernel(const PassArgs a) {
 #pragma unroll
       for (int d = 0; d < R0; ++d) {
         const int p = PL::pos(0, t + TPL * b, d);
-        v[b * R0 + d] = valid ? cvt<T>(src[base + p * S]) : cx<T>{0, 0};
+        if constexpr (STREAM) v[b * R0 + d] = cvt<T>(load_stream(&src[base + p * S]));
+        else v[b * R0 + d] = valid ? cvt<T>(src[base + p * S]) : cx<T>{0, 0};
       }
     if (has_scale || pre != PH_NONE || (red & RED_REAL)) {
       const double sc = has_scale ? *pscale : 1.0;
@@ -776,7 +800,8 @@ axis_pass_kernel(const PassArgs a) {
 #pragma unroll
         for (int d = 0; d < R0; ++d) {
           const int p = PL::pos(0, t + TPL * b, d);
-          dst[base + p * S] = cvt<SX>(v[b * R0 + d]);
+          if constexpr (STREAM) store_stream(&dst[base + p * S], cvt<SX>(v[b * R0 + d]));
+          else dst[base + p * S] = cvt<SX>(v[b * R0 + d]);
         }
     }
   }
@@ -849,6 +874,14 @@ void launch_mode(const PassArgs &a, int mode, dim3 grid, dim3 block, hipStream_t
     case MODE_POST_IMAG_RED_EXACT:
       hipLaunchKernelGGL((axis_pass_kernel<T, PL, W, STRIDED, MODE_POST_IMAG_RED_EXACT, SX>),
                          grid, block, 0, s, a);
+      break;
+    case MODE_PLAIN_STREAM:
+      hipLaunchKernelGGL((axis_pass_kernel<T, PL, W, STRIDED, MODE_PLAIN_STREAM, SX>), grid, block,
+                         0, s, a);
+      break;
+    case MODE_PRE_REAL_STREAM:
+      hipLaunchKernelGGL((axis_pass_kernel<T, PL, W, STRIDED, MODE_PRE_REAL_STREAM, SX>), grid,
+                         block, 0, s, a);
       break;
     case MODE_POST_REAL:
       hipLaunchKernelGGL((axis_pass_kernel<T, PL, W, STRIDED, MODE_POST_REAL, SX>), grid, block,

@@ -46,8 +46,10 @@ int pick_mode(const PassArgs &a, const PassShape &sh) {
     return bare && a.mid == MID_NONE && a.post == PH_NONE && !a.refwd ? MODE_FWD : MODE_GENERIC;
   if (a.mid != MID_TABLE) return MODE_GENERIC;
   if (a.refwd) return bare && a.post == PH_DERIV ? MODE_DERIV : MODE_GENERIC;
-  if (a.pre == PH_NONE && a.post == PH_NONE && a.red == RED_NONE && !a.scale) return MODE_PLAIN;
-  if (a.pre == PH_REAL && a.post == PH_NONE && a.red == RED_NONE && !a.scale) return MODE_PRE_REAL;
+  if (a.pre == PH_NONE && a.post == PH_NONE && a.red == RED_NONE && !a.scale)
+    return a.stream ? MODE_PLAIN_STREAM : MODE_PLAIN;
+  if (a.pre == PH_REAL && a.post == PH_NONE && a.red == RED_NONE && !a.scale)
+    return a.stream ? MODE_PRE_REAL_STREAM : MODE_PRE_REAL;
   if (a.pre == PH_NONE && a.post == PH_REAL && a.red == RED_NONE && !a.scale) return MODE_POST_REAL;
   const bool im_pre = a.pre == PH_IMAG || a.pre == PH_IMAG_EXACT;
   const bool im_post = a.post == PH_IMAG || a.post == PH_IMAG_EXACT;

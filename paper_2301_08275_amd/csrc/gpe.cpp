@@ -175,6 +175,7 @@ gpe::PassArgs base_args(gpe_ctx *c, int vaxis) {
   a.axis = vaxis;
   a.wreq = c->wreq[vaxis];
   a.plan = c->plan[vaxis];
+  a.stream = c->streaming[vaxis];
   a.xcd_remap = (vaxis != 2 && c->xcd_remap[vaxis]) ? 1 : 0;
   a.vkind = c->V ? gpe::V_ARRAY
                  : c->vtab_on ? gpe::V_TABLES
@@ -581,8 +582,8 @@ uint64_t context_bytes(const gpe_desc &d, bool with_state) {
     sites *= d.n[j];
   }
   const uint64_t es = gpe::state_f32(d.precision) ? 8 : 16;
-  int wdef[3], xcd[3], order[3], plan[3];
-  effective_tuning(d, wdef, xcd, order, plan);
+  int wdef[3], xcd[3], order[3], plan[3], stream[3];
+  effective_tuning(d, wdef, xcd, order, plan, stream);
   long long maxb = 1;
   uint64_t tables = 0;
   for (int ax = off; ax < 3; ++ax) {
@@ -624,7 +625,7 @@ gpe_status create_context(const gpe_desc *desc, const double *V_host, const gpe_
   c->dim = desc->dim;
   c->prec = desc->precision;
   c->esize = gpe::state_f32(c->prec) ? 8 : 16;
-  effective_tuning(*desc, c->wreq, c->xcd_remap, c->pass_order, c->plan);
+  effective_tuning(*desc, c->wreq, c->xcd_remap, c->pass_order, c->plan, c->streaming);
   const int off = 3 - c->dim;
   c->sites = 1;
   c->dV = 1;

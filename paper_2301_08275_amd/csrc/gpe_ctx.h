@@ -89,6 +89,8 @@ struct gpe_ctx {
   // Radix plan per view axis (0 default, 1 the alternative plan where one
   // exists).
   int plan[3] = {0, 0, 0};
+  // Streaming (non-temporal) loads and stores in the step passes, per view axis.
+  int streaming[3] = {0, 0, 0};
 };
 
 
@@ -118,7 +120,8 @@ int view_axis(const gpe_ctx *c, int user_axis);
 gpe_status validate_desc(const gpe_desc *d, std::string &msg);
 // Launch shapes a new context of this class uses (view axes): the tuning
 // table's entry, else the defaults.
-void effective_tuning(const gpe_desc &d, int wreq[3], int xcd[3], int order[3], int plan[3]);
+void effective_tuning(const gpe_desc &d, int wreq[3], int xcd[3], int order[3], int plan[3],
+                      int stream[3]);
 // Device bytes of a context (with_state: including the state array).
 uint64_t context_bytes(const gpe_desc &d, bool with_state = true);
 // gpe_create, optionally without the state array (a holder of the tables of

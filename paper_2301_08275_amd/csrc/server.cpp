@@ -198,8 +198,8 @@ uint64_t class_bytes(const gpe_desc &d, int max_slots) {
   uint64_t ktabs = 0;
   for (int ax = off; ax < 3; ++ax) ktabs += 2 * (uint64_t)n3[ax] * 16;
   // blocks of the last pass of a step, with the launch shapes the class will use
-  int wreq[3], xcd[3], order[3], plan[3];
-  effective_tuning(d, wreq, xcd, order, plan);
+  int wreq[3], xcd[3], order[3], plan[3], stream[3];
+  effective_tuning(d, wreq, xcd, order, plan, stream);
   int last = -1;
   for (int j = 0; j < 3; ++j)
     if (order[j] >= off) last = order[j];

@@ -1,10 +1,11 @@
 // Launch-shape tuning per shape class (gpe_autotune and gpe_tuning_* calls).
 //
-// The fused axis passes have four run-time shape choices: the columns per
+// The fused axis passes have five run-time shape choices: the columns per
 // workgroup of each strided axis (8 or 16, i.e. 128- or 256-byte rows in
 // FP64), whether each XCD takes a contiguous run of tiles, and the order in
-// which a step visits the axes (none changes the arithmetic of a line), and
-// the radix plan of a 1024-point axis (which changes the rounding only).
+// which a step visits the axes (none changes the arithmetic of a line), the
+// radix plan of a 1024-point axis (which changes the rounding only), and
+// streaming (non-temporal) loads and stores per axis (cache policy only).
 // gpe_autotune times the real-time step over these on the device for one
 // shape class (dim, n, precision) by coordinate descent and records the
 // fastest in a process-wide table; every context created afterwards for that
@@ -49,8 +50,10 @@ std::map<TuneKey, gpe_tuning> g_table;
 // Defaults (measured at 512^3 on MI355X): 256-byte rows on the slowest axis,
 // 128-byte rows on the middle one in FP64 (64-byte rows of 16 columns in FP32),
 // contiguous tile runs per XCD on the strided axes, slowest axis last.
-void defaults(const gpe_desc &d, int wreq[3], int xcd[3], int order[3], int plan[3]) {
+void defaults(const gpe_desc &d, int wreq[3], int xcd[3], int order[3], int plan[3],
+              int stream[3]) {
   plan[0] = plan[1] = plan[2] = 0;
+  stream[0] = stream[1] = stream[2] = 0;
   wreq[0] = 16;
   wreq[1] = d.precision == GPE_FP64 ? 8 : 16;
   wreq[2] = 8;
@@ -65,6 +68,11 @@ bool valid_tuning(int dim, const int *n, const gpe_tuning &t, std::string &msg) 
   for (int j = 0; j < dim; ++j)
     if (!gpe::plan_available(n[j], t.plan[j])) {
       msg = "plan 1 exists only for 1024-point axes";
+      return false;
+    }
+  for (int j = 0; j < dim; ++j)
+    if (t.stream[j] != 0 && t.stream[j] != 1) {
+      msg = "stream must be 0 or 1";
       return false;
     }
   for (int j = 0; j < dim - 1; ++j) {
@@ -92,10 +100,11 @@ bool valid_tuning(int dim, const int *n, const gpe_tuning &t, std::string &msg) 
 // ABI form (user axes) to the view-axis arrays of a context (3D view: 2D
 // problems use view axes 1 and 2).
 void to_view(int dim, const gpe_tuning &t, int wreq[3], int xcd[3], int order[3],
-             int plan[3]) {
+             int plan[3], int stream[3]) {
   const int off = 3 - dim;
   for (int j = 0; j < dim; ++j) {
     plan[j + off] = t.plan[j];
+    stream[j + off] = t.stream[j];
     if (j < dim - 1) {
       wreq[j + off] = t.width[j];
       xcd[j + off] = t.xcd_remap[j];
@@ -108,11 +117,12 @@ void to_view(int dim, const gpe_tuning &t, int wreq[3], int xcd[3], int order[3]
 }
 
 void from_view(int dim, const int wreq[3], const int xcd[3], const int order[3],
-               const int plan[3], gpe_tuning *t) {
+               const int plan[3], const int stream[3], gpe_tuning *t) {
   const int off = 3 - dim;
   std::memset(t, 0, sizeof(*t));
   for (int j = 0; j < dim; ++j) {
     t->plan[j] = plan[j + off];
+    t->stream[j] = stream[j + off];
     t->width[j] = j < dim - 1 ? wreq[j + off] : 0;
     t->xcd_remap[j] = j < dim - 1 ? xcd[j + off] : 0;
   }
@@ -262,11 +272,12 @@ double time_steps(gpe_ctx *c, int steps, hipEvent_t e0, hipEvent_t e1) {
 
 }  // namespace
 
-void effective_tuning(const gpe_desc &d, int wreq[3], int xcd[3], int order[3], int plan[3]) {
-  defaults(d, wreq, xcd, order, plan);
+void effective_tuning(const gpe_desc &d, int wreq[3], int xcd[3], int order[3], int plan[3],
+                      int stream[3]) {
+  defaults(d, wreq, xcd, order, plan, stream);
   std::lock_guard<std::mutex> lk(g_mu);
   auto it = g_table.find(key_of(d));
-  if (it != g_table.end()) to_view(d.dim, it->second, wreq, xcd, order, plan);
+  if (it != g_table.end()) to_view(d.dim, it->second, wreq, xcd, order, plan, stream);
 }
 
 }  // namespace gpe_host
@@ -282,7 +293,7 @@ gpe_status gpe_tuning_set(const gpe_desc *desc, const gpe_tuning *t) {
   if (!t || !valid_tuning(desc->dim, desc->n, *t, msg)) return GPE_EINVAL;
   gpe_tuning v = *t;
   for (int j = desc->dim - 1; j < 3; ++j) v.width[j] = v.xcd_remap[j] = 0;
-  for (int i = desc->dim; i < 3; ++i) v.pass_order[i] = v.plan[i] = 0;
+  for (int i = desc->dim; i < 3; ++i) v.pass_order[i] = v.plan[i] = v.stream[i] = 0;
   std::lock_guard<std::mutex> lk(g_mu);
   g_table[key_of(*desc)] = v;
   return GPE_OK;
@@ -302,9 +313,9 @@ gpe_status gpe_tuning_get(const gpe_desc *desc, gpe_tuning *out, int32_t *found)
       return GPE_OK;
     }
   }
-  int w[3], x[3], o[3], pl[3];
-  defaults(*desc, w, x, o, pl);
-  from_view(desc->dim, w, x, o, pl, out);
+  int w[3], x[3], o[3], pl[3], sm[3];
+  defaults(*desc, w, x, o, pl, sm);
+  from_view(desc->dim, w, x, o, pl, sm, out);
   out->ms_per_step = 0;
   if (found) *found = 0;
   return GPE_OK;
@@ -333,11 +344,12 @@ gpe_status gpe_tuning_save(const char *path) {
       };
       std::snprintf(buf, sizeof(buf),
                     "%s\n    {\"dim\": %d, \"n\": %s, \"precision\": \"%s\", \"width\": %s, "
-                    "\"xcd_remap\": %s, \"pass_order\": %s, \"plan\": %s, \"ms_per_step\": %.6g}",
+                    "\"xcd_remap\": %s, \"pass_order\": %s, \"plan\": %s, \"stream\": %s, "
+                    "\"ms_per_step\": %.6g}",
                     first ? "" : ",", d, arr(k.n).c_str(),
                     k.prec == GPE_FP32 ? "fp32" : k.prec == GPE_FP32_STATE ? "fp32s" : "fp64",
                     arr(t.width).c_str(), arr(t.xcd_remap).c_str(), arr(t.pass_order).c_str(),
-                    arr(t.plan).c_str(), t.ms_per_step);
+                    arr(t.plan).c_str(), arr(t.stream).c_str(), t.ms_per_step);
       s += buf;
       first = false;
     }
@@ -396,6 +408,8 @@ gpe_status gpe_tuning_load(const char *path) {
     std::string msg;
     const JVal *pl = e.get("plan");  // optional (files written before plans existed)
     if (pl && !int_array(pl, d, t.plan)) return GPE_EINVAL;
+    const JVal *sm = e.get("stream");  // optional likewise
+    if (sm && !int_array(sm, d, t.stream)) return GPE_EINVAL;
     if (validate_desc(&desc, msg) != GPE_OK || !valid_tuning(d, desc.n, t, msg))
       return GPE_EINVAL;
     t.ms_per_step = ms && ms->kind == JVal::NUM ? ms->num : 0;
@@ -418,8 +432,8 @@ gpe_status gpe_autotune(const gpe_desc *desc, int32_t steps, gpe_tuning *out) {
   // run the same instructions for any state, but a zero state draws less
   // power and would time faster than real data).  The real-time step uses no
   // partial sums, so the shapes tried need no other buffers.
-  int w0[3], x0[3], o0[3], p0[3];
-  effective_tuning(d, w0, x0, o0, p0);
+  int w0[3], x0[3], o0[3], p0[3], s0[3];
+  effective_tuning(d, w0, x0, o0, p0, s0);
   if ((st = create_context(&d, nullptr, nullptr, nullptr, true, &c)) != GPE_OK) return st;
   if (gpe::launch_fill_noise(c->prec, c->psi, c->sites, c->stream) != hipSuccess) {
     gpe_destroy(c);
@@ -431,12 +445,15 @@ gpe_status gpe_autotune(const gpe_desc *desc, int32_t steps, gpe_tuning *out) {
     gpe_destroy(c);
     return GPE_EDEVICE;
   }
+  int bs[3];  // streaming flags (the last coordinate tried)
+  std::memcpy(bs, s0, sizeof(bs));
   auto apply = [&](const int w[3], const int x[3], const int o[3], const int p[3]) {
     for (int j = 0; j < 3; ++j) {
       c->wreq[j] = w[j];
       c->xcd_remap[j] = x[j];
       c->pass_order[j] = o[j];
       c->plan[j] = p[j];
+      c->streaming[j] = bs[j];
     }
     drop_step_graphs(c);  // cached step graphs hold the previous shapes
   };
@@ -496,12 +513,20 @@ gpe_status gpe_autotune(const gpe_desc *desc, int32_t steps, gpe_tuning *out) {
       std::memcpy(bo, to, sizeof(bo));
     }
   } while (std::next_permutation(perm, perm + na));
+  // 3. per axis: streaming (non-temporal) loads and stores in the step passes
+  for (int ax = off; ax < 3 && best > 0; ++ax) {
+    bs[ax] ^= 1;
+    apply(bw, bx, bo, bp);
+    const double t = time_steps(c, steps, e0, e1);
+    if (t > 0 && t < best * (1 - kMargin)) best = t;
+    else bs[ax] ^= 1;
+  }
   (void)hipEventDestroy(e0);
   (void)hipEventDestroy(e1);
   gpe_destroy(c);
   if (!(best > 0)) return GPE_EDEVICE;
   gpe_tuning t{};
-  from_view(d.dim, bw, bx, bo, bp, &t);
+  from_view(d.dim, bw, bx, bo, bp, bs, &t);
   t.ms_per_step = best;
   if ((st = gpe_tuning_set(&d, &t)) != GPE_OK) return st;
   if (out) *out = t;

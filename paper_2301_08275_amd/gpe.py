@@ -122,7 +122,7 @@ class gpe_server_stats(ctypes.Structure):
 class gpe_tuning(ctypes.Structure):
     _fields_ = [("width", ctypes.c_int32 * 3), ("xcd_remap", ctypes.c_int32 * 3),
                 ("pass_order", ctypes.c_int32 * 3), ("plan", ctypes.c_int32 * 3),
-                ("ms_per_step", ctypes.c_double)]
+                ("stream", ctypes.c_int32 * 3), ("ms_per_step", ctypes.c_double)]
 
 
 _P = ctypes.c_void_p
@@ -392,7 +392,7 @@ def gpe_request_bytes(desc, max_slots):
 def _tuning_dict(t, dim):
     return {"width": list(t.width[:dim]), "xcd_remap": list(t.xcd_remap[:dim]),
             "pass_order": list(t.pass_order[:dim]), "plan": list(t.plan[:dim]),
-            "ms_per_step": t.ms_per_step}
+            "stream": list(t.stream[:dim]), "ms_per_step": t.ms_per_step}
 
 
 def gpe_autotune(desc, steps=10):
@@ -404,13 +404,14 @@ def gpe_autotune(desc, steps=10):
     return _tuning_dict(t, desc.dim)
 
 
-def gpe_tuning_set(desc, width, xcd_remap, pass_order, plan=None):
+def gpe_tuning_set(desc, width, xcd_remap, pass_order, plan=None, stream=None):
     t = gpe_tuning()
     for j in range(desc.dim):
         t.width[j] = int(width[j])
         t.xcd_remap[j] = int(xcd_remap[j])
         t.pass_order[j] = int(pass_order[j])
         t.plan[j] = int(plan[j]) if plan is not None else 0
+        t.stream[j] = int(stream[j]) if stream is not None else 0
     st = load_library().gpe_tuning_set(ctypes.byref(desc), ctypes.byref(t))
     if st != GPE_OK:
         raise GpeError(st, "gpe_tuning_set")

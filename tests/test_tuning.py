@@ -46,7 +46,7 @@ def test_files_without_plans_load(tmp_path):
                     '"pass_order": [0, 1], "ms_per_step": 0.01}]}')
     gpe.gpe_tuning_load(str(path))
     t, found = gpe.gpe_tuning_get(desc((64, 64)))
-    assert found and t["plan"] == [0, 0] and t["width"] == [16, 0]
+    assert found and t["plan"] == [0, 0] and t["width"] == [16, 0] and t["stream"] == [0, 0]
 
 
 def test_set_get_is_per_shape_class():
@@ -74,11 +74,21 @@ def test_invalid_entries_are_rejected(width, xcd, order):
     assert e.value.status == gpe.GPE_EINVAL
 
 
+def test_stream_flags_are_0_or_1_per_axis():
+    d = desc((64, 64, 64))
+    gpe.gpe_tuning_set(d, [8, 8, 0], [0, 0, 0], [2, 1, 0], stream=[1, 0, 1])
+    t, found = gpe.gpe_tuning_get(d)
+    assert found and t["stream"] == [1, 0, 1]
+    with pytest.raises(gpe.GpeError) as e:
+        gpe.gpe_tuning_set(d, [8, 8, 0], [0, 0, 0], [2, 1, 0], stream=[2, 0, 0])
+    assert e.value.status == gpe.GPE_EINVAL
+
+
 def test_save_load_round_trip(tmp_path):
     gpe.gpe_tuning_set(desc((512, 512, 512)), [16, 8, 0], [0, 1, 0], [2, 1, 0])
     gpe.gpe_tuning_set(desc((128, 256), "fp32"), [16, 0], [1, 0], [0, 1])
     gpe.gpe_tuning_set(desc((1024,) * 3, "fp32s"), [8, 16, 0], [1, 0, 0], [2, 1, 0],
-                       plan=[0, 0, 1])
+                       plan=[0, 0, 1], stream=[0, 1, 1])
     path = tmp_path / "tune.json"
     gpe.gpe_tuning_save(str(path))
     data = json.loads(path.read_text())
@@ -92,6 +102,7 @@ def test_save_load_round_trip(tmp_path):
     assert found and t["width"] == [16, 0] and t["pass_order"] == [0, 1]
     t, found = gpe.gpe_tuning_get(desc((1024,) * 3, "fp32s"))
     assert found and t["plan"] == [0, 0, 1] and t["width"] == [8, 16, 0]
+    assert t["stream"] == [0, 1, 1]
 
 
 @pytest.mark.parametrize("text", [
