@@ -279,8 +279,8 @@ typedef struct {
   int32_t plan[3];        /* radix plan per axis: 0 default; 1 the alternative (1024
                              points only: stages 8, 8, 8, 2 with 8 points per thread
                              instead of 16, 8, 8 with 16) */
-  int32_t stream[3];      /* per axis: 1 = the step passes load and store with the
-                             non-temporal (streaming) cache policy */
+  int32_t stream[3];      /* per axis, the step passes' non-temporal (streaming)
+                             cache policy: bit 0 loads, bit 1 stores (0..3) */
   double ms_per_step;     /* measured real-time step (gpe_autotune), else 0 */
 } gpe_tuning;             /* entries beyond dim (and width/xcd_remap of the last axis) are 0 */
 

@@ -554,13 +554,13 @@ enum PassMode : int {
   MODE_PRE_IMAG_EXACT = 11,       // MODE_PRE_IMAG with the exact substep
   MODE_POST_IMAG_RED_EXACT = 12,  // MODE_POST_IMAG_RED with the exact substep
   MODE_POST_REAL = 13,     // forward, table, inverse, closing real-time phase
-  MODE_PLAIN_STREAM = 14,     // MODE_PLAIN with streaming loads and stores
-  MODE_PRE_REAL_STREAM = 15,  // MODE_PRE_REAL with streaming loads and stores
 };
 
-__host__ __device__ constexpr int base_mode(int m) {
-  return m == MODE_PLAIN_STREAM ? MODE_PLAIN : m == MODE_PRE_REAL_STREAM ? MODE_PRE_REAL : m;
-}
+// The step modes (MODE_PLAIN, MODE_PRE_REAL) also come with streaming
+// (non-temporal) loads, stores or both: mode | STREAM_LOAD and/or
+// | STREAM_STORE.
+constexpr int STREAM_LOAD = 16, STREAM_STORE = 32;
+__host__ __device__ constexpr int base_mode(int m) { return m & 15; }
 
 // Storage type of the state in HBM, converted on load and store: the
 // arithmetic type T, or FP32 storage with FP64 arithmetic (SX = float,
@@ -574,7 +574,7 @@ template <typename T, class PL, int W, bool STRIDED, int MODE_ARG, typename SX =
 __global__ void __launch_bounds__(PL::TPL * W)
 axis_pass_kernel(const PassArgs a) {
   constexpr int MODE = base_mode(MODE_ARG);
-  constexpr bool STREAM = MODE != MODE_ARG;  // streaming loads and stores
+  constexpr bool SLOAD = (MODE_ARG & STREAM_LOAD) != 0, SSTORE = (MODE_ARG & STREAM_STORE) != 0;
   constexpr int N = PL::N, E = PL::E, TPL = PL::TPL;
   using L = Lds<N, W, STRIDED>;
   __shared__ T lre[PL::M > 1 ? L::size : 1], lim[PL::M > 1 ? L::size : 1];
@@ -694,7 +694,7 @@ axis_pass_kernel(const PassArgs a) {
 #pragma unroll
       for (int d = 0; d < R0; ++d) {
         const int p = PL::pos(0, t + TPL * b, d);
-        if constexpr (STREAM) v[b * R0 + d] = cvt<T>(load_stream(&src[base + p * S]));
+        if constexpr (SLOAD) v[b * R0 + d] = cvt<T>(load_stream(&src[base + p * S]));
         else v[b * R0 + d] = valid ? cvt<T>(src[base + p * S]) : cx<T>{0, 0};
       }
     if (has_scale || pre != PH_NONE || (red & RED_REAL)) {
@@ -800,7 +800,7 @@ axis_pass_kernel(const PassArgs a) {
 #pragma unroll
         for (int d = 0; d < R0; ++d) {
           const int p = PL::pos(0, t + TPL * b, d);
-          if constexpr (STREAM) store_stream(&dst[base + p * S], cvt<SX>(v[b * R0 + d]));
+          if constexpr (SSTORE) store_stream(&dst[base + p * S], cvt<SX>(v[b * R0 + d]));
           else dst[base + p * S] = cvt<SX>(v[b * R0 + d]);
         }
     }
@@ -875,14 +875,22 @@ void launch_mode(const PassArgs &a, int mode, dim3 grid, dim3 block, hipStream_t
       hipLaunchKernelGGL((axis_pass_kernel<T, PL, W, STRIDED, MODE_POST_IMAG_RED_EXACT, SX>),
                          grid, block, 0, s, a);
       break;
-    case MODE_PLAIN_STREAM:
-      hipLaunchKernelGGL((axis_pass_kernel<T, PL, W, STRIDED, MODE_PLAIN_STREAM, SX>), grid, block,
-                         0, s, a);
-      break;
-    case MODE_PRE_REAL_STREAM:
-      hipLaunchKernelGGL((axis_pass_kernel<T, PL, W, STRIDED, MODE_PRE_REAL_STREAM, SX>), grid,
-                         block, 0, s, a);
-      break;
+#define GPE_STREAM_CASES(M)                                                                    \
+  case M | STREAM_LOAD:                                                                        \
+    hipLaunchKernelGGL((axis_pass_kernel<T, PL, W, STRIDED, M | STREAM_LOAD, SX>), grid, block, \
+                       0, s, a);                                                               \
+    break;                                                                                     \
+  case M | STREAM_STORE:                                                                       \
+    hipLaunchKernelGGL((axis_pass_kernel<T, PL, W, STRIDED, M | STREAM_STORE, SX>), grid,      \
+                       block, 0, s, a);                                                        \
+    break;                                                                                     \
+  case M | STREAM_LOAD | STREAM_STORE:                                                         \
+    hipLaunchKernelGGL((axis_pass_kernel<T, PL, W, STRIDED, M | STREAM_LOAD | STREAM_STORE, SX>), \
+                       grid, block, 0, s, a);                                                  \
+    break;
+    GPE_STREAM_CASES(MODE_PLAIN)
+    GPE_STREAM_CASES(MODE_PRE_REAL)
+#undef GPE_STREAM_CASES
     case MODE_POST_REAL:
       hipLaunchKernelGGL((axis_pass_kernel<T, PL, W, STRIDED, MODE_POST_REAL, SX>), grid, block,
                          0, s, a);

@@ -30,6 +30,10 @@ namespace {
 // with the opening or closing phase;
 // forward-only transforms; the spectral-derivative pass; the observables'
 // forward passes); anything else runs generic.
+int stream_bits(const PassArgs &a) {
+  return ((a.stream & 1) ? STREAM_LOAD : 0) | ((a.stream & 2) ? STREAM_STORE : 0);
+}
+
 int pick_mode(const PassArgs &a, const PassShape &sh) {
   if (a.slots) return a.slot_imag ? MODE_SLOTS_IMAG : MODE_SLOTS_REAL;
   const bool full = sh.strided || ((long long)a.n[0] * a.n[1]) % sh.W == 0;
@@ -47,9 +51,9 @@ int pick_mode(const PassArgs &a, const PassShape &sh) {
   if (a.mid != MID_TABLE) return MODE_GENERIC;
   if (a.refwd) return bare && a.post == PH_DERIV ? MODE_DERIV : MODE_GENERIC;
   if (a.pre == PH_NONE && a.post == PH_NONE && a.red == RED_NONE && !a.scale)
-    return a.stream ? MODE_PLAIN_STREAM : MODE_PLAIN;
+    return MODE_PLAIN | stream_bits(a);
   if (a.pre == PH_REAL && a.post == PH_NONE && a.red == RED_NONE && !a.scale)
-    return a.stream ? MODE_PRE_REAL_STREAM : MODE_PRE_REAL;
+    return MODE_PRE_REAL | stream_bits(a);
   if (a.pre == PH_NONE && a.post == PH_REAL && a.red == RED_NONE && !a.scale) return MODE_POST_REAL;
   const bool im_pre = a.pre == PH_IMAG || a.pre == PH_IMAG_EXACT;
   const bool im_post = a.post == PH_IMAG || a.post == PH_IMAG_EXACT;

@@ -89,7 +89,8 @@ struct gpe_ctx {
   // Radix plan per view axis (0 default, 1 the alternative plan where one
   // exists).
   int plan[3] = {0, 0, 0};
-  // Streaming (non-temporal) loads and stores in the step passes, per view axis.
+  // Streaming (non-temporal) loads (bit 0) and stores (bit 1) in the step
+  // passes, per view axis.
   int streaming[3] = {0, 0, 0};
 };
 

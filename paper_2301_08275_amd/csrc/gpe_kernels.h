@@ -82,7 +82,7 @@ struct PassArgs {
   const double *kw;   // RED_KIN weights per frequency (N doubles)
   const double *scale;  // PH_IMAG pre: psi <- (*scale) psi (null: 1)
   const double *mu_shift;  // PH_IMAG_EXACT: the substeps use V - *mu_shift (null: 0)
-  int stream;         // step passes: non-temporal loads and stores (tuned per axis)
+  int stream;         // step passes: non-temporal loads (bit 0) and stores (bit 1), tuned per axis
   double *partial;      // reductions, kRedSlots doubles per workgroup
   // batched shape class (MODE_SLOTS): per-slot state and operations
   Slot *slots;

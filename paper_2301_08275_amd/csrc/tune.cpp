@@ -71,8 +71,8 @@ bool valid_tuning(int dim, const int *n, const gpe_tuning &t, std::string &msg) 
       return false;
     }
   for (int j = 0; j < dim; ++j)
-    if (t.stream[j] != 0 && t.stream[j] != 1) {
-      msg = "stream must be 0 or 1";
+    if (t.stream[j] < 0 || t.stream[j] > 3) {
+      msg = "stream must be 0..3";
       return false;
     }
   for (int j = 0; j < dim - 1; ++j) {
@@ -513,13 +513,21 @@ gpe_status gpe_autotune(const gpe_desc *desc, int32_t steps, gpe_tuning *out) {
       std::memcpy(bo, to, sizeof(bo));
     }
   } while (std::next_permutation(perm, perm + na));
-  // 3. per axis: streaming (non-temporal) loads and stores in the step passes
+  // 3. per axis: streaming (non-temporal) loads and/or stores in the step passes
   for (int ax = off; ax < 3 && best > 0; ++ax) {
-    bs[ax] ^= 1;
-    apply(bw, bx, bo, bp);
-    const double t = time_steps(c, steps, e0, e1);
-    if (t > 0 && t < best * (1 - kMargin)) best = t;
-    else bs[ax] ^= 1;
+    const int cur = bs[ax];
+    int pick = cur;
+    for (int v = 0; v < 4; ++v) {
+      if (v == cur) continue;
+      bs[ax] = v;
+      apply(bw, bx, bo, bp);
+      const double t = time_steps(c, steps, e0, e1);
+      if (t > 0 && t < best * (1 - kMargin)) {
+        best = t;
+        pick = v;
+      }
+    }
+    bs[ax] = pick;
   }
   (void)hipEventDestroy(e0);
   (void)hipEventDestroy(e1);

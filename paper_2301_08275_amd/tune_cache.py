@@ -35,7 +35,7 @@ def main(out):
         sites = 1
         for n in shape:
             sites *= n
-        steps = 4 if sites >= 1 << 30 else 10 if sites >= 1 << 24 else 64
+        steps = 6 if sites >= 1 << 30 else 24 if sites >= 1 << 24 else 64
         t = gpe.gpe_autotune(d, steps=steps)
         print("%-16s %s %s (%.1f s)" % ("x".join(map(str, shape)), prec, t, time.time() - t0),
               flush=True)

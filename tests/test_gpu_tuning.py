@@ -50,7 +50,7 @@ def test_widths_and_tile_orders_are_bitwise_neutral(prec):
         got = run(shape, lo, hi, 20.0, trap, psi0, 12, prec)
         assert np.array_equal(got, ref), (w0, w1, x0, x1)
     # streaming loads and stores change the cache policy, not the values
-    for stream in itertools.product([0, 1], repeat=3):
+    for stream in itertools.product(range(4), repeat=3):
         gpe.gpe_tuning_set(d, [16, 8, 0], [1, 1, 0], [2, 1, 0], stream=list(stream))
         say(prec, "stream", stream)
         got = run(shape, lo, hi, 20.0, trap, psi0, 12, prec)

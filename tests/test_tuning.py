@@ -74,13 +74,14 @@ def test_invalid_entries_are_rejected(width, xcd, order):
     assert e.value.status == gpe.GPE_EINVAL
 
 
-def test_stream_flags_are_0_or_1_per_axis():
+@pytest.mark.parametrize("bad", [[4, 0, 0], [0, -1, 0]])
+def test_stream_flags_are_two_bits_per_axis(bad):
     d = desc((64, 64, 64))
-    gpe.gpe_tuning_set(d, [8, 8, 0], [0, 0, 0], [2, 1, 0], stream=[1, 0, 1])
+    gpe.gpe_tuning_set(d, [8, 8, 0], [0, 0, 0], [2, 1, 0], stream=[3, 0, 2])
     t, found = gpe.gpe_tuning_get(d)
-    assert found and t["stream"] == [1, 0, 1]
+    assert found and t["stream"] == [3, 0, 2]
     with pytest.raises(gpe.GpeError) as e:
-        gpe.gpe_tuning_set(d, [8, 8, 0], [0, 0, 0], [2, 1, 0], stream=[2, 0, 0])
+        gpe.gpe_tuning_set(d, [8, 8, 0], [0, 0, 0], [2, 1, 0], stream=bad)
     assert e.value.status == gpe.GPE_EINVAL
 
 
