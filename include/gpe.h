@@ -284,9 +284,9 @@ typedef struct {
   double ms_per_step;     /* measured real-time step (gpe_autotune), else 0 */
 } gpe_tuning;             /* entries beyond dim (and width/xcd_remap of the last axis) are 0 */
 
-/* Time the real-time step of this shape class on the current device for
- * every radix plan, width and tile order of each axis, then for every pass
- * order, then the streaming flag of each axis (coordinate descent from the
+/* Time the real-time step of this shape class on the current device: per
+ * axis every radix plan x width x tile order x streaming policy, then every
+ * pass order, then the per-axis choices again (coordinate descent from the
  * current entry or the defaults; `steps` timed
  * steps per candidate, the minimum of three runs; a candidate must be more
  * than 1% faster than the incumbent to replace it), record the result in the

@@ -465,37 +465,48 @@ gpe_status gpe_autotune(const gpe_desc *desc, int32_t steps, gpe_tuning *out) {
   apply(bw, bx, bo, bp);
   double best = time_steps(c, steps, e0, e1);
   const int off = 3 - d.dim;
-  // 1. per axis: radix plan x width x tile order (width and tile order on the
-  // strided axes only)
-  for (int ax = off; ax < 3 && best > 0; ++ax) {
-    for (int pl : {0, 1}) {
-      if (!gpe::plan_available(c->n3[ax], pl)) continue;
-      for (int w : {8, 16}) {
-        if (ax == 2 && w != bw[ax]) continue;
-        if (ax != 2 && gpe::pass_shape(d.precision, c->n3, ax, w, pl).W != w) continue;
-        for (int x : {0, 1}) {
-          if (ax == 2 && x != bx[ax]) continue;
-          if (pl == bp[ax] && w == bw[ax] && x == bx[ax]) continue;
-          int tw[3], tx[3], tp[3];
-          std::memcpy(tw, bw, sizeof(tw));
-          std::memcpy(tx, bx, sizeof(tx));
-          std::memcpy(tp, bp, sizeof(tp));
-          tw[ax] = w;
-          tx[ax] = x;
-          tp[ax] = pl;
-          apply(tw, tx, bo, tp);
-          const double t = time_steps(c, steps, e0, e1);
-          if (t > 0 && t < best * (1 - kMargin)) {
-            best = t;
-            std::memcpy(bw, tw, sizeof(bw));
-            std::memcpy(bx, tx, sizeof(bx));
-            std::memcpy(bp, tp, sizeof(bp));
+  // Per axis, jointly: radix plan x width x tile order x streaming policy
+  // (width and tile order on the strided axes only; a narrower tile may only
+  // pay off with streaming loads, so the policy is not tried separately).
+  auto axis_round = [&]() {
+    for (int ax = off; ax < 3 && best > 0; ++ax) {
+      for (int pl : {0, 1}) {
+        if (!gpe::plan_available(c->n3[ax], pl)) continue;
+        for (int w : {8, 16}) {
+          if (ax == 2 && w != bw[ax]) continue;
+          if (ax != 2 && gpe::pass_shape(d.precision, c->n3, ax, w, pl).W != w) continue;
+          for (int x : {0, 1}) {
+            if (ax == 2 && x != bx[ax]) continue;
+            for (int sm = 0; sm < 4; ++sm) {
+              if (pl == bp[ax] && w == bw[ax] && x == bx[ax] && sm == bs[ax]) continue;
+              int tw[3], tx[3], tp[3];
+              std::memcpy(tw, bw, sizeof(tw));
+              std::memcpy(tx, bx, sizeof(tx));
+              std::memcpy(tp, bp, sizeof(tp));
+              const int s_keep = bs[ax];
+              tw[ax] = w;
+              tx[ax] = x;
+              tp[ax] = pl;
+              bs[ax] = sm;
+              apply(tw, tx, bo, tp);
+              const double t = time_steps(c, steps, e0, e1);
+              if (t > 0 && t < best * (1 - kMargin)) {
+                best = t;
+                std::memcpy(bw, tw, sizeof(bw));
+                std::memcpy(bx, tx, sizeof(bx));
+                std::memcpy(bp, tp, sizeof(bp));
+              } else {
+                bs[ax] = s_keep;
+              }
+            }
           }
         }
       }
     }
-  }
-  // 2. axis order of the step
+  };
+  // 1. per-axis shapes; 2. the axis order of the step (it decides which pass
+  // carries the phase); 3. per-axis shapes again for that order
+  axis_round();
   int perm[3] = {0, 1, 2};
   int axes[3], na = 0;
   for (int ax = off; ax < 3; ++ax) axes[na++] = ax;
@@ -513,22 +524,7 @@ gpe_status gpe_autotune(const gpe_desc *desc, int32_t steps, gpe_tuning *out) {
       std::memcpy(bo, to, sizeof(bo));
     }
   } while (std::next_permutation(perm, perm + na));
-  // 3. per axis: streaming (non-temporal) loads and/or stores in the step passes
-  for (int ax = off; ax < 3 && best > 0; ++ax) {
-    const int cur = bs[ax];
-    int pick = cur;
-    for (int v = 0; v < 4; ++v) {
-      if (v == cur) continue;
-      bs[ax] = v;
-      apply(bw, bx, bo, bp);
-      const double t = time_steps(c, steps, e0, e1);
-      if (t > 0 && t < best * (1 - kMargin)) {
-        best = t;
-        pick = v;
-      }
-    }
-    bs[ax] = pick;
-  }
+  axis_round();
   (void)hipEventDestroy(e0);
   (void)hipEventDestroy(e1);
   gpe_destroy(c);
