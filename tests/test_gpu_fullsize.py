@@ -31,6 +31,17 @@ def say(*a):
     sys.stdout.flush()
 
 
+@pytest.fixture(autouse=True, scope="module")
+def bench_launch_shapes():
+    """The shipped tuning cache, as bench.py loads it (widths, tile orders,
+    pass order, streaming policy per axis)."""
+    from paper_2301_08275_amd import tune_cache
+
+    gpe.gpe_tuning_load(tune_cache.SHIPPED)
+    yield
+    gpe.gpe_tuning_clear()
+
+
 @pytest.fixture(scope="module")
 def psi512():
     return I.phase_field(512, seed=2)
