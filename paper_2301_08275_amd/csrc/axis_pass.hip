@@ -64,10 +64,33 @@ int pick_mode(const PassArgs &a, const PassShape &sh) {
   return MODE_GENERIC;
 }
 
+// Operation sets that need more than 128 VGPRs on a 1024-thread tile with
+// FP64 arithmetic (compiler resource report at 512 points: 12-304 bytes of
+// scratch per lane; the step passes, transforms and observables fit), and the
+// exact imaginary-time pre pass, which fits but whose per-site exp, expm1 and
+// sqrt make a lone 1024-thread tile per CU compute-bound (measured at 512^3:
+// 3 % faster on 8-column tiles in FP64, 12 % with the FP32 state).
+bool heavy_mode(int mode) {
+  switch (base_mode(mode)) {
+    case MODE_GENERIC:
+    case MODE_PRE_IMAG:
+    case MODE_PRE_IMAG_EXACT:
+    case MODE_POST_IMAG_RED:
+    case MODE_POST_IMAG_RED_EXACT:
+    case MODE_POST_REAL:
+    case MODE_SLOTS_REAL:
+    case MODE_SLOTS_IMAG:
+    case MODE_DERIV:
+      return true;
+    default:
+      return false;
+  }
+}
+
 }  // namespace
 }  // namespace pass
 
-PassShape pass_shape(int precision, const int n[3], int axis, int wreq, int plan) {
+PassShape pass_shape(int precision, const int n[3], int axis, int wreq, int plan, bool narrow) {
   using namespace pass;
   PassShape sh{};
   sh.N = n[axis];
@@ -81,7 +104,9 @@ PassShape pass_shape(int precision, const int n[3], int axis, int wreq, int plan
     sh.blocks = (lines + sh.W - 1) / sh.W;
   } else {
     const int want = wreq == 16 ? 16 : 8;
-    const int ws = fit_w(sh.N, math_f32(precision) ? 8 : 16, want, tpl);
+    int ws = fit_w(sh.N, math_f32(precision) ? 8 : 16, want, tpl);
+    if (narrow && ws == 16 && tpl * 16 == 1024 && (!math_f32(precision) || sh.N / tpl == 16))
+      ws = 8;
     sh.W = n[2] >= ws ? ws : 8;
     sh.threads = tpl * sh.W;
     const long long outer = axis == 1 ? n[0] : n[1];
@@ -90,8 +115,17 @@ PassShape pass_shape(int precision, const int n[3], int axis, int wreq, int plan
   return sh;
 }
 
-hipError_t launch_axis_pass(int precision, const PassArgs &a, hipStream_t s) {
+PassShape launch_shape(int precision, const PassArgs &a) {
   const PassShape sh = pass_shape(precision, a.n, a.axis, a.wreq, a.plan);
+  // (narrowing changes strided tiles only, and the mode depends on the shape
+  // only through the contiguous full-tile test, so the mode is unchanged)
+  return pass::heavy_mode(pass::pick_mode(a, sh))
+             ? pass_shape(precision, a.n, a.axis, a.wreq, a.plan, true)
+             : sh;
+}
+
+hipError_t launch_axis_pass(int precision, const PassArgs &a, hipStream_t s) {
+  const PassShape sh = launch_shape(precision, a);
   if (sh.threads == 0 || (sh.strided && a.n[2] < sh.W)) return hipErrorInvalidValue;
   const int mode = pass::pick_mode(a, sh);
   if (precision == 1) return pass::launch_f32(a, sh, mode, s);

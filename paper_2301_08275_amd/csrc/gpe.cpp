@@ -401,7 +401,7 @@ gpe_status enqueue_observe(gpe_ctx *c, const double *scale, double *sums_dev) {
     a.partial = c->partial + i * c->partial_region;
     gpe_status st = launch_pass(c, a);
     if (st != GPE_OK) return st;
-    const gpe::PassShape sh = gpe::pass_shape(c->prec, c->n3, ax, c->wreq[ax], c->plan[ax]);
+    const gpe::PassShape sh = gpe::launch_shape(c->prec, a);
     HIPCHK(c, gpe::launch_finalize(a.partial, sh.blocks, sums_dev + i * gpe::kRedSlots,
                                    nullptr, 0, 1, c->stream, c->fin), "finalize launch");
   }
@@ -541,9 +541,6 @@ gpe_status compute_spectra(gpe_ctx *c, gpe_spectra *spec) {
     a.mtab = deriv_tab[ax];
     a.post = gpe::PH_DERIV;
     a.refwd = 1;  // Z_j leaves this pass already transformed along axis j
-    // With FP64 arithmetic this pass needs more registers than a 16-column
-    // tile of 1024 threads allows (measured: 8 columns are faster there).
-    if (!gpe::math_f32(c->prec)) a.wreq = 8;
     st = launch_pass(c, a);
     if (st != GPE_OK) return st;
     st = forward_all(c, c->work[j], c->work[j], ax);
@@ -587,7 +584,7 @@ uint64_t context_bytes(const gpe_desc &d, bool with_state) {
   long long maxb = 1;
   uint64_t tables = 0;
   for (int ax = off; ax < 3; ++ax) {
-    const gpe::PassShape sh = gpe::pass_shape(d.precision, n3, ax, wdef[ax], plan[ax]);
+    const gpe::PassShape sh = gpe::pass_shape(d.precision, n3, ax, wdef[ax], plan[ax], true);
     if (sh.blocks > maxb) maxb = sh.blocks;
     tables += (uint64_t)n3[ax] * (16 + sizeof(double));
   }
@@ -675,7 +672,8 @@ gpe_status create_context(const gpe_desc *desc, const double *V_host, const gpe_
   if (const char *w = std::getenv("GPE_TUNE_XCD")) c->xcd_remap[0] = c->xcd_remap[1] = std::atoi(w);
   long long maxb = 1;
   for (int ax = 3 - c->dim; ax < 3; ++ax) {
-    const gpe::PassShape sh = gpe::pass_shape(c->prec, c->n3, ax, c->wreq[ax], c->plan[ax]);
+    // (narrow shapes have the most blocks: room for every pass's partials)
+    const gpe::PassShape sh = gpe::pass_shape(c->prec, c->n3, ax, c->wreq[ax], c->plan[ax], true);
     if (sh.blocks > maxb) maxb = sh.blocks;
   }
   c->partial_region = maxb * gpe::kRedSlots;
@@ -881,7 +879,7 @@ gpe_status imag_step(gpe_ctx *c, void *const K[3], double dt) {
     gpe_status st = launch_pass(c, a);
     if (st != GPE_OK) return st;
     if (i == na - 1) {
-      const gpe::PassShape sh = gpe::pass_shape(c->prec, c->n3, ax, c->wreq[ax], c->plan[ax]);
+      const gpe::PassShape sh = gpe::launch_shape(c->prec, a);
       HIPCHK(c, gpe::launch_finalize(c->partial, sh.blocks, c->sums + 3 * gpe::kRedSlots,
                                      c->scale, c->desc.norm_target, c->dV, c->stream, c->fin,
                                      exact ? dt : 0.0),

@@ -106,7 +106,18 @@ struct PassShape {
 // Launch geometry the kernels are built for (must match the template choice).
 // plan: 0 the default radix plan of the axis length, 1 the alternative
 // (only 1024 points has one; elsewhere 1 means 0).
-PassShape pass_shape(int precision, const int n[3], int axis, int wreq, int plan = 0);
+// narrow: the pass runs one of the register-heavy operation sets (closing
+// real-time phase, imaginary-time pre and post passes, batched slots, the
+// spectral derivative, generic; also the exact imaginary-time pre pass, which
+// is compute-bound there).  Where a 16-column strided tile would take
+// 1024 threads (128 VGPRs each) with FP64 arithmetic or 16 points per thread,
+// those kernels spill to scratch, so they take 8-column tiles there.  Block
+// counts with narrow = true are never smaller than without.
+PassShape pass_shape(int precision, const int n[3], int axis, int wreq, int plan = 0,
+                     bool narrow = false);
+// The shape launch_axis_pass uses for these arguments; the partial sums of a
+// reducing pass have one row per block of this shape.
+PassShape launch_shape(int precision, const PassArgs &a);
 inline bool plan_available(int n, int plan) { return plan == 0 || (plan == 1 && n == 1024); }
 
 // Launch one axis pass; precision 0 = FP64, 1 = FP32.

@@ -203,7 +203,8 @@ uint64_t class_bytes(const gpe_desc &d, int max_slots) {
   int last = -1;
   for (int j = 0; j < 3; ++j)
     if (order[j] >= off) last = order[j];
-  const long long bpg = gpe::pass_shape(d.precision, n3, last, wreq[last], plan[last]).blocks;
+  // (the batched slot passes are register-heavy: narrow shapes)
+  const long long bpg = gpe::pass_shape(d.precision, n3, last, wreq[last], plan[last], true).blocks;
   return context_bytes(d, false) + ktabs +
          (uint64_t)max_slots * (sizeof(gpe::Slot) + sizeof(int)) +
          (uint64_t)max_slots * bpg * gpe::kRedSlots * sizeof(double);
@@ -360,7 +361,7 @@ gpe_status create_class(gpe_server *s, const gpe_request &r, ShapeClass **out) {
     }
   }
   const int last = order_axis(p, n_axes(p) - 1);
-  c->bpg_last = gpe::pass_shape(p->prec, p->n3, last, p->wreq[last], p->plan[last]).blocks;
+  c->bpg_last = gpe::pass_shape(p->prec, p->n3, last, p->wreq[last], p->plan[last], true).blocks;
   // Graph replay over all slots pays for the empty rows' dispatch, which is
   // negligible for small grids (where launch latency dominates) and not for
   // large ones.
