@@ -273,7 +273,11 @@ void gpe_destroy(gpe_ctx *ctx);
  * their shapes.  The table is process-wide and thread-safe.
  * ---------------------------------------------------------------------- */
 typedef struct {
-  int32_t width[3];       /* strided axes (all but the last): columns per workgroup, 8 or 16 */
+  int32_t width[3];       /* strided axes (all but the last): columns per workgroup, 8 or 16,
+                             for the step passes and transforms; the register-heavy
+                             passes (closing phase, imaginary-time passes, batched
+                             slots, spectral derivative) take 8 where 16 would put
+                             1024 threads in a workgroup with FP64 arithmetic */
   int32_t xcd_remap[3];   /* strided axes: 1 = each XCD takes a contiguous run of tiles */
   int32_t pass_order[3];  /* the axes (0 = slowest) in the order a step visits them */
   int32_t plan[3];        /* radix plan per axis: 0 default; 1 the alternative (1024
