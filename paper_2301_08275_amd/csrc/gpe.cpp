@@ -852,9 +852,9 @@ gpe_status real_step(gpe_ctx *c, void *const K[3], double tau_pre, double tau_po
 // pass, N(dt/2) and the norm reduction after the last; the finalize kernel
 // turns the reduction into the next scale.  The axes go in the reverse of the
 // real-time order, so that the closing pass, whose phase and reduction need
-// the most registers, is the contiguous-axis pass (the strided 16-column
-// form spills there): 2.94 instead of 3.42 ms per step at 512^3 FP64,
-// 0.301 instead of 0.327 at 256^3.
+// the most registers, is the contiguous-axis pass (on a strided axis it
+// spills at 16 columns and runs on 8): 2.94 instead of 3.42 ms per step at
+// 512^3 FP64 when this was chosen, 0.301 instead of 0.327 at 256^3.
 gpe_status imag_step(gpe_ctx *c, void *const K[3], double dt) {
   const int na = n_axes(c);
   for (int i = 0; i < na; ++i) {
