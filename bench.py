@@ -128,13 +128,19 @@ def traffic_for(kernel):
     return k["hbm_bytes_per_launch"] if k else None
 
 
-def cpu_baseline(n, seed, steps=1):
+def cpu_baseline(n, seed, target_s=12.0, max_steps=25):
+    """The oracle on the host cores: a bounded sample of the same workload,
+    its step count sized by one untimed step to about target_s seconds."""
     import oracle
     from paper_2301_08275_amd import inputs as I
 
     psi = I.phase_field(n, seed)
     lo, hi = (0.0,) * 3, (2 * 3.141592653589793,) * 3
     oracle.set_threads(0)
+    t0 = time.perf_counter()
+    oracle.tssp_real(psi, lo, hi, None, 1.0, 5e-4, 1)
+    t1 = time.perf_counter() - t0
+    steps = max(1, min(max_steps, int(round(target_s / t1))))
     t0 = time.perf_counter()
     oracle.tssp_real(psi, lo, hi, None, 1.0, 5e-4, steps)
     t = time.perf_counter() - t0
@@ -359,7 +365,7 @@ def main():
                     help="skip the separable / time-dependent potential timing")
     args = ap.parse_args()
     if args.gpus != 1:
-        print("bench.py measures one GPU: this build has no multi-GPU path "
+        print("bench.py measures one GPU: the library has no multi-GPU path "
               "(run with --gpus 1)", file=sys.stderr)
         sys.exit(2)
 

@@ -245,7 +245,7 @@ gpe_status enqueue_step(gpe_server *s, ShapeClass *c, int k) {
              : GPE_EDEVICE;
 }
 
-// Steps to give class c this round: quantum_ms of GPU time per running
+// Steps to give class c in this scheduling pass: quantum_ms of GPU time per running
 // request, from the GPU time per step measured on its last chunk.  Large
 // grids are bandwidth-bound (time grows with the running slots); small ones
 // are launch-bound (it does not), and run whole graph replays.  On-chip
