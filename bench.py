@@ -119,7 +119,10 @@ def dominant(kinds):
     return name, avg_ms, k["bytes"] / (avg_ms * 1e-3) / 1e9, k["bytes"]
 
 
-def traffic_for(kernel):
+def traffic_for(kernel, bytes_per_launch):
+    """Measured HBM bytes per launch of `kernel` from the committed counter
+    summary, or None when the summary was made from other kernel sources or
+    for another workload (its algorithmic bytes per launch differ)."""
     if not os.path.exists(TRAFFIC_FILE):
         return None
     with open(TRAFFIC_FILE) as f:
@@ -127,7 +130,9 @@ def traffic_for(kernel):
     if t.get("kernel_hash") != kernel_hash():
         return None
     k = t.get("kernels", {}).get(kernel)
-    return k["hbm_bytes_per_launch"] if k else None
+    if not k or k.get("algorithmic_bytes_per_launch") != bytes_per_launch:
+        return None
+    return k["hbm_bytes_per_launch"]
 
 
 def cpu_baseline(n, seed, target_s=12.0, max_steps=25):
@@ -454,7 +459,7 @@ def main():
                    "grid": [n, n, n], "sites": sites, "dt": dt, "g": g,
                    "spectra_evaluations": r64["nspec"], "passes_per_step": 3},
         "roofline": {"bound": "hbm", "achieved": achieved, "peak": HBM_PEAK_GBS, "unit": "GB/s",
-                     "frac": achieved / HBM_PEAK_GBS, "traffic": traffic_for(name),
+                     "frac": achieved / HBM_PEAK_GBS, "traffic": traffic_for(name, bytes_per),
                      "kernel": name, "avg_launch_ms": avg_ms, "bytes_per_launch": bytes_per},
         "stepping_only": {"ms_per_step": step_ms, "site_steps_per_s": sites / (step_ms * 1e-3),
                           "hbm_GBps_at_96B_per_site_step":

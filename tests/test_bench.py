@@ -24,3 +24,19 @@ def test_cpu_baseline_sample_is_bounded():
     steps = int(r["sample"].split()[0])
     assert 1 <= steps <= 6
     assert "32^3" in r["sample"]
+
+
+def test_traffic_is_reported_only_for_the_profiled_workload():
+    import json
+
+    import bench
+
+    with open(bench.TRAFFIC_FILE) as f:
+        t = json.load(f)
+    k = t["kernels"]["step_x_fp64"]
+    if t["kernel_hash"] == bench.kernel_hash():
+        assert bench.traffic_for("step_x_fp64", k["algorithmic_bytes_per_launch"]) == \
+            k["hbm_bytes_per_launch"]
+    # another grid (1024^3: 8x the bytes) or another kernel: no figure
+    assert bench.traffic_for("step_x_fp64", 8 * k["algorithmic_bytes_per_launch"]) is None
+    assert bench.traffic_for("no_such_kernel", k["algorithmic_bytes_per_launch"]) is None
