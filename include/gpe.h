@@ -259,6 +259,15 @@ gpe_status gpe_timing_read(gpe_ctx *ctx, gpe_timing *out);
 /* Bytes of device memory the context holds. */
 uint64_t gpe_device_bytes(const gpe_ctx *ctx);
 
+/* HIP device ordinal the context was created on (the current device at
+ * gpe_create); -1 for NULL.  Device pointers handed to the context
+ * (gpe_set_state_device, gpe_get_state_device) must be on this device. */
+int32_t gpe_device(const gpe_ctx *ctx);
+
+/* The stream the context enqueues on (the caller's, or the private one the
+ * library created when gpe_create got NULL). */
+void *gpe_stream(const gpe_ctx *ctx);
+
 /* Message for the last failing call on ctx (ctx may be NULL: last failure of
  * gpe_create on this thread).  Never NULL. */
 const char *gpe_last_error(const gpe_ctx *ctx);

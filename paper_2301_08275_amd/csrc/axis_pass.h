@@ -410,10 +410,11 @@ __device__ __forceinline__ double harmonic_potential(const double (&lo)[3], cons
 }
 
 __device__ __forceinline__ double site_potential(const PassArgs &a, int vkind, const double (&hv)[3],
-                                                 int j0, int j1, int j2) {
+                                                 int j0, int j1, int j2,
+                                                 const double *__restrict__ vt) {
   if (vkind == V_NONE) return 0.0;
   if (vkind == V_ARRAY) return a.V[((long long)j0 * a.n[1] + j1) * a.n[2] + j2];
-  if (vkind == V_TABLES) return a.vtab[j0] + a.vtab[a.n[0] + j1] + a.vtab[a.n[0] + a.n[1] + j2];
+  if (vkind == V_TABLES) return vt[j0] + vt[a.n[0] + j1] + vt[a.n[0] + a.n[1] + j2];
   return harmonic_potential(a.lo, a.h, hv, j0, j1, j2);
 }
 
@@ -710,7 +711,7 @@ axis_pass_kernel(const PassArgs a) {
           cx<T> u = v[b * R0 + d];
           if (has_scale) u = {(T)(sc * (double)u.x), (T)(sc * (double)u.y)};
           const double V = (pre != PH_NONE || (red & RED_REAL)) && valid
-                               ? site_potential(a, vkind, hv, k0, k1, k2) : 0.0;
+                               ? site_potential(a, vkind, hv, k0, k1, k2, a.vtab) : 0.0;
           if (red & RED_REAL) {
             const double rho = (double)u.x * u.x + (double)u.y * u.y;
             const double x0 = a.lo[0] + k0 * a.h[0], x1 = a.lo[1] + k1 * a.h[1],
@@ -772,7 +773,10 @@ axis_pass_kernel(const PassArgs a) {
             u = mag > 0 ? cx<T>{(T)(zi / mag), (T)(zr / mag)} : cx<T>{0, 0};
           } else if (post != PH_NONE) {
             const int k0 = axis == 0 ? p : j0, k1 = axis == 1 ? p : j1, k2 = axis == 2 ? p : j2;
-            const double V = valid ? site_potential(a, vkind, hv, k0, k1, k2) : 0.0;
+            const double V =
+                valid ? site_potential(a, vkind, hv, k0, k1, k2,
+                                       a.vtab_post ? a.vtab_post : a.vtab)
+                      : 0.0;
             const double mus =
                 (G || EXACT) && post == PH_IMAG_EXACT && a.mu_shift ? *a.mu_shift : 0.0;
             u = apply_phase(post, u, V - mus, g, tau_post);

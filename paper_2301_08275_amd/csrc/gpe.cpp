@@ -359,9 +359,11 @@ bool sep_params(const gpe_ctx *c, const gpe_separable &u, gpe::SepParams *P) {
   return true;
 }
 
+// Two regions of per-axis tables: the second holds the closing phase's
+// potential when one pass carries both phases (a 1D grid).
 gpe_status alloc_vtab(gpe_ctx *c) {
   if (c->vtab) return GPE_OK;
-  return dalloc(c, (void **)&c->vtab, (c->n3[0] + c->n3[1] + c->n3[2]) * sizeof(double),
+  return dalloc(c, (void **)&c->vtab, 2 * vtab_len(c) * sizeof(double),
                 "potential table allocation");
 }
 
@@ -369,7 +371,7 @@ gpe_status alloc_vtab(gpe_ctx *c) {
 // V(ta) (weight wa) and V(tb) (weight wb; skipped when 0); a static
 // potential needs nothing.  Enqueued on the context stream, so passes
 // already enqueued read the previous tables.
-gpe_status vtables_at(gpe_ctx *c, const VAt &at) {
+gpe_status vtables_at(gpe_ctx *c, const VAt &at, int region) {
   if (!c->vfn) return GPE_OK;
   gpe_separable u[2] = {};
   gpe::SepParams P[2];
@@ -378,8 +380,9 @@ gpe_status vtables_at(gpe_ctx *c, const VAt &at) {
   if (!sep_params(c, u[0], &P[0]) || (at.wb != 0 && !sep_params(c, u[1], &P[1])))
     return fail(c, GPE_EINVAL, "the potential callback returned a non-finite parameter");
   if (at.wb == 0) P[1] = P[0];
-  HIPCHK(c, gpe::launch_vtables(P[0], at.wa, P[1], at.wb, c->n3, c->lo3, c->h3, c->vtab,
-                                c->stream), "potential table launch");
+  HIPCHK(c, gpe::launch_vtables(P[0], at.wa, P[1], at.wb, c->n3, c->lo3, c->h3,
+                                c->vtab + region * vtab_len(c), c->stream),
+         "potential table launch");
   return GPE_OK;
 }
 
@@ -827,11 +830,17 @@ gpe_status real_step(gpe_ctx *c, void *const K[3], double tau_pre, double tau_po
   const int na = n_axes(c);
   for (int i = 0; i < na; ++i) {
     const int ax = order_axis(c, i);
+    // The closing phase's potential goes to the second table region when the
+    // same pass also opens the step (one axis), else over the opening one
+    // (stream order: the first pass has read it by then).
+    const bool closing = i == na - 1 && tau_post != 0 && post;
+    const int post_region = (i == 0 && pre) ? 1 : 0;
     gpe_status vst = GPE_OK;
-    if (i == 0 && pre) vst = vtables_at(c, *pre);
-    if (i == na - 1 && tau_post != 0 && post) vst = vtables_at(c, *post);
+    if (i == 0 && pre) vst = vtables_at(c, *pre, 0);
+    if (vst == GPE_OK && closing) vst = vtables_at(c, *post, post_region);
     if (vst != GPE_OK) return vst;
     gpe::PassArgs a = base_args(c, ax);
+    if (closing && post_region == 1) a.vtab_post = c->vtab + vtab_len(c);
     a.mid = gpe::MID_TABLE;
     a.mtab = K[ax];
     if (i == 0) {
@@ -1151,6 +1160,10 @@ gpe_status gpe_timing_read(gpe_ctx *c, gpe_timing *out) {
 }
 
 uint64_t gpe_device_bytes(const gpe_ctx *c) { return c ? c->dev_bytes : 0; }
+
+int32_t gpe_device(const gpe_ctx *c) { return c ? c->device : -1; }
+
+void *gpe_stream(const gpe_ctx *c) { return c ? static_cast<void *>(c->stream) : nullptr; }
 
 const char *gpe_last_error(const gpe_ctx *c) {
   if (!c) return g_create_error.c_str();

@@ -107,7 +107,9 @@ gpe_status set_potential(gpe_ctx *c, const double *V_host, const gpe_harmonic *V
 struct VAt {
   double ta, wa, tb, wb;
 };
-gpe_status vtables_at(gpe_ctx *c, const VAt &at);
+// Writes table region `region` (0 or 1, each n3[0] + n3[1] + n3[2] doubles).
+gpe_status vtables_at(gpe_ctx *c, const VAt &at, int region = 0);
+inline long long vtab_len(const gpe_ctx *c) { return c->n3[0] + c->n3[1] + c->n3[2]; }
 void drop_step_graphs(gpe_ctx *c);
 // Steps per step graph unless convergence checks set the length.
 constexpr int kGraphSteps = 32;
@@ -115,6 +117,12 @@ constexpr int kGraphSteps = 32;
 // closing phase; 1: imaginary time), from graphs of len steps where allowed.
 gpe_status steady_steps(gpe_ctx *c, int mode, double dt, int64_t n, int len, void *const K[3]);
 gpe_status compute_obs(gpe_ctx *c, const double *scale, gpe_obs *o);
+// One real-time step (opening phase N(tau_pre), the kinetic factor K on every
+// axis, closing phase N(tau_post) if nonzero; pre/post: time-dependent
+// potential times, or null) and one imaginary-time step; direct launches.
+gpe_status real_step(gpe_ctx *c, void *const K[3], double tau_pre, double tau_post,
+                     const VAt *pre, const VAt *post);
+gpe_status imag_step(gpe_ctx *c, void *const K[3], double dt);
 int n_axes(const gpe_ctx *c);
 int order_axis(const gpe_ctx *c, int i);
 int view_axis(const gpe_ctx *c, int user_axis);

@@ -76,6 +76,8 @@ struct PassArgs {
   const double *V;    // FP64 potential per site, or null
   double hv[3];       // analytic V = sum_j hv[j] x_j^2 when V is null
   const double *vtab; // V_TABLES: V = t[j0] + t[n0 + j1] + t[n0 + n1 + j2] (view axes)
+  const double *vtab_post;  // V_TABLES tables of the post phase when it differs from
+                            // the pre phase's in the same pass (null: vtab)
   double lo[3], h[3]; // coordinates x_j = lo[j] + i h[j] (3D indexing)
   const void *tw;     // twiddles exp(-2 pi i j / N), j < N, complex T
   const void *mtab;   // mid table (complex T, N entries) for MID_TABLE

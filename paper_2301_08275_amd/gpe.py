@@ -156,6 +156,8 @@ SIGNATURES = {
     "gpe_timing_enable": (_I32, [_P, _I32]),
     "gpe_timing_read": (_I32, [_P, ctypes.POINTER(gpe_timing)]),
     "gpe_device_bytes": (ctypes.c_uint64, [_P]),
+    "gpe_device": (_I32, [_P]),
+    "gpe_stream": (ctypes.c_void_p, [_P]),
     "gpe_last_error": (ctypes.c_char_p, [_P]),
     "gpe_destroy": (None, [_P]),
     "gpe_server_create": (_I32, [ctypes.c_uint64, _I32, _I32, _I32, ctypes.POINTER(_P)]),
@@ -456,6 +458,11 @@ class Context:
     FP64 arithmetic); V: FP64 array of `shape` or None; harmonic:
     trap frequencies per axis (V = 1/2 sum w^2 x^2) or None; stream: a
     hipStream_t handle (int) such as torch.cuda.current_stream().cuda_stream.
+    The null stream (handle 0, torch's default stream) cannot be handed to
+    the library, whose NULL means "create a private stream": with stream None
+    or 0 the context runs on a private stream, and the device-tensor calls
+    (set_state_device, get_state_device) order themselves against the
+    caller's current torch stream by waiting on the host.
     """
 
     def __init__(self, shape, lo, hi, g, precision="fp64", norm_target=1.0,
@@ -491,6 +498,7 @@ class Context:
         self._ctx = None
         self._vfn = None  # (callback object, exceptions it caught)
         self._ctx = gpe_create(d, Vh, an, ctypes.c_void_p(stream) if stream else None)
+        self._own_stream = not stream
 
     @property
     def handle(self):
@@ -590,18 +598,45 @@ class Context:
         gpe_get_state(self._ctx, out.view(np.float64))
         return out
 
+    def _device_tensor(self, tensor):
+        """Check a torch tensor before its pointer reaches the library: a
+        contiguous complex128/complex64 tensor of the context's shape on the
+        context's HIP device.  Returns the library's precision code."""
+        dtype = str(getattr(tensor, "dtype", None))
+        if dtype not in ("torch.complex128", "torch.complex64"):
+            raise ValueError("need a complex128 or complex64 tensor, got %s" % dtype)
+        dev = getattr(tensor, "device", None)
+        if getattr(dev, "type", None) != "cuda":
+            raise ValueError("need a tensor on the context's HIP device, got %s" % (dev,))
+        ordinal = load_library().gpe_device(self._ctx)
+        if dev.index is not None and dev.index != ordinal:
+            raise ValueError("tensor on device %d, context on device %d" % (dev.index, ordinal))
+        if tuple(tensor.shape) != self.shape or not tensor.is_contiguous():
+            raise ValueError("need a contiguous tensor of shape %s" % (self.shape,))
+        return GPE_FP32 if dtype == "torch.complex64" else GPE_FP64
+
+    def _caller_stream_sync(self, tensor):
+        """A context on its private stream is not ordered with the caller's
+        torch stream: wait for the caller's pending work on the tensor."""
+        if self._own_stream:
+            import torch
+
+            torch.cuda.current_stream(tensor.device).synchronize()
+
     def set_state_device(self, tensor):
         """tensor: a contiguous torch complex128/complex64 CUDA tensor."""
-        src = GPE_FP32 if str(tensor.dtype) == "torch.complex64" else GPE_FP64
-        if tuple(tensor.shape) != self.shape or not tensor.is_contiguous():
-            raise ValueError("need a contiguous tensor of shape %s" % (self.shape,))
+        src = self._device_tensor(tensor)
+        self._caller_stream_sync(tensor)
         gpe_set_state_device(self._ctx, ctypes.c_void_p(tensor.data_ptr()), src)
+        if self._own_stream:
+            gpe_synchronize(self._ctx)  # the caller may overwrite the tensor next
 
     def get_state_device(self, tensor):
-        dst = GPE_FP32 if str(tensor.dtype) == "torch.complex64" else GPE_FP64
-        if tuple(tensor.shape) != self.shape or not tensor.is_contiguous():
-            raise ValueError("need a contiguous tensor of shape %s" % (self.shape,))
+        dst = self._device_tensor(tensor)
+        self._caller_stream_sync(tensor)
         gpe_get_state_device(self._ctx, ctypes.c_void_p(tensor.data_ptr()), dst)
+        if self._own_stream:
+            gpe_synchronize(self._ctx)  # the caller's stream reads the tensor next
 
     def evolve(self, dt, nsteps):
         with self._callbacks():

@@ -54,3 +54,29 @@ def test_header_is_plain_c(tmp_path):
     r = subprocess.run(["gcc", "-std=c99", "-Wall", "-Wextra", "-Werror", "-fsyntax-only",
                         "-I", os.path.join(ROOT, "include"), src], capture_output=True, text=True)
     assert r.returncode == 0, r.stderr
+
+
+def _unbound_context(shape=(8, 8)):
+    """A Context object with no library context behind it: only the host-side
+    argument checks can run on it."""
+    ctx = gpe.Context.__new__(gpe.Context)
+    ctx.shape, ctx.dim, ctx._ctx, ctx._own_stream, ctx._vfn = tuple(shape), len(shape), None, True, None
+    return ctx
+
+
+@pytest.mark.parametrize("make", [
+    lambda torch: torch.zeros((8, 8), dtype=torch.complex128),      # host tensor
+    lambda torch: torch.zeros((8, 8), dtype=torch.float64),         # real dtype
+    lambda torch: torch.zeros((8, 8, 2), dtype=torch.float32),      # real dtype, other shape
+    lambda torch: torch.zeros((8, 8), dtype=torch.complex64),       # host tensor, FP32
+])
+def test_device_state_calls_reject_bad_tensors_before_any_library_call(make):
+    """set_state_device / get_state_device hand a raw device pointer to the
+    library: a host tensor or a real-valued one must raise before that."""
+    torch = pytest.importorskip("torch")
+    ctx = _unbound_context()
+    t = make(torch)
+    with pytest.raises(ValueError):
+        ctx.set_state_device(t)
+    with pytest.raises(ValueError):
+        ctx.get_state_device(t)

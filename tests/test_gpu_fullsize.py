@@ -7,6 +7,7 @@ any size (norm conservation, exact plane waves, FP32 against FP64 bars, the
 ground-state virial identity).
 """
 import math
+import os
 import sys
 
 import numpy as np
@@ -57,43 +58,90 @@ def test_512_fp64_two_steps_match_oracle(psi512):
     assert rel(got, ref) < 1e-12
 
 
-def check_reduced(name, ref, got, err):
-    """The FP32 bars against the FP64 run: rel L2 <= 1e-4, norm drift <= 1e-6,
-    energy rel error <= 1e-5 (energy_bar), spectra within 1e-4 (L2 over
-    shells).  Prints the measured values."""
-    (o0, o1, _, sp64), (p0, p1, _, sp32) = ref, got
-    dn = abs(p1["norm"] - p0["norm"]) / p0["norm"]
-    de = abs(p1["energy"] - o1["energy"]) / abs(o1["energy"])
-    ds = max(np.linalg.norm(sp32[k] - sp64[k]) / np.linalg.norm(sp64[k])
-             for k in ("n_k", "e_comp", "e_incomp"))
-    say("%s vs fp64: rel L2 %.3g, norm drift %.3g, energy %.3g, spectra %.3g"
-        % (name, err, dn, de, ds))
-    return err, dn, de, ds
+def spectra_err(sp, ref):
+    """Largest relative L2 error over shells of the N, compressible and
+    incompressible spectra."""
+    return max(np.linalg.norm(sp[k] - ref[k]) / np.linalg.norm(ref[k])
+               for k in ("n_k", "e_comp", "e_incomp"))
 
 
-def test_512_fp64_1000_steps_norm_and_fp32_bars(psi512):
-    """1000 steps of the turbulence workload in FP64, FP32 and FP32 state with
-    FP64 arithmetic: FP64 norm drift <= 1e-12; each FP32 form against FP64:
-    rel L2 <= 1e-4, norm drift <= 1e-6, energy rel error <= 1e-5; spectra
-    agree to 1e-4 (L2 over shells)."""
-    say("512^3 fp64/fp32/fp32s 1000 steps")
-    res = {}
-    for prec in ("fp64", "fp32", "fp32s"):
-        with gpe.Context((512,) * 3, LO3, HI3, 1.0, precision=prec, norm_target=NORM3) as ctx:
-            ctx.set_state(psi512)
-            o0 = ctx.observables()
-            ctx.evolve(5e-4, 1000)
-            o1 = ctx.observables()
-            spec = ctx.spectra()
-            res[prec] = (o0, o1, ctx.get_state(), spec)
-    o0, o1, s64, sp64 = res["fp64"]
-    assert abs(o1["norm"] - o0["norm"]) / o0["norm"] < 1e-12
-    for prec in ("fp32", "fp32s"):
-        err, dn, de, ds = check_reduced(prec, res["fp64"], res[prec], rel(res[prec][2], s64))
-        assert err < 1e-4 and dn < 1e-6 and de < 1e-5 and ds < 1e-4, prec
-    # one rounding per pass instead of per operation: far inside the bars
-    err, dn, de, ds = check_reduced("fp32s", res["fp64"], res["fp32s"], rel(res["fp32s"][2], s64))
-    assert err < 1e-5 and dn < 1e-8 and de < 1e-6
+GOLDEN512 = os.path.join(os.path.dirname(os.path.abspath(__file__)), "golden",
+                         "turbulence_512_1000.npz")
+
+
+def test_512_1000_steps_fp64_vs_oracle_and_fp32_series(psi512):
+    """The turbulence workload at 512^3 for 1000 steps, observed every 100.
+
+    FP64 against the oracle's own 1000-step run (stored by
+    tests/golden/make_oracle_goldens.py): norm (1e-12) and energy (1e-11)
+    at every checkpoint, the four shell spectra (1e-10, L2 over shells), and
+    psi after 1000 steps at 65536 seeded sites (rel L2 over the sites and
+    largest deviation, both <= 1e-10 of max |psi|).  FP64 norm drift <= 1e-12.
+
+    Both FP32 forms, stepped in lockstep from the same state, against the FP64
+    run at every checkpoint: rel L2 <= 1e-4, norm drift <= 1e-6, energy rel
+    error <= 1e-5, spectra <= 1e-4."""
+    import torch
+
+    if not os.path.exists(GOLDEN512):
+        pytest.skip("oracle golden missing: run tests/golden/make_oracle_goldens.py turbulence")
+    gold = np.load(GOLDEN512)
+    keys = [str(k) for k in gold["obs_keys"]]
+    ik, ie = keys.index("norm"), keys.index("energy")
+    say("512^3 fp64 + fp32 forms, 1000 steps in lockstep")
+    dev0 = torch.from_numpy(psi512).to("cuda")
+    forms = ("fp64", "fp32s", "fp32")
+    ctxs = {p: gpe.Context((512,) * 3, LO3, HI3, 1.0, precision=p, norm_target=NORM3)
+            for p in forms}
+    worst = {p: dict(err=0.0, dn=0.0, de=0.0, ds=0.0) for p in forms[1:]}
+    try:
+        n0 = {}
+        for p, c in ctxs.items():
+            c.set_state_device(dev0)
+            n0[p] = c.observables()["norm"]
+        assert abs(n0["fp64"] - gold["obs"][0, ik]) < 1e-13 * NORM3
+        ref = torch.empty_like(dev0)
+        got = torch.empty_like(dev0)
+        for j, t in enumerate(gold["steps"][1:], start=1):
+            res = {}
+            for p, c in ctxs.items():
+                c.evolve(5e-4, 100)
+                res[p] = c.spectra(with_obs=True)
+            sp64, o64 = res["fp64"]
+            dn = abs(o64["norm"] - gold["obs"][j, ik]) / gold["obs"][j, ik]
+            de = abs(o64["energy"] - gold["obs"][j, ie]) / abs(gold["obs"][j, ie])
+            ds = max(np.linalg.norm(sp64[k] - gold[k][j]) / np.linalg.norm(gold[k][j])
+                     for k in ("n_k", "e_comp", "e_incomp", "e_qp"))
+            say("step %d fp64 vs oracle: norm %.3g energy %.3g spectra %.3g" % (t, dn, de, ds))
+            assert dn < 1e-12 and de < 1e-11 and ds < 1e-10, t
+            assert abs(o64["norm"] - n0["fp64"]) / n0["fp64"] < 1e-12
+            ctxs["fp64"].get_state_device(ref)
+            nref = float(torch.linalg.vector_norm(ref))
+            for p in forms[1:]:
+                ctxs[p].get_state_device(got)
+                sp, o = res[p]
+                w = worst[p]
+                w["err"] = max(w["err"], float(torch.linalg.vector_norm(got - ref)) / nref)
+                w["dn"] = max(w["dn"], abs(o["norm"] - n0[p]) / n0[p])
+                w["de"] = max(w["de"], abs(o["energy"] - o64["energy"]) / abs(o64["energy"]))
+                w["ds"] = max(w["ds"], spectra_err(sp, sp64))
+        # psi at the seeded sites after 1000 steps
+        idx = torch.from_numpy(gold["sites"].astype(np.int64)).to("cuda")
+        samp = ref.view(-1)[idx].cpu().numpy()
+        d = np.abs(samp - gold["psi"])
+        scale = float(np.abs(gold["psi"]).max())
+        say("psi at %d sites: rel L2 %.3g, max %.3g"
+            % (idx.numel(), np.linalg.norm(d) / np.linalg.norm(gold["psi"]), d.max() / scale))
+        assert np.linalg.norm(d) / np.linalg.norm(gold["psi"]) < 1e-10
+        assert d.max() < 1e-10 * scale
+    finally:
+        for c in ctxs.values():
+            c.close()
+    for p in forms[1:]:
+        w = worst[p]
+        say("%s vs fp64 (worst over checkpoints): rel L2 %.3g, norm drift %.3g, energy %.3g, "
+            "spectra %.3g" % (p, w["err"], w["dn"], w["de"], w["ds"]))
+        assert w["err"] < 1e-4 and w["dn"] < 1e-6 and w["de"] < 1e-5 and w["ds"] < 1e-4, p
 
 
 def test_512_plane_wave_exact():
@@ -107,9 +155,32 @@ def test_512_plane_wave_exact():
     assert rel(got, expect) < 1e-11
 
 
+def load_ground_golden():
+    """The oracle's 256^3 ground state (tests/golden/ground_state_256.txt):
+    stopping step, final observables and every check's energy."""
+    path = os.path.join(os.path.dirname(os.path.abspath(__file__)), "golden",
+                        "ground_state_256.txt")
+    if not os.path.exists(path):
+        pytest.skip("oracle golden missing: run tests/golden/make_oracle_goldens.py ground")
+    out, energies = {}, []
+    with open(path) as f:
+        for line in f:
+            if line.startswith("#") or not line.strip():
+                continue
+            k, v = line.split()
+            if k == "E":
+                energies.append(float(v))
+            else:
+                out[k] = float(v)
+    out["check_energies"] = energies
+    return out
+
+
 def test_256_ground_state_parity_and_virial():
     """256^3 on [-12,12)^3, trap (1, 2, 4), g = 50.  The first imaginary-time
-    steps match the oracle element by element; the converged state satisfies
+    steps match the oracle element by element; the converged run stops at the
+    oracle's stopping step with the oracle's energy (1e-10 relative) and
+    observables (1e-9); the converged state satisfies
     the 3D virial identity 2 E_kin - 2 E_pot + 3 E_int = 0 to O(dt).  Then the
     trap switches to isotropic and the state evolves in real time for 2000
     steps with observables every 10: the first 10 steps match the oracle, the
@@ -130,6 +201,16 @@ def test_256_ground_state_parity_and_virial():
         o = ctx.observables()
         gs = ctx.get_state()
     assert conv
+    gold = load_ground_golden()
+    say("256^3 ground state: %d steps (oracle %d), E %.15g (oracle %.15g)"
+        % (steps, gold["steps_done"], E, gold["energy"]))
+    # the stop rule fires where the change crosses tol; the oracle's margin there
+    ce = np.abs(np.diff(gold["check_energies"]))
+    assert ce[-1] < 0.9e-10 and ce[-2] > 1.1e-10  # no borderline check
+    assert steps == int(gold["steps_done"])
+    assert abs(E - gold["energy"]) < 1e-10 * abs(gold["energy"])
+    for k in ("mu", "e_kin", "e_pot", "e_int", "sigma_x", "sigma_y", "sigma_z", "r_rms"):
+        assert abs(o[k] - gold[k]) < 1e-9 * abs(gold[k]), k
     assert abs(o["norm"] - 1) < 1e-12
     virial = 2 * o["e_kin"] - 2 * o["e_pot"] + 3 * o["e_int"]
     # O(dt) bias of the split imaginary-time step: 3.1e-3 of E on 64^3 (oracle)
@@ -158,18 +239,18 @@ def test_256_ground_state_parity_and_virial():
     assert sz.max() > 1.2 * e0["sigma_z"]
 
 
-def test_1024_fp64_step_and_fp32_bars():
-    """The mixed-precision configuration at 1024^3: one FP64 step against the
-    oracle element by element, then 1000 steps in FP64, FP32 and FP32 state
-    with FP64 arithmetic from the same state, held to the FP32 bars (rel L2 <=
-    1e-4, norm drift <= 1e-6, energy <= 1e-5, spectra <= 1e-4).  States are
-    compared on the device.
+FP32_FFT_ENERGY_1024 = pytest.mark.xfail(
+    reason="FP32 FFT arithmetic: its rounding noise is white in k-space (rel L2 ~7e-6 after "
+           "1000 steps), and the kinetic energy of white noise grows with the mean |k|^2 of the "
+           "grid, 4x from 512^3 to 1024^3: energy error ~1.16e-5 against the 1e-5 bar",
+    strict=False)
 
-    The FP32 form (FP32 FFT) misses the energy bar here: its rounding noise is
-    white in k-space (rel L2 ~7e-6 after 1000 steps), and the kinetic energy
-    of white noise grows with the mean |k|^2 of the grid, 4x from 512^3 to
-    1024^3: measured 1.16e-5.  It is held to 2e-5; the FP32-state form meets
-    every bar."""
+
+@pytest.fixture(scope="module")
+def run1024():
+    """The mixed-precision configuration at 1024^3: one FP64 step against the
+    oracle element by element, then 1000 FP64 steps from the same state
+    (states compared on the device)."""
     import torch
 
     n = 1024
@@ -181,28 +262,53 @@ def test_1024_fp64_step_and_fp32_bars():
         ctx.set_state(psi0)
         ctx.evolve(5e-4, 1)
         got = ctx.get_state()
-    assert rel(got, ref) < 1e-12
+    one_step = rel(got, ref)
     del ref, got
     dev0 = torch.from_numpy(psi0).to("cuda")
     del psi0
-    res = {}
-    for prec in ("fp64", "fp32", "fp32s"):
-        say("1024^3 %s 1000 steps" % prec)
-        with gpe.Context((n,) * 3, LO3, HI3, 1.0, precision=prec, norm_target=NORM3) as ctx:
-            ctx.set_state_device(dev0)
-            o0 = ctx.observables()
-            ctx.evolve(5e-4, 1000)
-            o1 = ctx.observables()
-            spec = ctx.spectra()
-            out = torch.empty_like(dev0)
-            ctx.get_state_device(out)
-            ctx.synchronize()
-        res[prec] = (o0, o1, out, spec)
-    o0, o1, s64, sp64 = res["fp64"]
+    say("1024^3 fp64 1000 steps")
+    res = run_form(torch, dev0, "fp64")
+    yield one_step, dev0, res
+    del dev0, res
+    torch.cuda.empty_cache()
+
+
+def run_form(torch, dev0, prec, n=1024):
+    with gpe.Context((n,) * 3, LO3, HI3, 1.0, precision=prec, norm_target=NORM3) as ctx:
+        ctx.set_state_device(dev0)
+        o0 = ctx.observables()
+        ctx.evolve(5e-4, 1000)
+        o1 = ctx.observables()
+        spec = ctx.spectra()
+        out = torch.empty_like(dev0)
+        ctx.get_state_device(out)
+        ctx.synchronize()
+    return o0, o1, out, spec
+
+
+def test_1024_fp64_step_and_norm(run1024):
+    one_step, _, (o0, o1, _, _) = run1024
+    assert one_step < 1e-12
     assert abs(o1["norm"] - o0["norm"]) / o0["norm"] < 1e-12
-    for prec, energy_bar in (("fp32", 2e-5), ("fp32s", 1e-5)):
-        s = res[prec][2]
-        err = float(torch.linalg.vector_norm(s - s64) / torch.linalg.vector_norm(s64))
-        err, dn, de, ds = check_reduced("1024^3 " + prec, res["fp64"], res[prec], err)
-        assert err < 1e-4 and dn < 1e-6 and ds < 1e-4, prec
-        assert de < energy_bar, prec
+
+
+@pytest.mark.parametrize("prec", ["fp32s", pytest.param("fp32", marks=FP32_FFT_ENERGY_1024)])
+def test_1024_fp32_bars(run1024, prec):
+    """Each FP32 form at 1024^3, 1000 steps from the FP64 run's state, at the
+    FP32 bars against the FP64 run: rel L2 <= 1e-4, norm drift <= 1e-6,
+    energy <= 1e-5, spectra <= 1e-4."""
+    import torch
+
+    _, dev0, (o0, o1, s64, sp64) = run1024
+    say("1024^3 %s 1000 steps" % prec)
+    p0, p1, s, sp = run_form(torch, dev0, prec)
+    err = float(torch.linalg.vector_norm(s - s64) / torch.linalg.vector_norm(s64))
+    dn = abs(p1["norm"] - p0["norm"]) / p0["norm"]
+    de = abs(p1["energy"] - o1["energy"]) / abs(o1["energy"])
+    ds = spectra_err(sp, sp64)
+    say("1024^3 %s vs fp64: rel L2 %.3g, norm drift %.3g, energy %.3g, spectra %.3g"
+        % (prec, err, dn, de, ds))
+    del s
+    torch.cuda.empty_cache()
+    assert err < 1e-4 and dn < 1e-6 and ds < 1e-4
+    assert de < 1e-5

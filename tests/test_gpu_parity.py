@@ -250,53 +250,94 @@ def test_fp32_transform():
     assert rel(got, oracle.fft(x)) < 2e-6
 
 
+# The FP32 bars against the FP64 oracle: rel L2 <= 1e-4, norm drift <= 1e-6,
+# energy rel error <= 1e-5.  "fp32s" (FP32 state in HBM, FP64 arithmetic in
+# every pass) is the FP32 form the benchmark reports; "fp32" (FP32 state and
+# FP32 FFT) is held to the same bars and marked where it misses them.
+FP32_FFT_NORM = pytest.mark.xfail(
+    reason="FP32 FFT arithmetic: the rounding of the FP32 butterflies drifts the norm "
+           "~3.4e-6 per 1000 steps on the localised 2D trap state (bar 1e-6)", strict=False)
+_ORACLE_TURB = {}
+
+
+def oracle_turbulence(n, steps):
+    """The oracle's turbulence run, computed once per size for every form."""
+    if (n, steps) not in _ORACLE_TURB:
+        lo, hi = (0.0,) * 3, (2 * np.pi,) * 3
+        psi0 = I.phase_field(n, seed=2)
+        ref = oracle.tssp_real(psi0, lo, hi, None, 1.0, 5e-4, steps)
+        _ORACLE_TURB[(n, steps)] = (psi0, ref, oracle.observables(ref, lo, hi, None, 1.0))
+    return _ORACLE_TURB[(n, steps)]
+
+
+@pytest.mark.parametrize("prec", ["fp32s", "fp32"])
 @pytest.mark.parametrize("n", [64, 128])
-def test_fp32_turbulence_1000_steps(n):
-    """The turbulence workload at reduced size: FP32 state and FFT against the
-    FP64 oracle after 1000 steps: rel L2 <= 1e-4, norm drift <= 1e-6, energy
-    rel error <= 1e-5."""
-    say("fp32 turbulence", n)
+def test_fp32_turbulence_1000_steps(n, prec):
+    """The turbulence workload at reduced size: each FP32 form against the
+    FP64 oracle after 1000 steps at the FP32 bars."""
+    say("fp32 turbulence", n, prec)
     lo, hi = (0.0,) * 3, (2 * np.pi,) * 3
-    psi0 = I.phase_field(n, seed=2)
-    steps = 1000 if n == 64 else 200
-    ref = oracle.tssp_real(psi0, lo, hi, None, 1.0, 5e-4, steps)
-    o_ref = oracle.observables(ref, lo, hi, None, 1.0)
-    with gpe.Context((n, n, n), lo, hi, 1.0, precision="fp32",
+    psi0, ref, o_ref = oracle_turbulence(n, 1000)
+    with gpe.Context((n, n, n), lo, hi, 1.0, precision=prec,
                      norm_target=(2 * np.pi) ** 3) as ctx:
         ctx.set_state(psi0)
         n0 = ctx.observables()["norm"]
-        ctx.evolve(5e-4, steps)
+        ctx.evolve(5e-4, 1000)
         got = ctx.get_state()
         o = ctx.observables()
-    assert rel(got, ref) < 1e-4
-    assert abs(o["norm"] - n0) / n0 < 1e-6
-    assert abs(o["energy"] - o_ref["energy"]) / abs(o_ref["energy"]) < 1e-5
+    err, dn = rel(got, ref), abs(o["norm"] - n0) / n0
+    de = abs(o["energy"] - o_ref["energy"]) / abs(o_ref["energy"])
+    say("  rel L2 %.3g, norm drift %.3g, energy %.3g" % (err, dn, de))
+    assert err < 1e-4
+    assert dn < 1e-6
+    assert de < 1e-5
 
 
-def test_fp32_cfg0_1000_steps():
-    """FP32 on the 2D trap workload.  The norm-drift bar of 1e-6 is set for the
-    turbulence workload (checked above); a localised state in a strong trap
-    drifts ~3e-6 per 1000 steps from FP32 FFT rounding, so 1e-5 here."""
+@pytest.mark.parametrize("prec", ["fp32s", pytest.param("fp32", marks=FP32_FFT_NORM)])
+def test_fp32_cfg0_1000_steps(prec):
+    """Each FP32 form on the 2D trap workload, 1000 steps, at the FP32 bars
+    against the FP64 oracle."""
     shape, lo, hi, V, psi0 = cfg0()
     ref = oracle.tssp_real(psi0, lo, hi, V, 10.0, 1e-3, 1000)
-    with gpe.Context(shape, lo, hi, 10.0, harmonic=[1.0, 1.0], precision="fp32") as ctx:
+    o_ref = oracle.observables(ref, lo, hi, V, 10.0)
+    with gpe.Context(shape, lo, hi, 10.0, harmonic=[1.0, 1.0], precision=prec) as ctx:
         ctx.set_state(psi0)
+        n0 = ctx.observables()["norm"]
         ctx.evolve(1e-3, 1000)
         got = ctx.get_state()
         o = ctx.observables()
-    assert rel(got, ref) < 1e-4
-    assert abs(o["norm"] - 1) < 1e-5
+    err, dn = rel(got, ref), abs(o["norm"] - n0) / n0
+    de = abs(o["energy"] - o_ref["energy"]) / abs(o_ref["energy"])
+    say("2D trap %s: rel L2 %.3g, norm drift %.3g, energy %.3g" % (prec, err, dn, de))
+    assert err < 1e-4
+    assert de < 1e-5
+    assert dn < 1e-6
 
 
-def test_fp32_ground_state_matches_table():
+@pytest.mark.parametrize("prec", ["fp32s", "fp32"])
+def test_fp32_ground_state_matches_table(prec):
+    """A Table 1 row (2D, g = 62.742) in each FP32 form: the FP64 ground state
+    (stop rule at 1e-10) sets the step count; the FP32 run takes the same
+    number of imaginary-time steps (an energy stop rule at FP64 tolerances
+    would fire on FP32 rounding noise).  mu and r_rms within 1e-5 of the FP64
+    run; the FP64 run within 1e-3 of the printed values (the tolerance of the
+    oracle's own Table 1 pin; this grid is coarser than the oracle's)."""
     shape, lo, hi = (64, 64), (-12.0, -12.0), (12.0, 12.0)
-    with gpe.Context(shape, lo, hi, 62.742, harmonic=[1.0, 1.0], precision="fp32") as ctx:
+    with gpe.Context(shape, lo, hi, 62.742, harmonic=[1.0, 1.0]) as ctx:
         ctx.set_state(I.gaussian(shape, lo, hi))
-        steps, E, conv = ctx.ground_state(1e-3, tol=1e-8, check_every=10)
-        o = ctx.observables()
+        steps, E, conv = ctx.ground_state(1e-3, tol=1e-10, check_every=10)
+        o64 = ctx.observables()
     assert conv
-    assert abs(o["mu"] / 4.61136 - 1) < 2e-4
-    assert abs(o["r_rms"] / 1.78722 - 1) < 2e-4
+    assert abs(o64["mu"] / 4.61136 - 1) < 1e-3
+    assert abs(o64["r_rms"] / 1.78722 - 1) < 1e-3
+    with gpe.Context(shape, lo, hi, 62.742, harmonic=[1.0, 1.0], precision=prec) as ctx:
+        ctx.set_state(I.gaussian(shape, lo, hi))
+        ctx.imag_steps(1e-3, steps)
+        o = ctx.observables()
+    say("%s ground state after %d steps: mu %.9g (fp64 %.9g), r_rms %.9g (fp64 %.9g)"
+        % (prec, steps, o["mu"], o64["mu"], o["r_rms"], o64["r_rms"]))
+    assert abs(o["mu"] / o64["mu"] - 1) < 1e-5
+    assert abs(o["r_rms"] / o64["r_rms"] - 1) < 1e-5
 
 
 # ----------------------------------------- FP32 state, FP64 arithmetic ---

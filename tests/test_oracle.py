@@ -163,6 +163,63 @@ def test_linear_ground_state_energy():
     assert rel(np.abs(psi), np.abs(exact)) < 1e-6
 
 
+def _two_mode_energy(n_steps, a0, a1, k, dt):
+    """Energy after n imaginary-time steps of psi0 = a0 + a1 cos(k x) with
+    V = 0, g = 0, renormalised to 1 each step: the kinetic substep multiplies
+    the modes +-k by exp(-k^2 dt / 2) per step and leaves the mean alone, so
+    E_n = (k^2/2) (a1^2/2) e^(-k^2 n dt) / (a0^2 + (a1^2/2) e^(-k^2 n dt))."""
+    q = 0.5 * a1 * a1 * math.exp(-k * k * n_steps * dt)
+    return 0.5 * k * k * q / (a0 * a0 + q)
+
+
+@pytest.mark.parametrize("check_every", [3, 5, 10])
+def test_ground_state_stop_rule_closed_form(check_every):
+    """The stop rule of the imaginary-time ground state (energy every
+    check_every steps; stop at the first check whose energy differs from the
+    previous check's -- the initial state's for the first check -- by less than
+    tol, absolute).  The stopping step predicted from the closed-form energy
+    must be the oracle's exactly.  tol sits at the geometric mean of the two
+    energy changes around the predicted stop, so a relative tolerance, a wrong
+    check cadence or a comparison against the initial energy each stop
+    elsewhere (or never)."""
+    L, m, a0, a1 = 2 * np.pi, 2, 1.0, 0.6
+    k = 2 * np.pi * m / L
+    dt = 0.8 / (k * k * check_every)  # energy changes shrink by e^-0.8 per check
+    shape, lo, hi = (32,), (0.0,), (L,)
+    x = I.axes(shape, lo, hi)[0]
+    psi0 = (a0 + a1 * np.cos(k * x)).astype(np.complex128)
+    psi0 = I.normalise(psi0, shape, lo, hi)
+    E = [_two_mode_energy(j * check_every, a0, a1, k, dt) for j in range(200)]
+    dE = np.abs(np.diff(E))
+    stop_check = 8  # the check at which the rule should fire
+    tol = math.sqrt(dE[stop_check - 1] * dE[stop_check - 2])
+    # margins: the firing change is well below tol, the one before well above
+    assert dE[stop_check - 1] < 0.8 * tol and dE[stop_check - 2] > 1.25 * tol
+    psi, steps, En, conv = oracle.ground_state(psi0, lo, hi, None, 0.0, dt, tol=tol,
+                                               check_every=check_every, max_steps=10 ** 6)
+    assert conv
+    assert steps == stop_check * check_every
+    assert abs(En - E[stop_check]) < 1e-13
+    # a relative tolerance (tol * E) would fire elsewhere: E at the stop is far from 1
+    assert E[stop_check] < 0.2
+    # the cap: not converged, stopped at max_steps exactly
+    _, steps2, _, conv2 = oracle.ground_state(psi0, lo, hi, None, 0.0, dt, tol=tol,
+                                              check_every=check_every,
+                                              max_steps=stop_check * check_every - 1)
+    assert not conv2 and steps2 == stop_check * check_every - 1
+
+
+def test_ground_state_stop_rule_first_check_compares_with_the_start():
+    """A state that is already stationary (a constant, V = 0, g = 0) stops at
+    the first check: its energy equals the initial state's."""
+    shape, lo, hi = (16, 16), (0.0, 0.0), (1.0, 1.0)
+    psi0 = I.normalise(np.ones(shape, np.complex128), shape, lo, hi)
+    for c in (1, 4, 7):
+        _, steps, E, conv = oracle.ground_state(psi0, lo, hi, None, 0.0, 1e-3, tol=1e-12,
+                                                check_every=c, max_steps=1000)
+        assert conv and steps == c and abs(E) < 1e-14
+
+
 def test_table1_2d(golden):
     rows = golden("table1_2d.txt")
     shape, lo, hi = (64, 64), (-12.0, -12.0), (12.0, 12.0)
