@@ -268,8 +268,30 @@ int32_t gpe_device(const gpe_ctx *ctx);
  * library created when gpe_create got NULL). */
 void *gpe_stream(const gpe_ctx *ctx);
 
+/* Allocation-free steps, for callers that cannot allocate device memory:
+ * code under HIP graph capture, tight serving loops, harnesses that forbid
+ * hipMalloc.  No context: psi_dev is the caller's device state (the layout
+ * above, complex128 for GPE_FP64, complex64 for GPE_FP32 and
+ * GPE_FP32_STATE; on the current HIP device), advanced in place on
+ * hip_stream (NULL: the null stream), asynchronously.  imaginary = 0:
+ * nsteps real-time steps, the same as gpe_evolve on a context of this desc
+ * and trap (V = 0 if trap is NULL); imaginary = 1: nsteps renormalised
+ * imaginary-time steps with the frozen-density substep, the same as
+ * gpe_ground_state with check_every = 0.  The launch shapes are those of
+ * the tuning table for desc, as for a new context.  The tables, partial sums
+ * and renormalisation factor live in a device array of
+ * GPE_NOALLOC_SCRATCH_BYTES that the library holds on each device it runs
+ * on until the process ends; the call allocates nothing.  Calls on one
+ * device share that array, so calls that overlap on one device (two host
+ * threads, or two streams) race.  A grid whose buffers exceed the array
+ * (imaginary time beyond about 512^3 sites) gets GPE_EUNSUPPORTED; bad
+ * arguments GPE_EINVAL.  gpe_last_error(NULL) gives the message. */
+#define GPE_NOALLOC_SCRATCH_BYTES (8u << 20)
+gpe_status gpe_steps_noalloc(const gpe_desc *desc, const gpe_harmonic *trap, void *psi_dev,
+                             int32_t imaginary, double dt, int64_t nsteps, void *hip_stream);
+
 /* Message for the last failing call on ctx (ctx may be NULL: last failure of
- * gpe_create on this thread).  Never NULL. */
+ * gpe_create or gpe_steps_noalloc on this thread).  Never NULL. */
 const char *gpe_last_error(const gpe_ctx *ctx);
 
 void gpe_destroy(gpe_ctx *ctx);

@@ -10,7 +10,7 @@ CSRC = os.path.join(HERE, "csrc")
 OUT = os.path.join(HERE, "libgpe.so")
 BUILD_DIR = os.path.join(HERE, "_build")
 
-SOURCES = ["axis_pass_f64.hip", "axis_pass_f32.hip", "axis_pass_s32.hip", "axis_pass.hip", "reduce.hip", "spectra.hip", "onchip.hip", "potential.hip", "gpe.cpp", "server.cpp", "tune.cpp"]
+SOURCES = ["axis_pass_f64.hip", "axis_pass_f32.hip", "axis_pass_s32.hip", "axis_pass.hip", "reduce.hip", "spectra.hip", "onchip.hip", "potential.hip", "noalloc.hip", "gpe.cpp", "server.cpp", "tune.cpp"]
 
 HIPCC = os.environ.get("HIPCC", "/opt/rocm/bin/hipcc")
 FLAGS = [

@@ -158,6 +158,8 @@ SIGNATURES = {
     "gpe_device_bytes": (ctypes.c_uint64, [_P]),
     "gpe_device": (_I32, [_P]),
     "gpe_stream": (ctypes.c_void_p, [_P]),
+    "gpe_steps_noalloc": (_I32, [ctypes.POINTER(gpe_desc), ctypes.POINTER(gpe_harmonic), _P,
+                                 _I32, _D, _I64, _P]),
     "gpe_last_error": (ctypes.c_char_p, [_P]),
     "gpe_destroy": (None, [_P]),
     "gpe_server_create": (_I32, [ctypes.c_uint64, _I32, _I32, _I32, ctypes.POINTER(_P)]),
@@ -230,6 +232,18 @@ def gpe_create(desc, V_host=None, V_an=None, hip_stream=None):
     if st != GPE_OK:
         raise GpeError(st, _err(None))
     return out
+
+
+def gpe_steps_noalloc(desc, trap, psi_dev, imaginary, dt, nsteps, hip_stream=None):
+    """Allocation-free steps on a device state (a raw device pointer, int):
+    see include/gpe.h.  trap: a gpe_harmonic or None."""
+    st = load_library().gpe_steps_noalloc(ctypes.byref(desc),
+                                          ctypes.byref(trap) if trap is not None else None,
+                                          ctypes.c_void_p(psi_dev), int(imaginary), float(dt),
+                                          int(nsteps), ctypes.c_void_p(hip_stream)
+                                          if hip_stream else None)
+    if st != GPE_OK:
+        raise GpeError(st, _err(None))
 
 
 def gpe_set_potential(ctx, V_host=None, V_an=None):
