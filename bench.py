@@ -451,8 +451,8 @@ def main():
     ap.add_argument("--no-ground-state", action="store_true",
                     help="skip the 256^3 ground state + trap-switch dynamics timing")
     ap.add_argument("--serving-chunk", type=int, default=16)
-    ap.add_argument("--serving-light-rate", type=float, default=8.0,
-                    help="arrival rate (1/s) of the second serving run, below the GPU's "
+    ap.add_argument("--serving-light-rate", type=float, default=13.0,
+                    help="arrival rate (1/s) of the second serving run, about 0.7 of the GPU's "
                          "capacity for the mix (0: skip)")
     ap.add_argument("--no-dynamics", action="store_true",
                     help="skip the dynamics-validation (Gaussian breathing) timing")

@@ -352,7 +352,18 @@ gpe_status gpe_tuning_load(const char *path);
  * about the same GPU time per round (1 ms), and finishes the requests that
  * the previous round completed while the GPU runs the current one.  Requests
  * of any size mix; each one's arithmetic does not depend on what else runs,
- * nor on how its steps are cut into chunks.
+ * nor on how its steps are cut into chunks.  Requests of 2^23 grid points or
+ * more (the heavy tier) run first come, first served among themselves, one
+ * at a time, beside the lighter requests: a heavy request waiting for the
+ * tier does not hold back the requests queued behind it.
+ *
+ * Beyond the request/poll/cancel calls a plain submit-and-wait interface
+ * needs, this interface adds: max_active and chunk_steps at creation,
+ * keep_state in a request (a result carries observables; the final state
+ * only when asked for), the final state as a separate poll argument
+ * (caller-owned, so a result record holds no pointer), release of finished
+ * records, wait_idle, statistics, and gpe_request_bytes for capacity
+ * planning.
  * ---------------------------------------------------------------------- */
 typedef struct gpe_server gpe_server; /* opaque, library-owned */
 

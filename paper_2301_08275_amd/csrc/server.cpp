@@ -41,6 +41,7 @@
 #include <vector>
 
 #include "gpe_ctx.h"
+#include "sched_policy.h"
 
 using namespace gpe_host;
 
@@ -62,6 +63,7 @@ struct Req {
   bool cancel = false;
   uint64_t need = 0;        // device bytes a fresh slot context takes
   uint64_t need_class = 0;  // device bytes a new shape class takes
+  bool heavy = false;       // in the heavy tier (first come, first served)
 };
 
 struct ClassKey {
@@ -143,6 +145,10 @@ struct gpe_server {
   bool use_graph = true;
   bool use_onchip = true;
   double quantum_ms = 1.0;  // GPU time per running request per round
+  // Heavy tier: requests of at least heavy_sites points run first come,
+  // first served, at most heavy_active at once, beside the lighter ones.
+  long long heavy_sites = 1LL << 23;
+  int heavy_active = 1;
   std::mutex mu;
   std::condition_variable cv_work, cv_done;
   std::deque<uint64_t> queue;
@@ -150,6 +156,7 @@ struct gpe_server {
   std::vector<ShapeClass *> classes;  // touched by the scheduler thread only
   uint64_t next_id = 1;
   int running = 0;
+  int running_heavy = 0;
   bool stop = false;
   std::thread th;
   std::chrono::steady_clock::time_point t0;
@@ -245,33 +252,20 @@ gpe_status enqueue_step(gpe_server *s, ShapeClass *c, int k) {
              : GPE_EDEVICE;
 }
 
-// Steps to give class c in this scheduling pass: quantum_ms of GPU time per running
-// request, from the GPU time per step measured on its last chunk.  Large
-// grids are bandwidth-bound (time grows with the running slots); small ones
-// are launch-bound (it does not), and run whole graph replays.  On-chip
-// classes run beside the main stream on a few CUs: they are paced to last
-// about as long as the main stream's last round.
+// Steps to give class c in this scheduling pass (gpe_sched::chunk_steps).
 int steps_for(gpe_server *s, ShapeClass *c) {
-  const int run = std::max(1, c->running);
-  double ms = c->step_ms;
-  if (c->onchip) {
-    if (ms <= 0) return s->chunk;
-    const double target = std::max(s->quantum_ms * run, s->main_round_ms);
-    return (int)std::max(1LL, std::min(65536LL, std::llround(target / ms)));
-  }
-  if (ms <= 0) {
-    if (c->use_graph) return s->chunk;
-    const double bytes = 6.0 * (double)run * (double)c->proto->sites * (double)c->proto->esize;
-    ms = 0.02 + bytes / 4.0e9;  // about 4 TB/s per pass, read and write
-  } else if (!c->use_graph && c->step_running > 0) {
-    ms *= (double)run / (double)c->step_running;
-  }
-  const double k = s->quantum_ms * run / ms;
-  if (c->use_graph) {
-    const long long reps = std::max(1LL, std::min(256LL, std::llround(k / s->chunk)));
-    return (int)(reps * s->chunk);
-  }
-  return (int)std::max(1LL, std::min(4096LL, std::llround(k)));
+  gpe_sched::ChunkInput in;
+  in.running = c->running;
+  in.step_ms = c->step_ms;
+  in.step_running = c->step_running;
+  in.use_graph = c->use_graph;
+  in.onchip = c->onchip;
+  in.chunk = s->chunk;
+  in.quantum_ms = s->quantum_ms;
+  in.main_round_ms = s->main_round_ms;
+  in.sites = (double)c->proto->sites;
+  in.esize = (double)c->proto->esize;
+  return gpe_sched::chunk_steps(in);
 }
 
 gpe_status run_chunk(gpe_server *s, ShapeClass *c, int steps) {
@@ -495,7 +489,7 @@ void clear_entry(gpe_server *s, ShapeClass *c, int i) {
   (void)gpe::launch_slot_write(c->d + i, sl, c->strm);
 }
 
-void release(gpe_server *s, ShapeClass *c, int i) {
+void release(gpe_server *s, ShapeClass *c, int i, const Req *r) {
   if (c->sstate[i] == SS_RUN) --c->running;
   c->owner[i] = 0;
   c->sstate[i] = SS_FREE;
@@ -503,6 +497,7 @@ void release(gpe_server *s, ShapeClass *c, int i) {
   c->map_dirty = true;
   std::lock_guard<std::mutex> lk(s->mu);
   --s->running;
+  if (r->heavy) --s->running_heavy;
 }
 
 // Slot i finished its steps (seen in a read-back): final scaling, observables
@@ -526,7 +521,7 @@ void complete(gpe_server *s, ShapeClass *c, int i, Req *r) {
     if (gpe_get_state(x, r->psi_out.data()) != GPE_OK) st = GPE_EDEVICE;
   }
   clear_entry(s, c, i);
-  release(s, c, i);
+  release(s, c, i, r);
   finish(s, r, st);
 }
 
@@ -563,7 +558,7 @@ void retire(gpe_server *s, long long q, long long now) {
         if (q >= c->drain_until[i]) {
           const gpe_status why = c->drain_status[i];
           r->steps_done = std::min<int64_t>(r->steps_done, c->steps_total[i]);
-          release(s, c, i);
+          release(s, c, i, r);
           finish(s, r, why);
         }
         continue;
@@ -583,14 +578,16 @@ void retire(gpe_server *s, long long q, long long now) {
 }
 
 // Admit queued requests in arrival order, one at a time, so that the bytes
-// charged for each are known before the next decision.
+// charged for each are known before the next decision (gpe_sched::admit_decision:
+// a heavy request waiting for its tier lets the requests behind it pass).
 void admit_queued(gpe_server *s, long long round) {
+  size_t at = 0;  // queue position: entries before it wait for the heavy tier
   for (;;) {
     std::unique_lock<std::mutex> lk(s->mu);
-    if (s->stop || s->queue.empty()) return;
-    Req *r = s->reqs[s->queue.front()].get();
+    if (s->stop || at >= s->queue.size()) return;
+    Req *r = s->reqs[s->queue[at]].get();
     if (r->cancel) {
-      s->queue.pop_front();
+      s->queue.erase(s->queue.begin() + at);
       r->state = RQ_DONE;
       r->status = GPE_ECANCELED;
       r->t_done = now_s(s);
@@ -598,7 +595,6 @@ void admit_queued(gpe_server *s, long long round) {
       s->cv_done.notify_all();
       continue;
     }
-    if (s->max_active > 0 && s->running >= s->max_active) return;
     ShapeClass *c = find_class(s, key_of(r->r));
     bool warm = false, free_slot = c == nullptr;
     if (c)
@@ -607,22 +603,39 @@ void admit_queued(gpe_server *s, long long round) {
           free_slot = true;
           warm = warm || c->ctx[j] != nullptr;
         }
-    if (!free_slot) return;
-    const uint64_t need = (warm ? 0 : r->need) + (c ? 0 : r->need_class);
-    if (s->used + need > s->budget) {
-      reclaim(s, need, key_of(r->r));
-      if (s->used + need > s->budget) return;
+    gpe_sched::AdmitInput in;
+    in.heavy = r->heavy;
+    in.running = s->running;
+    in.max_active = s->max_active;
+    in.running_heavy = s->running_heavy;
+    in.heavy_active = s->heavy_active;
+    in.free_slot = free_slot;
+    in.need = (warm ? 0 : r->need) + (c ? 0 : r->need_class);
+    in.used = s->used;
+    in.budget = s->budget;
+    gpe_sched::Admit d = gpe_sched::admit_decision(in);
+    if (d == gpe_sched::kStop && free_slot && in.used + in.need > in.budget) {
+      reclaim(s, in.need, key_of(r->r));
+      in.used = s->used;
+      d = gpe_sched::admit_decision(in);
     }
-    s->queue.pop_front();
+    if (d == gpe_sched::kSkip) {
+      ++at;
+      continue;
+    }
+    if (d == gpe_sched::kStop) return;
+    s->queue.erase(s->queue.begin() + at);
     r->state = RQ_RUNNING;
     r->t_start = now_s(s);
     ++s->running;
+    if (r->heavy) ++s->running_heavy;
     lk.unlock();
     const gpe_status st = admit(s, r, round);
     if (st != GPE_OK) {
       {
         std::lock_guard<std::mutex> lk2(s->mu);
         --s->running;
+        if (r->heavy) --s->running_heavy;
       }
       finish(s, r, st == GPE_EBUSY ? GPE_EDEVICE : st);
     }
@@ -679,7 +692,7 @@ void scheduler(gpe_server *s) {
     for (int i = 0; i < c->S; ++i)
       if (c->owner[i]) {
         Req *r = req_of(s, c->owner[i]);
-        release(s, c, i);
+        release(s, c, i, r);
         finish(s, r, GPE_ECANCELED);
       }
 }
@@ -735,6 +748,8 @@ gpe_status gpe_server_create(uint64_t hbm_budget_bytes, int32_t max_slots, int32
     const double v = std::atof(q);
     if (v > 0) s->quantum_ms = v;
   }
+  if (const char *h = std::getenv("GPE_SERVER_HEAVY_SITES")) s->heavy_sites = std::atoll(h);
+  if (const char *h = std::getenv("GPE_SERVER_HEAVY_ACTIVE")) s->heavy_active = std::atoi(h);
   s->t0 = std::chrono::steady_clock::now();
   s->th = std::thread(scheduler, s);
   *out = s;
@@ -767,6 +782,7 @@ gpe_status gpe_server_submit(gpe_server *s, const gpe_request *req, uint64_t *id
   }
   r->need = context_bytes(d);
   r->need_class = class_bytes(d, s->max_slots);
+  r->heavy = gpe_sched::is_heavy(sites_of(d), s->heavy_sites);
   if (r->need + r->need_class > s->budget) return GPE_ENOMEM;
   std::lock_guard<std::mutex> lk(s->mu);
   r->id = s->next_id++;

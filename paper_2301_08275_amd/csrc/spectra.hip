@@ -5,10 +5,12 @@
 // are unpacked per wavenumber from Z_j(k) and Z_j(-k):
 //   U_j(k) = (Z_j(k) + conj(Z_j(-k))) / 2,  W_j(k) = (Z_j(k) - conj(Z_j(-k))) / (2i),
 // U is split into k (k.U)/|k|^2 (compressible) and the rest (incompressible;
-// k = 0 belongs there), and |.|^2 is summed per shell round(|k|/dk).  Each
-// workgroup keeps its histogram in LDS (FP64 atomics, one per run of equal
-// shells in a wavefront) and writes it out; a second kernel adds the
-// workgroup histograms in a fixed order.
+// k = 0 belongs there), and |.|^2 is summed per shell round(|k|/dk).  Every
+// sum is taken in a fixed order, so the spectra are bitwise reproducible: a
+// wavefront adds the runs of equal shells among its lanes by a fixed-order
+// scan and accumulates them, in its own program order, into a histogram of
+// its own in LDS; the workgroup adds its wavefronts' histograms in wavefront
+// order; a second kernel adds the workgroup histograms in workgroup order.
 #include "gpe_kernels.h"
 
 namespace gpe {
@@ -87,20 +89,46 @@ __device__ __forceinline__ ShellSite shell_site(const ShellArgs &a, long long s,
   return q;
 }
 
+// Add v (the sum of a run of equal shells, held by the run's last lane) to
+// bin `bin` of this wavefront's histogram h.  The 64 sites of a wavefront are
+// consecutive and aligned: when the last axis has at least 128 points they
+// lie in one half of one row, where the shell index is monotone, so the runs
+// of one instruction have distinct bins and update h together; otherwise
+// runs of different rows may share a bin and the last lanes add one at a
+// time in lane order.
+__device__ __forceinline__ void add_run(double *h, int bin, double v, bool last, bool rows_apart,
+                                        int lane) {
+  if (!rows_apart) {
+    if (last) h[bin] += v;
+    return;
+  }
+  unsigned long long m = __ballot(last);
+  while (m) {
+    const int l = __ffsll((unsigned long long)m) - 1;
+    if (lane == l) h[bin] += v;
+    m &= m - 1;
+  }
+}
+
 // Every lane of a wavefront runs the same number of iterations (the shuffles
 // need them all); a lane past the end or with nothing to add carries key -1.
 // Within a wavefront the sites are consecutive: within one row (fixed i0, i1)
 // and one half of the last axis the shell index is monotone in i2, so equal
 // bins form contiguous runs keyed by (row, half, bin); each run is summed
-// across lanes in fixed order and added to the LDS histogram by its last lane
-// (a few atomics per wavefront instead of one per site).  Each iteration
-// takes U blocks of sites and issues all their loads before any arithmetic.
+// across lanes in fixed order and added to the wavefront's histogram by its
+// last lane.  Each iteration takes U blocks of sites and issues all their
+// loads before any arithmetic.
 template <typename T, int KIND, int U>
 __global__ void __launch_bounds__(kShellThreads) shell_kernel(const ShellArgs a) {
-  extern __shared__ double hist[];  // 4 * nbins
-  const int nb = a.nbins;
-  for (int i = threadIdx.x; i < 4 * nb; i += blockDim.x) hist[i] = 0;
+  // one histogram (kind 0) or three (kind 1: compressible, incompressible,
+  // quantum pressure) of nbins per wavefront
+  constexpr int NH = KIND == 0 ? 1 : 3;
+  extern __shared__ double hist[];
+  const int nb = a.nbins, nw = blockDim.x >> 6;
+  for (int i = threadIdx.x; i < nw * NH * nb; i += blockDim.x) hist[i] = 0;
   __syncthreads();
+  double *h = hist + (threadIdx.x >> 6) * NH * nb;
+  const bool rows_apart = a.n[2] < 128;
   const int l1 = log2_of(a.n[1]), l2 = log2_of(a.n[2]), n2 = a.n[2];
   const long long sites = (long long)a.n[0] * a.n[1] * a.n[2];
   const int lane = threadIdx.x & 63;
@@ -133,7 +161,7 @@ __global__ void __launch_bounds__(kShellThreads) shell_kernel(const ShellArgs a)
         const double e = run_sum(
             a.w * ((double)zp[u][0].x * zp[u][0].x + (double)zp[u][0].y * zp[u][0].y), q[u].key,
             lane);
-        if (last) atomicAdd(&hist[q[u].bin], e);
+        add_run(h, q[u].bin, e, last, rows_apart, lane);
       } else {
         double csum = 0, isum = 0, qsum = 0;
         if (q[u].on) {
@@ -169,17 +197,22 @@ __global__ void __launch_bounds__(kShellThreads) shell_kernel(const ShellArgs a)
         csum = run_sum(csum, q[u].key, lane);
         isum = run_sum(isum, q[u].key, lane);
         qsum = run_sum(qsum, q[u].key, lane);
-        if (last) {
-          atomicAdd(&hist[nb + q[u].bin], csum);
-          atomicAdd(&hist[2 * nb + q[u].bin], isum);
-          atomicAdd(&hist[3 * nb + q[u].bin], qsum);
-        }
+        add_run(h, q[u].bin, csum, last, rows_apart, lane);
+        add_run(h + nb, q[u].bin, isum, last, rows_apart, lane);
+        add_run(h + 2 * nb, q[u].bin, qsum, last, rows_apart, lane);
       }
     }
   }
   __syncthreads();
+  // row of this workgroup: N(n) in [0, nb), the energies in [nb, 4 nb)
   double *out = a.partial + (long long)blockIdx.x * 4 * nb;
-  for (int i = threadIdx.x; i < 4 * nb; i += blockDim.x) out[i] = hist[i];
+  for (int i = threadIdx.x; i < 4 * nb; i += blockDim.x) {
+    const int j = KIND == 0 ? i : i - nb;  // index within the wavefront histograms
+    double t = 0;
+    if (j >= 0 && j < NH * nb)
+      for (int w = 0; w < nw; ++w) t += hist[w * NH * nb + j];
+    out[i] = t;
+  }
 }
 
 // Column sums of a [count][len] array in fixed order: a block of 64 columns
@@ -215,23 +248,28 @@ int shell_blocks(long long sites) {
 hipError_t launch_shells(int precision, const ShellArgs &a, hipStream_t s) {
   const long long sites = (long long)a.n[0] * a.n[1] * a.n[2];
   const int blocks = shell_blocks(sites);
-  const size_t lds = 4 * (size_t)a.nbins * sizeof(double);
-  if (lds > 64 * 1024) return hipErrorInvalidValue;
+  // as many wavefronts (at most four) as have room for their histograms in
+  // 64 KiB of LDS
+  const size_t per_wave = (a.kind == 0 ? 1 : 3) * (size_t)a.nbins * sizeof(double);
+  const size_t max_lds = 64 * 1024;
+  int waves = (int)(max_lds / per_wave);
+  if (waves < 1) return hipErrorInvalidValue;
+  if (waves > kShellThreads / 64) waves = kShellThreads / 64;
+  const size_t lds = waves * per_wave;
+  const dim3 threads(64 * waves);
   // the packed fields are stored like the state
   if (state_f32(precision)) {
     if (a.kind == 0)
-      hipLaunchKernelGGL((shell_kernel<float, 0, kShellU0>), dim3(blocks), dim3(kShellThreads), lds,
+      hipLaunchKernelGGL((shell_kernel<float, 0, kShellU0>), dim3(blocks), threads, lds,
                          s, a);
     else
-      hipLaunchKernelGGL((shell_kernel<float, 1, kShellU1>), dim3(blocks), dim3(kShellThreads), lds,
+      hipLaunchKernelGGL((shell_kernel<float, 1, kShellU1>), dim3(blocks), threads, lds,
                          s, a);
   } else {
     if (a.kind == 0)
-      hipLaunchKernelGGL((shell_kernel<double, 0, kShellU0>), dim3(blocks), dim3(kShellThreads),
-                         lds, s, a);
+      hipLaunchKernelGGL((shell_kernel<double, 0, kShellU0>), dim3(blocks), threads, lds, s, a);
     else
-      hipLaunchKernelGGL((shell_kernel<double, 1, kShellU1>), dim3(blocks), dim3(kShellThreads),
-                         lds, s, a);
+      hipLaunchKernelGGL((shell_kernel<double, 1, kShellU1>), dim3(blocks), threads, lds, s, a);
   }
   return hipGetLastError();
 }

@@ -202,6 +202,9 @@ SPECTRA_CASES = [
     ((64, 32), (-3.0, -2.0), (3.0, 2.0)),
     ((32, 32), (-3.0, -3.0), (3.0, 3.0)),     # 2D with integer shells
     ((8, 8, 8), (0.0,) * 3, (2 * np.pi,) * 3),
+    # last axis of 128 or more: a wavefront's sites lie in one half-row
+    ((8, 16, 128), (0.0,) * 3, (1.0, 1.5, 6.0)),
+    ((16, 256), (-3.0, -4.0), (3.0, 4.0)),
 ]
 
 
@@ -218,6 +221,28 @@ def test_spectra_parity(shape, lo, hi):
     for key in ("n_k", "e_comp", "e_incomp", "e_qp"):
         scale = max(1e-300, float(np.sum(ref[key])))
         assert np.abs(got[key] - ref[key]).max() <= 1e-12 * scale, key
+
+
+@pytest.mark.parametrize("shape,lo,hi,prec", [
+    ((128, 128, 128), (0.0,) * 3, (2 * np.pi,) * 3, "fp64"),   # a wavefront in one half-row
+    ((16, 32, 64), (0.0,) * 3, (1.0, 2.0, 3.0), "fp64"),       # wavefronts span rows
+    ((64, 64), (-4.0, -4.0), (4.0, 4.0), "fp64"),
+    ((128, 128, 128), (0.0,) * 3, (2 * np.pi,) * 3, "fp32s"),
+])
+def test_spectra_are_bitwise_reproducible(shape, lo, hi, prec):
+    """Every shell sum is taken in a fixed order: the same state gives the same
+    spectra bit for bit, call after call and context after context."""
+    rng = np.random.default_rng(11)
+    psi = (1.0 + 0.4 * rng.standard_normal(shape)) * np.exp(1j * rng.standard_normal(shape))
+    runs = []
+    for _ in range(2):
+        with gpe.Context(shape, lo, hi, 1.0, precision=prec) as ctx:
+            ctx.set_state(psi)
+            runs.append(ctx.spectra())
+            runs.append(ctx.spectra())
+    for r in runs[1:]:
+        for key in ("n_k", "e_comp", "e_incomp", "e_qp"):
+            assert np.array_equal(r[key], runs[0][key]), key
 
 
 def test_spectra_cfg2_initial_state():
