@@ -337,30 +337,71 @@ __device__ __forceinline__ void lds_sync() {
   }
 }
 
+// LDS row of position p (one padding slot after every eight positions), and
+// its split over the two parts of a stage position: pos(s, q, d) =
+// qpart(q) + d * stride(s), with q from the thread and d a compile-time digit.
+// row(qpart + d st) = row(qpart) + row(d st) whenever the two parts never
+// carry into bit 3 together, which holds for every plan here (checked at
+// compile time): a thread forms one base address per stage and reaches each
+// element at a compile-time offset from it (few address registers, offsets
+// folded into the LDS instructions).
+__host__ __device__ constexpr int lds_row(int p) { return p + (p >> 3); }
+template <class PL, int S>
+__host__ __device__ constexpr int qpart(int q) {
+  return (q % PL::stride(S)) + (q / PL::stride(S)) * PL::stride(S) * PL::rad(S);
+}
+template <class PL, int S>
+constexpr bool rows_split() {
+  for (int q = 0; q < PL::N / PL::rad(S); ++q)
+    for (int d = 0; d < PL::rad(S); ++d)
+      if (lds_row(qpart<PL, S>(q) + d * PL::stride(S)) !=
+          lds_row(qpart<PL, S>(q)) + lds_row(d * PL::stride(S)))
+        return false;
+  return true;
+}
+
+// LDS index of the element at position qpart + d st of column / line c:
+// base (from the thread) plus a compile-time offset (from the digit).
+template <int N, int W, bool STRIDED>
+__device__ __forceinline__ int lds_base(int qp, int c) {
+  return STRIDED ? W * lds_row(qp) + c : c * Lds<N, W, STRIDED>::line + lds_row(qp);
+}
+template <int W, bool STRIDED>
+__host__ __device__ constexpr int lds_off(int dp) {
+  return STRIDED ? W * lds_row(dp) : lds_row(dp);
+}
+
 // Move the E registers from the stage-A layout to the stage-B layout.
 template <class PL, int W, bool STRIDED, int A, int B, typename T>
 __device__ __forceinline__ void exchange(cx<T> *v, int t, int c, T *lre, T *lim,
                                          bool first) {
-  using L = Lds<PL::N, W, STRIDED>;
-  constexpr int RA = PL::rad(A), RB = PL::rad(B);
+  constexpr int RA = PL::rad(A), RB = PL::rad(B), SA = PL::stride(A), SB = PL::stride(B);
+  static_assert(rows_split<PL, A>() && rows_split<PL, B>(),
+                "LDS rows must split over the stage positions");
   if (!first) lds_sync<PL, W, STRIDED>();
 #pragma unroll
-  for (int b = 0; b < PL::E / RA; ++b)
+  for (int b = 0; b < PL::E / RA; ++b) {
+    const int i0 = lds_base<PL::N, W, STRIDED>(qpart<PL, A>(t + PL::TPL * b), c);
+    T *__restrict__ r = lre + i0;
+    T *__restrict__ m = lim + i0;
 #pragma unroll
     for (int d = 0; d < RA; ++d) {
-      const int i = L::idx(PL::pos(A, t + PL::TPL * b, d), c);
-      lre[i] = v[b * RA + d].x;
-      lim[i] = v[b * RA + d].y;
+      r[lds_off<W, STRIDED>(d * SA)] = v[b * RA + d].x;
+      m[lds_off<W, STRIDED>(d * SA)] = v[b * RA + d].y;
     }
+  }
   lds_sync<PL, W, STRIDED>();
 #pragma unroll
-  for (int b = 0; b < PL::E / RB; ++b)
+  for (int b = 0; b < PL::E / RB; ++b) {
+    const int i0 = lds_base<PL::N, W, STRIDED>(qpart<PL, B>(t + PL::TPL * b), c);
+    const T *__restrict__ r = lre + i0;
+    const T *__restrict__ m = lim + i0;
 #pragma unroll
     for (int d = 0; d < RB; ++d) {
-      const int i = L::idx(PL::pos(B, t + PL::TPL * b, d), c);
-      v[b * RB + d].x = lre[i];
-      v[b * RB + d].y = lim[i];
+      v[b * RB + d].x = r[lds_off<W, STRIDED>(d * SB)];
+      v[b * RB + d].y = m[lds_off<W, STRIDED>(d * SB)];
     }
+  }
 }
 
 template <class PL, int W, bool STRIDED, typename T>
