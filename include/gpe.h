@@ -316,8 +316,19 @@ typedef struct {
                              instead of 16, 8, 8 with 16) */
   int32_t stream[3];      /* per axis, the step passes' non-temporal (streaming)
                              cache policy: bit 0 loads, bit 1 stores (0..3) */
+  int32_t transpose;      /* 3D grids of more than 2^20 sites: 1 = the step passes
+                             rotate the grid.  Each reads whole lines of its axis and
+                             writes them, as rows of width[axis] sites, to a second
+                             state array (allocated on first use) in the layout the
+                             next pass reads; the axes go in the order 2, 0, 1, so
+                             that every step starts and ends in the stored layout.
+                             width, xcd_remap and stream then describe the rotating
+                             passes on all three axes; the read-only passes
+                             (observables, transforms, spectra) take the class's
+                             defaults, in pass_order.  0 = in-place passes */
   double ms_per_step;     /* measured real-time step (gpe_autotune), else 0 */
-} gpe_tuning;             /* entries beyond dim (and width/xcd_remap of the last axis) are 0 */
+} gpe_tuning;             /* entries beyond dim (and width/xcd_remap of the last axis
+                             unless transpose) are 0 */
 
 /* Time the real-time step of this shape class on the current device: per
  * axis every radix plan x width x tile order x streaming policy, then every
@@ -325,7 +336,10 @@ typedef struct {
  * current entry or the defaults; `steps` timed
  * steps per candidate, the minimum of three runs; a candidate must be more
  * than 1% faster than the incumbent to replace it), record the result in the
- * table and copy it to *out (nullable).  Allocates a scratch context of the
+ * table and copy it to *out (nullable).  On 3D grids of more than 2^20 sites
+ * the rotating step passes (transpose = 1) are searched the same way from
+ * 8-column tiles and kept when faster.  With GPE_TUNE_VERBOSE=1 in the
+ * environment every candidate and its time go to stderr.  Allocates a scratch context of the
  * class for the duration of the call.  g, box and norm_target of desc are not
  * used. */
 gpe_status gpe_autotune(const gpe_desc *desc, int32_t steps, gpe_tuning *out);

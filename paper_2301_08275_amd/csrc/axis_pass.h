@@ -686,9 +686,11 @@ axis_pass_kernel(const PassArgs a) {
   const int t = STRIDED ? (tid / W) : (tid % TPL);
   const int n1 = a.n[1], n2 = a.n[2];
 
-  // Line geometry: element p of this thread's line sits at base + p * S; its
-  // site coordinates are (j0, j1, j2) with the axis coordinate replaced by p.
-  long long base, S;
+  // Line geometry: element p of this thread's line is read at bin + p * Sin
+  // and written at bout + p * Sout (the same place unless the pass rotates);
+  // its site coordinates are (j0, j1, j2) with the axis coordinate replaced
+  // by p.
+  long long bin, Sin, bout, Sout;
   int j0 = 0, j1 = 0, j2 = 0;
   bool valid = true;
   if (!STRIDED) {
@@ -696,25 +698,45 @@ axis_pass_kernel(const PassArgs a) {
     valid = (!G && !SL) || line < (long long)a.n[0] * n1;
     j0 = (int)(line / n1);
     j1 = (int)(line % n1);
-    base = line * N;
-    S = 1;
+    bin = bout = line * N;
+    Sin = Sout = 1;
   } else {
-    const int ct = n2 / W;
     // Workgroups are dealt to the 8 XCDs round-robin; with xcd_remap each XCD
     // takes a contiguous run of tiles instead (same tiles, other order).
     int tile = blockIdx.x;
     if (a.xcd_remap && (gridDim.x & 7) == 0)
       tile = (blockIdx.x & 7) * (gridDim.x >> 3) + (blockIdx.x >> 3);
-    const int outer = tile / ct;
-    j2 = (tile % ct) * W + c;
-    if (a.axis == 1) {
-      j0 = outer;
-      base = (long long)outer * n1 * n2 + j2;
-      S = n2;
+    if (!SL && a.trans) {
+      // Rotating pass: the W lines of the tile sit at consecutive positions
+      // jb of axis b = axis + 1 (mod 3) and at position jc of the third axis;
+      // each line is contiguous in the input [b][c][a], and the output
+      // [c][a][b] puts the tile's W sites of each position p side by side.
+      const int ax = a.axis, bx = ax == 2 ? 0 : ax + 1, cxs = 3 - ax - bx;
+      const int nb = a.n[bx], nc = a.n[cxs];
+      const int ct = nb / W;
+      const int jc = tile / ct, jb = (tile % ct) * W + c;
+      bin = ((long long)jb * nc + jc) * N;
+      Sin = 1;
+      bout = (long long)jc * N * nb + jb;
+      Sout = nb;
+      j0 = bx == 0 ? jb : cxs == 0 ? jc : 0;
+      j1 = bx == 1 ? jb : cxs == 1 ? jc : 0;
+      j2 = bx == 2 ? jb : cxs == 2 ? jc : 0;
     } else {
-      j1 = outer;
-      base = (long long)outer * n2 + j2;
-      S = (long long)n1 * n2;
+      const int ct = n2 / W;
+      const int outer = tile / ct;
+      j2 = (tile % ct) * W + c;
+      if (a.axis == 1) {
+        j0 = outer;
+        bin = (long long)outer * n1 * n2 + j2;
+        Sin = n2;
+      } else {
+        j1 = outer;
+        bin = (long long)outer * n2 + j2;
+        Sin = (long long)n1 * n2;
+      }
+      bout = bin;
+      Sout = Sin;
     }
   }
   const int axis = STRIDED ? a.axis : 2;
@@ -736,8 +758,8 @@ axis_pass_kernel(const PassArgs a) {
 #pragma unroll
       for (int d = 0; d < R0; ++d) {
         const int p = PL::pos(0, t + TPL * b, d);
-        if constexpr (SLOAD) v[b * R0 + d] = cvt<T>(load_stream(&src[base + p * S]));
-        else v[b * R0 + d] = valid ? cvt<T>(src[base + p * S]) : cx<T>{0, 0};
+        if constexpr (SLOAD) v[b * R0 + d] = cvt<T>(load_stream(&src[bin + p * Sin]));
+        else v[b * R0 + d] = valid ? cvt<T>(src[bin + p * Sin]) : cx<T>{0, 0};
       }
     if (has_scale || pre != PH_NONE || (red & RED_REAL)) {
       const double sc = has_scale ? *pscale : 1.0;
@@ -777,7 +799,7 @@ axis_pass_kernel(const PassArgs a) {
 #pragma unroll
       for (int d = 0; d < RL; ++d) {
         const int p = PL::pos(PL::M - 1, t + TPL * b, d);
-        v[b * RL + d] = valid ? cvt<T>(src[base + PL::freq(p) * S]) : cx<T>{0, 0};
+        v[b * RL + d] = valid ? cvt<T>(src[bin + PL::freq(p) * Sin]) : cx<T>{0, 0};
       }
   }
 
@@ -792,7 +814,7 @@ axis_pass_kernel(const PassArgs a) {
         if (red & RED_KIN) acc[kSlotKin] += a.kw[f] * ((double)u.x * u.x + (double)u.y * u.y);
         if (mid == MID_TABLE) u = table_mul(u, mtab[f]);
         v[b * RL + d] = u;
-        if (!inverse && store && valid) dst[base + f * S] = cvt<SX>(u);
+        if (!inverse && store && valid) dst[bout + f * Sout] = cvt<SX>(u);
       }
   }
 
@@ -807,7 +829,7 @@ axis_pass_kernel(const PassArgs a) {
           cx<T> u = v[b * R0 + d];
           if (post == PH_DERIV) {
             // combine the derivative with the state at this site (re-read)
-            const cx<T> q = valid ? cvt<T>(src[base + p * S]) : cx<T>{0, 0};
+            const cx<T> q = valid ? cvt<T>(src[bin + p * Sin]) : cx<T>{0, 0};
             const double qr = q.x, qi = q.y, dr = u.x, di = u.y;
             const double mag = sqrt(qr * qr + qi * qi);
             const double zr = qr * dr + qi * di, zi = qr * di - qi * dr;  // conj(q) d
@@ -836,7 +858,7 @@ axis_pass_kernel(const PassArgs a) {
 #pragma unroll
           for (int d = 0; d < RL; ++d) {
             const int f = PL::freq(PL::pos(PL::M - 1, t + TPL * b, d));
-            dst[base + f * S] = cvt<SX>(v[b * RL + d]);
+            dst[bout + f * Sout] = cvt<SX>(v[b * RL + d]);
           }
       }
     } else if (store && valid) {
@@ -845,8 +867,8 @@ axis_pass_kernel(const PassArgs a) {
 #pragma unroll
         for (int d = 0; d < R0; ++d) {
           const int p = PL::pos(0, t + TPL * b, d);
-          if constexpr (SSTORE) store_stream(&dst[base + p * S], cvt<SX>(v[b * R0 + d]));
-          else dst[base + p * S] = cvt<SX>(v[b * R0 + d]);
+          if constexpr (SSTORE) store_stream(&dst[bout + p * Sout], cvt<SX>(v[b * R0 + d]));
+          else dst[bout + p * Sout] = cvt<SX>(v[b * R0 + d]);
         }
     }
   }

@@ -90,11 +90,12 @@ bool heavy_mode(int mode) {
 }  // namespace
 }  // namespace pass
 
-PassShape pass_shape(int precision, const int n[3], int axis, int wreq, int plan, bool narrow) {
+PassShape pass_shape(int precision, const int n[3], int axis, int wreq, int plan, bool narrow,
+                     bool trans) {
   using namespace pass;
   PassShape sh{};
   sh.N = n[axis];
-  sh.strided = axis != 2;
+  sh.strided = trans || axis != 2;
   const int tpl = tpl_of(sh.N, plan);
   if (tpl == 0) return sh;
   if (!sh.strided) {
@@ -107,6 +108,15 @@ PassShape pass_shape(int precision, const int n[3], int axis, int wreq, int plan
     int ws = fit_w(sh.N, math_f32(precision) ? 8 : 16, want, tpl);
     if (narrow && ws == 16 && tpl * 16 == 1024 && (!math_f32(precision) || sh.N / tpl == 16))
       ws = 8;
+    if (trans) {
+      // W lines at consecutive positions of the next axis, one tile per
+      // (third-axis position, run of W)
+      const int nb = n[axis == 2 ? 0 : axis + 1], nc = n[3 - axis - (axis == 2 ? 0 : axis + 1)];
+      sh.W = nb >= ws ? ws : 8;
+      sh.threads = tpl * sh.W;
+      sh.blocks = (long long)nc * (nb / sh.W);
+      return sh;
+    }
     sh.W = n[2] >= ws ? ws : 8;
     sh.threads = tpl * sh.W;
     const long long outer = axis == 1 ? n[0] : n[1];
@@ -116,17 +126,28 @@ PassShape pass_shape(int precision, const int n[3], int axis, int wreq, int plan
 }
 
 PassShape launch_shape(int precision, const PassArgs &a) {
-  const PassShape sh = pass_shape(precision, a.n, a.axis, a.wreq, a.plan);
+  const bool trans = a.trans && !a.slots;
+  const PassShape sh = pass_shape(precision, a.n, a.axis, a.wreq, a.plan, false, trans);
   // (narrowing changes strided tiles only, and the mode depends on the shape
   // only through the contiguous full-tile test, so the mode is unchanged)
   return pass::heavy_mode(pass::pick_mode(a, sh))
-             ? pass_shape(precision, a.n, a.axis, a.wreq, a.plan, true)
+             ? pass_shape(precision, a.n, a.axis, a.wreq, a.plan, true, trans)
              : sh;
 }
 
 hipError_t launch_axis_pass(int precision, const PassArgs &a, hipStream_t s) {
   const PassShape sh = launch_shape(precision, a);
-  if (sh.threads == 0 || (sh.strided && a.n[2] < sh.W)) return hipErrorInvalidValue;
+  if (sh.threads == 0) return hipErrorInvalidValue;
+  if (a.trans && !a.slots) {
+    // a rotating pass reads whole lines and writes rows elsewhere: 3D grids,
+    // distinct buffers, full tiles
+    const int bx = a.axis == 2 ? 0 : a.axis + 1;
+    if (a.n[0] < 2 || a.n[1] < 2 || a.n[2] < 2 || a.src == a.dst || a.n[bx] < sh.W ||
+        a.n[bx] % sh.W != 0)
+      return hipErrorInvalidValue;
+  } else if (sh.strided && a.n[2] < sh.W) {
+    return hipErrorInvalidValue;
+  }
   const int mode = pass::pick_mode(a, sh);
   if (precision == 1) return pass::launch_f32(a, sh, mode, s);
   if (precision == 2) return pass::launch_s32(a, sh, mode, s);

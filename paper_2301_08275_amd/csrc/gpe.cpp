@@ -505,9 +505,11 @@ gpe_status compute_spectra(gpe_ctx *c, gpe_spectra *spec) {
       if (st != GPE_OK) return st;
     }
   }
-  const int blocks = gpe::shell_blocks(c->sites);
+  const int blocks0 = gpe::shell_blocks(c->prec, 0, c->sites, nb);
+  const int blocks1 = gpe::shell_blocks(c->prec, 1, c->sites, nb);
   if (!c->hist_partial) {
-    gpe_status st = dalloc(c, (void **)&c->hist_partial, (size_t)blocks * 4 * nb * sizeof(double),
+    gpe_status st = dalloc(c, (void **)&c->hist_partial,
+                           (size_t)gpe::kShellMaxBlocks * 4 * nb * sizeof(double),
                            "histogram allocation");
     if (st != GPE_OK) return st;
     st = dalloc(c, (void **)&c->hist, 8 * (size_t)nb * sizeof(double), "histogram allocation");
@@ -528,8 +530,8 @@ gpe_status compute_spectra(gpe_ctx *c, gpe_spectra *spec) {
   if (st != GPE_OK) return st;
   sa.kind = 0;
   sa.f[0] = c->work[0];
-  HIPCHK(c, gpe::launch_shells(c->prec, sa, c->stream), "shell launch");
-  HIPCHK(c, gpe::launch_sum_columns(c->hist_partial, blocks, 4 * nb, c->hist, c->stream),
+  HIPCHK(c, gpe::launch_shells(c->prec, sa, blocks0, c->stream), "shell launch");
+  HIPCHK(c, gpe::launch_sum_columns(c->hist_partial, blocks0, 4 * nb, c->hist, c->stream),
          "histogram sum");
   // Z_j = u_j + i w_j from the spectral derivative along each axis, transformed
   void *deriv_tab[3] = {nullptr, nullptr, nullptr};
@@ -552,8 +554,8 @@ gpe_status compute_spectra(gpe_ctx *c, gpe_spectra *spec) {
   sa.kind = 1;
   for (int j = 0; j < 3; ++j) sa.f[j] = nullptr;
   for (int j = 0; j < c->dim; ++j) sa.f[view_axis(c, j)] = c->work[j];
-  HIPCHK(c, gpe::launch_shells(c->prec, sa, c->stream), "shell launch");
-  HIPCHK(c, gpe::launch_sum_columns(c->hist_partial, blocks, 4 * nb, c->hist + 4 * nb, c->stream),
+  HIPCHK(c, gpe::launch_shells(c->prec, sa, blocks1, c->stream), "shell launch");
+  HIPCHK(c, gpe::launch_sum_columns(c->hist_partial, blocks1, 4 * nb, c->hist + 4 * nb, c->stream),
          "histogram sum");
   std::vector<double> h(8 * (size_t)nb);
   HIPCHK(c, hipMemcpyAsync(h.data(), c->hist, h.size() * sizeof(double), hipMemcpyDeviceToHost,
@@ -589,6 +591,10 @@ uint64_t context_bytes(const gpe_desc &d, bool with_state) {
   for (int ax = off; ax < 3; ++ax) {
     const gpe::PassShape sh = gpe::pass_shape(d.precision, n3, ax, wdef[ax], plan[ax], true);
     if (sh.blocks > maxb) maxb = sh.blocks;
+    if (d.dim == 3) {
+      const gpe::PassShape st = gpe::pass_shape(d.precision, n3, ax, 8, plan[ax], true, true);
+      if (st.blocks > maxb) maxb = st.blocks;
+    }
     tables += (uint64_t)n3[ax] * (16 + sizeof(double));
   }
   return (with_state ? (uint64_t)sites * es : 0) +
@@ -625,7 +631,8 @@ gpe_status create_context(const gpe_desc *desc, const double *V_host, const gpe_
   c->dim = desc->dim;
   c->prec = desc->precision;
   c->esize = gpe::state_f32(c->prec) ? 8 : 16;
-  effective_tuning(*desc, c->wreq, c->xcd_remap, c->pass_order, c->plan, c->streaming);
+  effective_tuning(*desc, c->wreq, c->xcd_remap, c->pass_order, c->plan, c->streaming,
+                   &c->rot);
   const int off = 3 - c->dim;
   c->sites = 1;
   c->dV = 1;
@@ -675,9 +682,14 @@ gpe_status create_context(const gpe_desc *desc, const double *V_host, const gpe_
   if (const char *w = std::getenv("GPE_TUNE_XCD")) c->xcd_remap[0] = c->xcd_remap[1] = std::atoi(w);
   long long maxb = 1;
   for (int ax = 3 - c->dim; ax < 3; ++ax) {
-    // (narrow shapes have the most blocks: room for every pass's partials)
+    // (narrow shapes have the most blocks: room for every pass's partials,
+    // in either form of the step passes)
     const gpe::PassShape sh = gpe::pass_shape(c->prec, c->n3, ax, c->wreq[ax], c->plan[ax], true);
     if (sh.blocks > maxb) maxb = sh.blocks;
+    if (c->dim == 3) {
+      const gpe::PassShape st = gpe::pass_shape(c->prec, c->n3, ax, 8, c->plan[ax], true, true);
+      if (st.blocks > maxb) maxb = st.blocks;
+    }
   }
   c->partial_region = maxb * gpe::kRedSlots;
   if ((st = dalloc(c, (void **)&c->partial, 3 * c->partial_region * sizeof(double),
@@ -825,11 +837,49 @@ constexpr size_t kMaxStepGraphs = 8;   // graphs kept per context
 // One real-time step: phase N(tau_pre) before the first pass, the kinetic
 // factor K in every pass, and a closing phase N(dt/2) after the last pass of
 // the last step of a call.
+// (never on graph-sized grids: a graph would replay the rotating passes from
+// the arrays that were current when it was captured)
+bool use_trans(const gpe_ctx *c) {
+  return c->rot.on && c->dim == 3 && c->sites > kGraphSites;
+}
+
+// The rotating passes visit the axes in this order: the first reads the grid
+// as stored ([0][1][2]) and each writes the layout the next one reads, the
+// last one the stored layout again.
+constexpr int kTransOrder[3] = {2, 0, 1};
+
+gpe_status ensure_alt(gpe_ctx *c) {
+  if (c->psi_alt) return GPE_OK;
+  return dalloc(c, &c->psi_alt, c->sites * c->esize, "second state allocation");
+}
+
+// Point a step pass at the current state; a rotating pass writes the other
+// array, which then becomes the current state.
+void route(gpe_ctx *c, gpe::PassArgs &a, bool trans) {
+  a.src = c->psi;
+  a.dst = trans ? c->psi_alt : c->psi;
+  a.trans = trans ? 1 : 0;
+  if (trans) {
+    a.wreq = c->rot.wreq[a.axis];
+    a.xcd_remap = c->rot.xcd[a.axis];
+    a.stream = c->rot.stream[a.axis];
+  }
+}
+
+void after_pass(gpe_ctx *c, bool trans) {
+  if (trans) std::swap(c->psi, c->psi_alt);
+}
+
 gpe_status real_step(gpe_ctx *c, void *const K[3], double tau_pre, double tau_post,
                      const VAt *pre, const VAt *post) {
   const int na = n_axes(c);
+  const bool trans = use_trans(c);
+  if (trans) {
+    gpe_status ast = ensure_alt(c);
+    if (ast != GPE_OK) return ast;
+  }
   for (int i = 0; i < na; ++i) {
-    const int ax = order_axis(c, i);
+    const int ax = trans ? kTransOrder[i] : order_axis(c, i);
     // The closing phase's potential goes to the second table region when the
     // same pass also opens the step (one axis), else over the opening one
     // (stream order: the first pass has read it by then).
@@ -851,8 +901,10 @@ gpe_status real_step(gpe_ctx *c, void *const K[3], double tau_pre, double tau_po
       a.post = gpe::PH_REAL;
       a.tau_post = tau_post;
     }
+    route(c, a, trans);
     gpe_status st = launch_pass(c, a);
     if (st != GPE_OK) return st;
+    after_pass(c, trans);
   }
   return GPE_OK;
 }
@@ -866,8 +918,13 @@ gpe_status real_step(gpe_ctx *c, void *const K[3], double tau_pre, double tau_po
 // 512^3 FP64 when this was chosen, 0.301 instead of 0.327 at 256^3.
 gpe_status imag_step(gpe_ctx *c, void *const K[3], double dt) {
   const int na = n_axes(c);
+  const bool trans = use_trans(c);
+  if (trans) {
+    gpe_status ast = ensure_alt(c);
+    if (ast != GPE_OK) return ast;
+  }
   for (int i = 0; i < na; ++i) {
-    const int ax = order_axis(c, na - 1 - i);
+    const int ax = trans ? kTransOrder[i] : order_axis(c, na - 1 - i);
     gpe::PassArgs a = base_args(c, ax);
     a.mid = gpe::MID_TABLE;
     a.mtab = K[ax];
@@ -885,8 +942,10 @@ gpe_status imag_step(gpe_ctx *c, void *const K[3], double dt) {
       a.red = gpe::RED_NORM_OUT;
       a.partial = c->partial;
     }
+    route(c, a, trans);
     gpe_status st = launch_pass(c, a);
     if (st != GPE_OK) return st;
+    after_pass(c, trans);
     if (i == na - 1) {
       const gpe::PassShape sh = gpe::launch_shape(c->prec, a);
       HIPCHK(c, gpe::launch_finalize(c->partial, sh.blocks, c->sums + 3 * gpe::kRedSlots,
@@ -1185,6 +1244,7 @@ void gpe_destroy(gpe_ctx *c) {
     if (c->kw[j]) (void)hipFree(c->kw[j]);
   }
   if (c->psi) (void)hipFree(c->psi);
+  if (c->psi_alt) (void)hipFree(c->psi_alt);
   for (int j = 0; j < 3; ++j)
     if (c->work[j]) (void)hipFree(c->work[j]);
   if (c->hist_partial) (void)hipFree(c->hist_partial);

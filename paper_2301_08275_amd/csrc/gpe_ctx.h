@@ -19,6 +19,17 @@ constexpr double kPi = 3.14159265358979323846264338327950288;
 // Kinds of per-frequency tables along one axis.
 enum TableKind { TB_KREAL = 0, TB_KIMAG = 1, TB_DERIV = 2, TB_INVN = 3 };
 
+// Launch shapes of the rotating step passes (3D; see gpe_tuning.transpose):
+// on = 1 runs the step passes in their rotating form, with these widths, tile
+// orders and streaming flags per view axis; the context's in-place shapes then
+// serve the read-only passes (observables, transforms, spectra).
+struct RotShape {
+  int on = 0;
+  int wreq[3] = {8, 8, 8};
+  int xcd[3] = {1, 1, 1};
+  int stream[3] = {0, 0, 0};
+};
+
 struct TimedKind {
   std::string name;
   double total_ms = 0;
@@ -43,6 +54,9 @@ struct gpe_ctx {
   int device = 0;
 
   void *psi = nullptr;
+  // Second state array of the rotating passes (allocated on first use); the
+  // two swap roles after every pass, and psi always names the current state.
+  void *psi_alt = nullptr;
   void *work[3] = {nullptr, nullptr, nullptr};  // spectra work fields (allocated on demand)
   double *hist_partial = nullptr;  // shell histograms per workgroup
   double *hist = nullptr;          // 8 x nbins finalized shell sums
@@ -92,6 +106,9 @@ struct gpe_ctx {
   // Streaming (non-temporal) loads (bit 0) and stores (bit 1) in the step
   // passes, per view axis.
   int streaming[3] = {0, 0, 0};
+  // 3D: the step passes in their rotating form (axes in the order 2, 0, 1;
+  // pass_order then applies to the read-only passes only).
+  gpe_host::RotShape rot;
 };
 
 
@@ -130,7 +147,10 @@ gpe_status validate_desc(const gpe_desc *d, std::string &msg);
 // Launch shapes a new context of this class uses (view axes): the tuning
 // table's entry, else the defaults.
 void effective_tuning(const gpe_desc &d, int wreq[3], int xcd[3], int order[3], int plan[3],
-                      int stream[3]);
+                      int stream[3], RotShape *rot = nullptr);
+// The step passes of this context rotate the grid (3D, tuned so, and not
+// replayed from graphs).
+bool use_trans(const gpe_ctx *c);
 // Device bytes of a context (with_state: including the state array).
 uint64_t context_bytes(const gpe_desc &d, bool with_state = true);
 // gpe_create, optionally without the state array (a holder of the tables of

@@ -73,6 +73,10 @@ struct PassArgs {
   int wreq;           // columns per workgroup requested for a strided axis (8 or 16)
   int plan;           // radix plan of the axis (0 default, 1 alternative)
   int xcd_remap;      // strided axes: give each XCD a contiguous run of tiles
+  int trans;          // 1: rotating pass (3D; src and dst distinct): the input holds
+                      // the grid as [b][c][a] (a = axis, b = (a+1)%3, c = (a+2)%3,
+                      // last index fastest), the output as [c][a][b]; a tile is W
+                      // whole lines at consecutive b, written as rows of W sites
   const double *V;    // FP64 potential per site, or null
   double hv[3];       // analytic V = sum_j hv[j] x_j^2 when V is null
   const double *vtab; // V_TABLES: V = t[j0] + t[n0 + j1] + t[n0 + n1 + j2] (view axes)
@@ -99,7 +103,7 @@ struct PassArgs {
 
 struct PassShape {
   int N;        // axis length
-  bool strided; // axis is not the contiguous one
+  bool strided; // tiles of W columns (the axis is not the contiguous one, or the pass rotates)
   int W;        // lines (contiguous) or columns (strided) per workgroup
   int threads;  // workgroup size
   long long blocks;
@@ -115,8 +119,10 @@ struct PassShape {
 // 1024 threads (128 VGPRs each) with FP64 arithmetic or 16 points per thread,
 // those kernels spill to scratch, so they take 8-column tiles there.  Block
 // counts with narrow = true are never smaller than without.
+// trans: the rotating form of the pass (PassArgs::trans; 3D only): tiles of
+// W whole lines of the axis at consecutive positions of the next axis.
 PassShape pass_shape(int precision, const int n[3], int axis, int wreq, int plan = 0,
-                     bool narrow = false);
+                     bool narrow = false, bool trans = false);
 // The shape launch_axis_pass uses for these arguments; the partial sums of a
 // reducing pass have one row per block of this shape.
 PassShape launch_shape(int precision, const PassArgs &a);
@@ -156,8 +162,11 @@ struct ShellArgs {
   double w;          // dV / N_tot
   double *partial;   // [gridDim][4][nbins]
 };
-int shell_blocks(long long sites);
-hipError_t launch_shells(int precision, const ShellArgs &a, hipStream_t s);
+// Workgroups of a shell launch of this kind on the current device (at most
+// kShellMaxBlocks; the partial histograms need that many rows at most).
+constexpr int kShellMaxBlocks = 1024;
+int shell_blocks(int precision, int kind, long long sites, int nbins);
+hipError_t launch_shells(int precision, const ShellArgs &a, int blocks, hipStream_t s);
 // out[i] = sum_b partial[b * len + i] for i < len, b < count, fixed order.
 hipError_t launch_sum_columns(const double *partial, long long count, int len, double *out,
                               hipStream_t s);

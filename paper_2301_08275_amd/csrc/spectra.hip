@@ -17,7 +17,6 @@ namespace gpe {
 namespace {
 
 constexpr int kShellThreads = 256;
-constexpr int kShellMaxBlocks = 1024;
 constexpr int kShellU0 = 4, kShellU1 = 2;  // sites per thread per iteration (kind 0, 1)
 
 template <typename T>
@@ -141,26 +140,40 @@ __global__ void __launch_bounds__(kShellThreads) shell_kernel(const ShellArgs a)
     ShellSite q[U];
     cxs<T> zp[U][NF], zm[U][NF];
 #pragma unroll
-    for (int u = 0; u < U; ++u) {
+    for (int u = 0; u < U; ++u)
       q[u] = shell_site<KIND>(a, s0 + (long long)u * blockDim.x + threadIdx.x, sites, l1, l2);
+    // Every lane loads (a lane with nothing to add reads element 0) and the
+    // values are zeroed afterwards: loads under per-lane branches end up in
+    // blocks of their own, each waiting for its data before the next load
+    // issues.
 #pragma unroll
-      for (int j = 0; j < NF; ++j) {
-        zp[u][j] = cxs<T>{0, 0};
-        zm[u][j] = cxs<T>{0, 0};
-        if (q[u].on && fs[j]) {
-          zp[u][j] = fs[j][q[u].s];
-          if (KIND != 0) zm[u][j] = fs[j][q[u].ms];
+    for (int j = 0; j < NF; ++j) {
+      if (fs[j]) {  // (uniform: a missing axis has no field)
+#pragma unroll
+        for (int u = 0; u < U; ++u) {
+          zp[u][j] = fs[j][q[u].on ? q[u].s : 0];
+          zm[u][j] = KIND != 0 ? fs[j][q[u].on ? q[u].ms : 0] : cxs<T>{0, 0};
         }
+      } else {
+#pragma unroll
+        for (int u = 0; u < U; ++u) zp[u][j] = zm[u][j] = cxs<T>{0, 0};
       }
     }
+#pragma unroll
+    for (int u = 0; u < U; ++u)
+#pragma unroll
+      for (int j = 0; j < NF; ++j)
+        if (!q[u].on) zp[u][j] = zm[u][j] = cxs<T>{0, 0};
+    double en[U];  // kind 0: the weighted |Z|^2 of each site, formed once all loads are issued
+#pragma unroll
+    for (int u = 0; u < U; ++u)
+      en[u] = a.w * ((double)zp[u][0].x * zp[u][0].x + (double)zp[u][0].y * zp[u][0].y);
 #pragma unroll
     for (int u = 0; u < U; ++u) {
       const int key_next = __shfl_down(q[u].key, 1, 64);
       const bool last = q[u].on && (lane == 63 || key_next != q[u].key);
       if constexpr (KIND == 0) {
-        const double e = run_sum(
-            a.w * ((double)zp[u][0].x * zp[u][0].x + (double)zp[u][0].y * zp[u][0].y), q[u].key,
-            lane);
+        const double e = run_sum(en[u], q[u].key, lane);
         add_run(h, q[u].bin, e, last, rows_apart, lane);
       } else {
         double csum = 0, isum = 0, qsum = 0;
@@ -238,38 +251,64 @@ sum_columns_kernel(const double *__restrict__ partial, long long count, int len,
   }
 }
 
-}  // namespace
-
-int shell_blocks(long long sites) {
-  long long b = (sites + kShellThreads - 1) / kShellThreads;
-  return (int)(b < kShellMaxBlocks ? (b < 1 ? 1 : b) : kShellMaxBlocks);
+// Workgroup shape of a shell launch: as many wavefronts (at most four) as
+// have room for their histograms in 64 KiB of LDS.
+struct ShellShape {
+  int waves;
+  size_t lds;
+};
+ShellShape shell_shape(int kind, int nbins) {
+  const size_t per_wave = (kind == 0 ? 1 : 3) * (size_t)nbins * sizeof(double);
+  int waves = (int)((64 * 1024) / per_wave);
+  if (waves > kShellThreads / 64) waves = kShellThreads / 64;
+  return {waves, waves > 0 ? waves * per_wave : 0};
 }
 
-hipError_t launch_shells(int precision, const ShellArgs &a, hipStream_t s) {
-  const long long sites = (long long)a.n[0] * a.n[1] * a.n[2];
-  const int blocks = shell_blocks(sites);
-  // as many wavefronts (at most four) as have room for their histograms in
-  // 64 KiB of LDS
-  const size_t per_wave = (a.kind == 0 ? 1 : 3) * (size_t)a.nbins * sizeof(double);
-  const size_t max_lds = 64 * 1024;
-  int waves = (int)(max_lds / per_wave);
-  if (waves < 1) return hipErrorInvalidValue;
-  if (waves > kShellThreads / 64) waves = kShellThreads / 64;
-  const size_t lds = waves * per_wave;
-  const dim3 threads(64 * waves);
+const void *shell_fn(int precision, int kind) {
   // the packed fields are stored like the state
+  if (state_f32(precision))
+    return kind == 0 ? (const void *)shell_kernel<float, 0, kShellU0>
+                     : (const void *)shell_kernel<float, 1, kShellU1>;
+  return kind == 0 ? (const void *)shell_kernel<double, 0, kShellU0>
+                   : (const void *)shell_kernel<double, 1, kShellU1>;
+}
+
+}  // namespace
+
+// Every workgroup loops over an equal share of the sites, so the launch is
+// one round of the workgroups the device holds at once (a second, partial
+// round would leave most CUs idle), capped by the sites and kShellMaxBlocks.
+// The count depends only on the device and the grid: the fixed-order sums
+// stay bitwise reproducible.
+int shell_blocks(int precision, int kind, long long sites, int nbins) {
+  const ShellShape sh = shell_shape(kind, nbins);
+  if (sh.waves < 1) return 1;
+  long long b = (sites + 64LL * sh.waves - 1) / (64LL * sh.waves);
+  if (b > kShellMaxBlocks) b = kShellMaxBlocks;
+  int dev = 0, cus = 0, per_cu = 0;
+  if (hipGetDevice(&dev) == hipSuccess &&
+      hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev) == hipSuccess &&
+      hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, shell_fn(precision, kind),
+                                                   64 * sh.waves, sh.lds) == hipSuccess &&
+      cus > 0 && per_cu > 0 && (long long)cus * per_cu < b)
+    b = (long long)cus * per_cu;
+  return (int)(b < 1 ? 1 : b);
+}
+
+hipError_t launch_shells(int precision, const ShellArgs &a, int blocks, hipStream_t s) {
+  const ShellShape sh = shell_shape(a.kind, a.nbins);
+  if (sh.waves < 1 || blocks < 1 || blocks > kShellMaxBlocks) return hipErrorInvalidValue;
+  const dim3 threads(64 * sh.waves);
   if (state_f32(precision)) {
     if (a.kind == 0)
-      hipLaunchKernelGGL((shell_kernel<float, 0, kShellU0>), dim3(blocks), threads, lds,
-                         s, a);
+      hipLaunchKernelGGL((shell_kernel<float, 0, kShellU0>), dim3(blocks), threads, sh.lds, s, a);
     else
-      hipLaunchKernelGGL((shell_kernel<float, 1, kShellU1>), dim3(blocks), threads, lds,
-                         s, a);
+      hipLaunchKernelGGL((shell_kernel<float, 1, kShellU1>), dim3(blocks), threads, sh.lds, s, a);
   } else {
     if (a.kind == 0)
-      hipLaunchKernelGGL((shell_kernel<double, 0, kShellU0>), dim3(blocks), threads, lds, s, a);
+      hipLaunchKernelGGL((shell_kernel<double, 0, kShellU0>), dim3(blocks), threads, sh.lds, s, a);
     else
-      hipLaunchKernelGGL((shell_kernel<double, 1, kShellU1>), dim3(blocks), threads, lds, s, a);
+      hipLaunchKernelGGL((shell_kernel<double, 1, kShellU1>), dim3(blocks), threads, sh.lds, s, a);
   }
   return hipGetLastError();
 }

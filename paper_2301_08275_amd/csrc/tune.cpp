@@ -14,6 +14,7 @@
 #include <cctype>
 #include <cmath>
 #include <cstdio>
+#include <cstdlib>
 #include <cstring>
 #include <map>
 #include <mutex>
@@ -75,7 +76,12 @@ bool valid_tuning(int dim, const int *n, const gpe_tuning &t, std::string &msg) 
       msg = "stream must be 0..3";
       return false;
     }
-  for (int j = 0; j < dim - 1; ++j) {
+  if (t.transpose != 0 && (t.transpose != 1 || dim != 3)) {
+    msg = "transpose must be 0, or 1 on a 3D grid";
+    return false;
+  }
+  const int tiled = t.transpose ? dim : dim - 1;  // axes with tile widths
+  for (int j = 0; j < tiled; ++j) {
     if (t.width[j] != 8 && t.width[j] != 16) {
       msg = "width must be 8 or 16 on the strided axes";
       return false;
@@ -98,12 +104,25 @@ bool valid_tuning(int dim, const int *n, const gpe_tuning &t, std::string &msg) 
 }
 
 // ABI form (user axes) to the view-axis arrays of a context (3D view: 2D
-// problems use view axes 1 and 2).
+// problems use view axes 1 and 2).  An entry of rotating step passes leaves
+// the in-place shapes at their defaults (they then serve the read-only passes)
+// and fills *rot instead.
 void to_view(int dim, const gpe_tuning &t, int wreq[3], int xcd[3], int order[3],
-             int plan[3], int stream[3]) {
+             int plan[3], int stream[3], RotShape *rot) {
   const int off = 3 - dim;
+  const bool tr = dim == 3 && t.transpose == 1;
+  if (rot) *rot = RotShape{};
   for (int j = 0; j < dim; ++j) {
     plan[j + off] = t.plan[j];
+    if (tr) {
+      if (rot) {
+        rot->on = 1;
+        rot->wreq[j] = t.width[j];
+        rot->xcd[j] = t.xcd_remap[j];
+        rot->stream[j] = t.stream[j];
+      }
+      continue;
+    }
     stream[j + off] = t.stream[j];
     if (j < dim - 1) {
       wreq[j + off] = t.width[j];
@@ -116,15 +135,19 @@ void to_view(int dim, const gpe_tuning &t, int wreq[3], int xcd[3], int order[3]
   for (int ax = 0; ax < off; ++ax) order[k++] = ax;
 }
 
+// The inverse of to_view: the in-place shapes, or the rotating ones when
+// rot is on.
 void from_view(int dim, const int wreq[3], const int xcd[3], const int order[3],
-               const int plan[3], const int stream[3], gpe_tuning *t) {
+               const int plan[3], const int stream[3], const RotShape *rot, gpe_tuning *t) {
   const int off = 3 - dim;
   std::memset(t, 0, sizeof(*t));
+  const bool tr = dim == 3 && rot && rot->on;
+  t->transpose = tr ? 1 : 0;
   for (int j = 0; j < dim; ++j) {
     t->plan[j] = plan[j + off];
-    t->stream[j] = stream[j + off];
-    t->width[j] = j < dim - 1 ? wreq[j + off] : 0;
-    t->xcd_remap[j] = j < dim - 1 ? xcd[j + off] : 0;
+    t->stream[j] = tr ? rot->stream[j] : stream[j + off];
+    t->width[j] = tr ? rot->wreq[j] : j < dim - 1 ? wreq[j + off] : 0;
+    t->xcd_remap[j] = tr ? rot->xcd[j] : j < dim - 1 ? xcd[j + off] : 0;
   }
   int k = 0;
   for (int i = 0; i < 3 && k < dim; ++i)
@@ -273,11 +296,12 @@ double time_steps(gpe_ctx *c, int steps, hipEvent_t e0, hipEvent_t e1) {
 }  // namespace
 
 void effective_tuning(const gpe_desc &d, int wreq[3], int xcd[3], int order[3], int plan[3],
-                      int stream[3]) {
+                      int stream[3], RotShape *rot) {
   defaults(d, wreq, xcd, order, plan, stream);
+  if (rot) *rot = RotShape{};
   std::lock_guard<std::mutex> lk(g_mu);
   auto it = g_table.find(key_of(d));
-  if (it != g_table.end()) to_view(d.dim, it->second, wreq, xcd, order, plan, stream);
+  if (it != g_table.end()) to_view(d.dim, it->second, wreq, xcd, order, plan, stream, rot);
 }
 
 }  // namespace gpe_host
@@ -292,7 +316,7 @@ gpe_status gpe_tuning_set(const gpe_desc *desc, const gpe_tuning *t) {
   if (st != GPE_OK) return st;
   if (!t || !valid_tuning(desc->dim, desc->n, *t, msg)) return GPE_EINVAL;
   gpe_tuning v = *t;
-  for (int j = desc->dim - 1; j < 3; ++j) v.width[j] = v.xcd_remap[j] = 0;
+  for (int j = v.transpose ? desc->dim : desc->dim - 1; j < 3; ++j) v.width[j] = v.xcd_remap[j] = 0;
   for (int i = desc->dim; i < 3; ++i) v.pass_order[i] = v.plan[i] = v.stream[i] = 0;
   std::lock_guard<std::mutex> lk(g_mu);
   g_table[key_of(*desc)] = v;
@@ -315,7 +339,7 @@ gpe_status gpe_tuning_get(const gpe_desc *desc, gpe_tuning *out, int32_t *found)
   }
   int w[3], x[3], o[3], pl[3], sm[3];
   defaults(*desc, w, x, o, pl, sm);
-  from_view(desc->dim, w, x, o, pl, sm, out);
+  from_view(desc->dim, w, x, o, pl, sm, nullptr, out);
   out->ms_per_step = 0;
   if (found) *found = 0;
   return GPE_OK;
@@ -345,11 +369,11 @@ gpe_status gpe_tuning_save(const char *path) {
       std::snprintf(buf, sizeof(buf),
                     "%s\n    {\"dim\": %d, \"n\": %s, \"precision\": \"%s\", \"width\": %s, "
                     "\"xcd_remap\": %s, \"pass_order\": %s, \"plan\": %s, \"stream\": %s, "
-                    "\"ms_per_step\": %.6g}",
+                    "\"transpose\": %d, \"ms_per_step\": %.6g}",
                     first ? "" : ",", d, arr(k.n).c_str(),
                     k.prec == GPE_FP32 ? "fp32" : k.prec == GPE_FP32_STATE ? "fp32s" : "fp64",
                     arr(t.width).c_str(), arr(t.xcd_remap).c_str(), arr(t.pass_order).c_str(),
-                    arr(t.plan).c_str(), arr(t.stream).c_str(), t.ms_per_step);
+                    arr(t.plan).c_str(), arr(t.stream).c_str(), (int)t.transpose, t.ms_per_step);
       s += buf;
       first = false;
     }
@@ -410,6 +434,9 @@ gpe_status gpe_tuning_load(const char *path) {
     if (pl && !int_array(pl, d, t.plan)) return GPE_EINVAL;
     const JVal *sm = e.get("stream");  // optional likewise
     if (sm && !int_array(sm, d, t.stream)) return GPE_EINVAL;
+    const JVal *tp = e.get("transpose");  // optional likewise
+    if (tp && (tp->kind != JVal::NUM || (tp->num != 0 && tp->num != 1))) return GPE_EINVAL;
+    t.transpose = tp ? (int32_t)tp->num : 0;
     if (validate_desc(&desc, msg) != GPE_OK || !valid_tuning(d, desc.n, t, msg))
       return GPE_EINVAL;
     t.ms_per_step = ms && ms->kind == JVal::NUM ? ms->num : 0;
@@ -447,13 +474,35 @@ gpe_status gpe_autotune(const gpe_desc *desc, int32_t steps, gpe_tuning *out) {
   }
   int bs[3];  // streaming flags (the last coordinate tried)
   std::memcpy(bs, s0, sizeof(bs));
+  int bt = 0;  // rotating step passes (tried last, from their own start)
+  // GPE_TUNE_VERBOSE=1 prints every candidate and its time to stderr.
+  const char *verbose_env = std::getenv("GPE_TUNE_VERBOSE");
+  const bool verbose = verbose_env && *verbose_env == '1';
+  auto report = [&](double t) {
+    if (!verbose) return;
+    const int *w = bt ? c->rot.wreq : c->wreq, *x = bt ? c->rot.xcd : c->xcd_remap;
+    const int *sm = bt ? c->rot.stream : c->streaming;
+    std::fprintf(stderr,
+                 "tune %dx%dx%d p%d rot %d width %d %d %d xcd %d %d %d stream %d %d %d order %d %d %d "
+                 "plan %d %d %d: %.4f ms\n",
+                 c->n3[0], c->n3[1], c->n3[2], d.precision, bt, w[0], w[1], w[2], x[0], x[1], x[2],
+                 sm[0], sm[1], sm[2], c->pass_order[0], c->pass_order[1], c->pass_order[2],
+                 c->plan[0], c->plan[1], c->plan[2], t);
+  };
   auto apply = [&](const int w[3], const int x[3], const int o[3], const int p[3]) {
+    c->rot.on = bt;
     for (int j = 0; j < 3; ++j) {
-      c->wreq[j] = w[j];
-      c->xcd_remap[j] = x[j];
       c->pass_order[j] = o[j];
       c->plan[j] = p[j];
-      c->streaming[j] = bs[j];
+      if (bt) {
+        c->rot.wreq[j] = w[j];
+        c->rot.xcd[j] = x[j];
+        c->rot.stream[j] = bs[j];
+      } else {
+        c->wreq[j] = w[j];
+        c->xcd_remap[j] = x[j];
+        c->streaming[j] = bs[j];
+      }
     }
     drop_step_graphs(c);  // cached step graphs hold the previous shapes
   };
@@ -464,6 +513,7 @@ gpe_status gpe_autotune(const gpe_desc *desc, int32_t steps, gpe_tuning *out) {
   std::memcpy(bp, p0, sizeof(bp));
   apply(bw, bx, bo, bp);
   double best = time_steps(c, steps, e0, e1);
+  report(best);
   const int off = 3 - d.dim;
   // Per axis, jointly: radix plan x width x tile order x streaming policy
   // (width and tile order on the strided axes only; a narrower tile may only
@@ -473,10 +523,12 @@ gpe_status gpe_autotune(const gpe_desc *desc, int32_t steps, gpe_tuning *out) {
       for (int pl : {0, 1}) {
         if (!gpe::plan_available(c->n3[ax], pl)) continue;
         for (int w : {8, 16}) {
-          if (ax == 2 && w != bw[ax]) continue;
-          if (ax != 2 && gpe::pass_shape(d.precision, c->n3, ax, w, pl).W != w) continue;
+          // (a rotating pass has tiles on every axis, the in-place contiguous one none)
+          const bool tiled = ax != 2 || bt;
+          if (!tiled && w != bw[ax]) continue;
+          if (tiled && gpe::pass_shape(d.precision, c->n3, ax, w, pl, false, bt).W != w) continue;
           for (int x : {0, 1}) {
-            if (ax == 2 && x != bx[ax]) continue;
+            if (!tiled && x != bx[ax]) continue;
             for (int sm = 0; sm < 4; ++sm) {
               if (pl == bp[ax] && w == bw[ax] && x == bx[ax] && sm == bs[ax]) continue;
               int tw[3], tx[3], tp[3];
@@ -490,6 +542,7 @@ gpe_status gpe_autotune(const gpe_desc *desc, int32_t steps, gpe_tuning *out) {
               bs[ax] = sm;
               apply(tw, tx, bo, tp);
               const double t = time_steps(c, steps, e0, e1);
+              report(t);
               if (t > 0 && t < best * (1 - kMargin)) {
                 best = t;
                 std::memcpy(bw, tw, sizeof(bw));
@@ -504,8 +557,10 @@ gpe_status gpe_autotune(const gpe_desc *desc, int32_t steps, gpe_tuning *out) {
       }
     }
   };
-  // 1. per-axis shapes; 2. the axis order of the step (it decides which pass
-  // carries the phase); 3. per-axis shapes again for that order
+  // In-place passes: 1. per-axis shapes; 2. the axis order of the step (it
+  // decides which pass carries the phase); 3. per-axis shapes again for that
+  // order.  Then, on large 3D grids, the rotating passes (their order is
+  // fixed) from 8-column tiles, per-axis shapes twice; the faster form wins.
   axis_round();
   int perm[3] = {0, 1, 2};
   int axes[3], na = 0;
@@ -519,18 +574,52 @@ gpe_status gpe_autotune(const gpe_desc *desc, int32_t steps, gpe_tuning *out) {
     if (std::equal(to, to + 3, bo) || best <= 0) continue;
     apply(bw, bx, to, bp);
     const double t = time_steps(c, steps, e0, e1);
+    report(t);
     if (t > 0 && t < best * (1 - kMargin)) {
       best = t;
       std::memcpy(bo, to, sizeof(bo));
     }
   } while (std::next_permutation(perm, perm + na));
   axis_round();
+  c->rot.on = 1;
+  if (d.dim == 3 && use_trans(c) && best > 0) {
+    int kw[3], kx[3], kp[3], ks[3];
+    std::memcpy(kw, bw, sizeof(kw));
+    std::memcpy(kx, bx, sizeof(kx));
+    std::memcpy(kp, bp, sizeof(kp));
+    std::memcpy(ks, bs, sizeof(ks));
+    const double keep = best;
+    bt = 1;
+    for (int j = 0; j < 3; ++j) {
+      bw[j] = 8;
+      bx[j] = 1;
+      bs[j] = 0;
+    }
+    apply(bw, bx, bo, bp);
+    best = time_steps(c, steps, e0, e1);
+    report(best);
+    axis_round();
+    axis_round();
+    if (!(best > 0 && best < keep * (1 - kMargin))) {
+      bt = 0;
+      best = keep;
+      std::memcpy(bw, kw, sizeof(bw));
+      std::memcpy(bx, kx, sizeof(bx));
+      std::memcpy(bp, kp, sizeof(bp));
+      std::memcpy(bs, ks, sizeof(bs));
+    }
+  }
   (void)hipEventDestroy(e0);
   (void)hipEventDestroy(e1);
   gpe_destroy(c);
   if (!(best > 0)) return GPE_EDEVICE;
   gpe_tuning t{};
-  from_view(d.dim, bw, bx, bo, bp, bs, &t);
+  RotShape rs;
+  rs.on = bt;
+  std::memcpy(rs.wreq, bw, sizeof(bw));
+  std::memcpy(rs.xcd, bx, sizeof(bx));
+  std::memcpy(rs.stream, bs, sizeof(bs));
+  from_view(d.dim, bw, bx, bo, bp, bs, &rs, &t);
   t.ms_per_step = best;
   if ((st = gpe_tuning_set(&d, &t)) != GPE_OK) return st;
   if (out) *out = t;

@@ -122,7 +122,8 @@ class gpe_server_stats(ctypes.Structure):
 class gpe_tuning(ctypes.Structure):
     _fields_ = [("width", ctypes.c_int32 * 3), ("xcd_remap", ctypes.c_int32 * 3),
                 ("pass_order", ctypes.c_int32 * 3), ("plan", ctypes.c_int32 * 3),
-                ("stream", ctypes.c_int32 * 3), ("ms_per_step", ctypes.c_double)]
+                ("stream", ctypes.c_int32 * 3), ("transpose", ctypes.c_int32),
+                ("ms_per_step", ctypes.c_double)]
 
 
 _P = ctypes.c_void_p
@@ -408,7 +409,8 @@ def gpe_request_bytes(desc, max_slots):
 def _tuning_dict(t, dim):
     return {"width": list(t.width[:dim]), "xcd_remap": list(t.xcd_remap[:dim]),
             "pass_order": list(t.pass_order[:dim]), "plan": list(t.plan[:dim]),
-            "stream": list(t.stream[:dim]), "ms_per_step": t.ms_per_step}
+            "stream": list(t.stream[:dim]), "transpose": t.transpose,
+            "ms_per_step": t.ms_per_step}
 
 
 def gpe_autotune(desc, steps=10):
@@ -420,8 +422,9 @@ def gpe_autotune(desc, steps=10):
     return _tuning_dict(t, desc.dim)
 
 
-def gpe_tuning_set(desc, width, xcd_remap, pass_order, plan=None, stream=None):
+def gpe_tuning_set(desc, width, xcd_remap, pass_order, plan=None, stream=None, transpose=0):
     t = gpe_tuning()
+    t.transpose = int(transpose)
     for j in range(desc.dim):
         t.width[j] = int(width[j])
         t.xcd_remap[j] = int(xcd_remap[j])

@@ -140,3 +140,29 @@ def test_separable_parameters_marshal_by_name():
     assert list(s.center) == [0.0, 0.0, 0.0] and list(s.phase) == [0.0, 0.0, 0.0]
     with pytest.raises(ValueError):
         gpe.fill_separable(gpe.gpe_separable(), dict(omega=[1.0]))
+
+
+def test_rotating_passes_entry(tmp_path):
+    d = desc((512, 512, 512), "fp32s")
+    gpe.gpe_tuning_set(d, [16, 8, 8], [0, 1, 1], [2, 0, 1], stream=[3, 1, 0], transpose=1)
+    t, found = gpe.gpe_tuning_get(d)
+    # the last axis keeps its width and tile order when the passes rotate
+    assert found and t["transpose"] == 1 and t["width"] == [16, 8, 8]
+    assert t["xcd_remap"] == [0, 1, 1]
+    path = tmp_path / "rot.json"
+    gpe.gpe_tuning_save(str(path))
+    assert json.loads(path.read_text())["classes"][0]["transpose"] == 1
+    gpe.gpe_tuning_clear()
+    gpe.gpe_tuning_load(str(path))
+    assert gpe.gpe_tuning_get(d)[0] == t
+    # in-place entries drop the last axis's width; entries without the key load as 0
+    gpe.gpe_tuning_set(d, [16, 8, 8], [0, 1, 1], [2, 1, 0])
+    t, _ = gpe.gpe_tuning_get(d)
+    assert t["transpose"] == 0 and t["width"] == [16, 8, 0]
+    assert gpe.gpe_tuning_get(desc((512, 512, 512)))[0]["transpose"] == 0
+    for bad in [dict(d=desc((64, 64)), w=[8, 8], x=[0, 0], o=[0, 1], tr=1),
+                dict(d=d, w=[16, 8, 4], x=[0, 1, 1], o=[2, 0, 1], tr=1),
+                dict(d=d, w=[16, 8, 8], x=[0, 1, 1], o=[2, 0, 1], tr=2)]:
+        with pytest.raises(gpe.GpeError) as e:
+            gpe.gpe_tuning_set(bad["d"], bad["w"], bad["x"], bad["o"], transpose=bad["tr"])
+        assert e.value.status == gpe.GPE_EINVAL
