@@ -308,7 +308,11 @@ typedef struct {
                              for the step passes and transforms; the register-heavy
                              passes (closing phase, imaginary-time passes, batched
                              slots, spectral derivative) take 8 where 16 would put
-                             1024 threads in a workgroup with FP64 arithmetic */
+                             1024 threads in a workgroup with FP64 arithmetic.  With
+                             FP32 storage (GPE_FP32, GPE_FP32_STATE) and in-place
+                             passes also 32: the plain step passes take tiles of 32
+                             columns that go through the LDS as two 16-column halves
+                             (the other passes take 16) */
   int32_t xcd_remap[3];   /* strided axes: 1 = each XCD takes a contiguous run of tiles */
   int32_t pass_order[3];  /* the axes (0 = slowest) in the order a step visits them */
   int32_t plan[3];        /* radix plan per axis: 0 default; 1 the alternative (1024

@@ -882,6 +882,97 @@ axis_pass_kernel(const PassArgs a) {
   }
 }
 
+// The plain in-place step pass (forward, per-frequency table, inverse) of a
+// strided axis over tiles of 2 W columns held as two W-column halves: both
+// halves are loaded at once and go through the LDS tile one after the other,
+// so the second half's loads and the first half's stores overlap the
+// arithmetic of the other half, and each row of the tile is 2 W sites wide.
+// For FP32 storage (the held half costs 8 x 2 FP32 registers per thread).
+// The arithmetic of a line is that of axis_pass_kernel in MODE_PLAIN.
+template <typename T, class PL, int W, int SM, typename SX>
+__global__ void __launch_bounds__(PL::TPL * W) axis_pass_halves_kernel(const PassArgs a) {
+  constexpr int N = PL::N, E = PL::E, TPL = PL::TPL;
+  constexpr int R0 = PL::rad(0), RL = PL::rad(PL::M - 1);
+  constexpr bool SLOAD = (SM & STREAM_LOAD) != 0, SSTORE = (SM & STREAM_STORE) != 0;
+  using L = Lds<N, W, true>;
+  __shared__ T lre[PL::M > 1 ? L::size : 1], lim[PL::M > 1 ? L::size : 1];
+  const int tid = threadIdx.x, c = tid % W, t = tid / W;
+  const int n1 = a.n[1], n2 = a.n[2];
+  int tile = blockIdx.x;
+  if (a.xcd_remap && (gridDim.x & 7) == 0)
+    tile = (blockIdx.x & 7) * (gridDim.x >> 3) + (blockIdx.x >> 3);
+  const int ct = n2 / (2 * W);
+  const int outer = tile / ct;
+  const int j2 = (tile % ct) * 2 * W + c;
+  long long base, S;
+  if (a.axis == 1) {
+    base = (long long)outer * n1 * n2 + j2;
+    S = n2;
+  } else {
+    base = (long long)outer * n2 + j2;
+    S = (long long)n1 * n2;
+  }
+  const cx<SX> *__restrict__ src = static_cast<const cx<SX> *>(a.src);
+  cx<SX> *__restrict__ dst = static_cast<cx<SX> *>(a.dst);
+  const tab_t<T> *__restrict__ tw = static_cast<const tab_t<T> *>(a.tw);
+  const tab_t<T> *__restrict__ mtab = static_cast<const tab_t<T> *>(a.mtab);
+  cx<SX> raw[2][E];
+#pragma unroll
+  for (int h = 0; h < 2; ++h)
+#pragma unroll
+    for (int b = 0; b < E / R0; ++b)
+#pragma unroll
+      for (int d = 0; d < R0; ++d) {
+        const long long i = base + h * W + PL::pos(0, t + TPL * b, d) * S;
+        if constexpr (SLOAD) raw[h][b * R0 + d] = load_stream(&src[i]);
+        else raw[h][b * R0 + d] = src[i];
+      }
+#pragma unroll
+  for (int h = 0; h < 2; ++h) {
+    cx<T> v[E];
+#pragma unroll
+    for (int k = 0; k < E; ++k) v[k] = cvt<T>(raw[h][k]);
+    // (the second half's first exchange waits for the first half's last reads)
+    forward_fft<PL, W, true>(v, t, c, lre, lim, tw, h == 0);
+#pragma unroll
+    for (int b = 0; b < E / RL; ++b)
+#pragma unroll
+      for (int d = 0; d < RL; ++d) {
+        const int f = PL::freq(PL::pos(PL::M - 1, t + TPL * b, d));
+        v[b * RL + d] = table_mul(v[b * RL + d], mtab[f]);
+      }
+    inverse_fft<PL, W, true>(v, t, c, lre, lim, tw, false);
+#pragma unroll
+    for (int b = 0; b < E / R0; ++b)
+#pragma unroll
+      for (int d = 0; d < R0; ++d) {
+        const long long i = base + h * W + PL::pos(0, t + TPL * b, d) * S;
+        if constexpr (SSTORE) store_stream(&dst[i], cvt<SX>(v[b * R0 + d]));
+        else dst[i] = cvt<SX>(v[b * R0 + d]);
+      }
+  }
+}
+
+template <typename T, class PL, typename SX>
+void launch_halves(const PassArgs &a, int mode, dim3 grid, dim3 block, hipStream_t s) {
+  switch (mode) {
+    case MODE_PLAIN:
+      hipLaunchKernelGGL((axis_pass_halves_kernel<T, PL, 16, 0, SX>), grid, block, 0, s, a);
+      break;
+    case MODE_PLAIN | STREAM_LOAD:
+      hipLaunchKernelGGL((axis_pass_halves_kernel<T, PL, 16, STREAM_LOAD, SX>), grid, block, 0, s,
+                         a);
+      break;
+    case MODE_PLAIN | STREAM_STORE:
+      hipLaunchKernelGGL((axis_pass_halves_kernel<T, PL, 16, STREAM_STORE, SX>), grid, block, 0,
+                         s, a);
+      break;
+    default:
+      hipLaunchKernelGGL((axis_pass_halves_kernel<T, PL, 16, STREAM_LOAD | STREAM_STORE, SX>),
+                         grid, block, 0, s, a);
+  }
+}
+
 template <class PL>
 constexpr int contig_lines() {
   return PL::TPL >= GPE_CONTIG_THREADS ? 1 : GPE_CONTIG_THREADS / PL::TPL;
@@ -978,6 +1069,14 @@ hipError_t launch_np(const PassArgs &a, const PassShape &sh, int mode, hipStream
   constexpr int W16 = fit_w(N, (int)(2 * sizeof(T)), 16, PL::TPL);
   if (!sh.strided) {
     launch_mode<T, PL, contig_lines<PL>(), false, SX>(a, mode, grid, block, s);
+  } else if (sh.W == 32) {
+    // two 16-column halves: the plain step pass with FP32 storage only
+    if constexpr (sizeof(SX) == 4 && N >= 256 && W16 == 16) {
+      if (base_mode(mode) != MODE_PLAIN || a.trans) return hipErrorInvalidValue;
+      launch_halves<T, PL, SX>(a, mode, grid, block, s);
+    } else {
+      return hipErrorInvalidValue;
+    }
   } else if (sh.W == 8) {
     launch_mode<T, PL, 8, true, SX>(a, mode, grid, block, s);
   } else if (sh.W == 16 && W16 == 16) {

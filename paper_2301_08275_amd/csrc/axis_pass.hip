@@ -104,7 +104,17 @@ PassShape pass_shape(int precision, const int n[3], int axis, int wreq, int plan
     const long long lines = (long long)n[0] * n[1];
     sh.blocks = (lines + sh.W - 1) / sh.W;
   } else {
-    const int want = wreq == 16 ? 16 : 8;
+    // 32: tiles of two 16-column halves (in-place plain step passes with FP32
+    // storage; launch_shape gives other passes 16)
+    if (wreq == 32 && !narrow && !trans && state_f32(precision) && sh.N >= 256 &&
+        fit_w(sh.N, math_f32(precision) ? 8 : 16, 16, tpl) == 16 && n[2] >= 32) {
+      sh.W = 32;
+      sh.threads = tpl * 16;
+      const long long outer = axis == 1 ? n[0] : n[1];
+      sh.blocks = outer * (n[2] / 32);
+      return sh;
+    }
+    const int want = wreq >= 16 ? 16 : 8;
     int ws = fit_w(sh.N, math_f32(precision) ? 8 : 16, want, tpl);
     if (narrow && ws == 16 && tpl * 16 == 1024 && (!math_f32(precision) || sh.N / tpl == 16))
       ws = 8;
@@ -127,11 +137,13 @@ PassShape pass_shape(int precision, const int n[3], int axis, int wreq, int plan
 
 PassShape launch_shape(int precision, const PassArgs &a) {
   const bool trans = a.trans && !a.slots;
-  const PassShape sh = pass_shape(precision, a.n, a.axis, a.wreq, a.plan, false, trans);
+  PassShape sh = pass_shape(precision, a.n, a.axis, a.wreq, a.plan, false, trans);
+  if (sh.W == 32 && (a.slots || pass::base_mode(pass::pick_mode(a, sh)) != pass::MODE_PLAIN))
+    sh = pass_shape(precision, a.n, a.axis, 16, a.plan, false, trans);
   // (narrowing changes strided tiles only, and the mode depends on the shape
   // only through the contiguous full-tile test, so the mode is unchanged)
   return pass::heavy_mode(pass::pick_mode(a, sh))
-             ? pass_shape(precision, a.n, a.axis, a.wreq, a.plan, true, trans)
+             ? pass_shape(precision, a.n, a.axis, a.wreq == 32 ? 16 : a.wreq, a.plan, true, trans)
              : sh;
 }
 

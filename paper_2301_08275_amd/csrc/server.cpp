@@ -149,6 +149,9 @@ struct gpe_server {
   // first served, at most heavy_active at once, beside the lighter ones.
   long long heavy_sites = 1LL << 23;
   int heavy_active = 1;
+  // GPU time per round of a running heavy request, in quanta (a running
+  // light request gets one).
+  double heavy_weight = 1.0;
   std::mutex mu;
   std::condition_variable cv_work, cv_done;
   std::deque<uint64_t> queue;
@@ -262,6 +265,7 @@ int steps_for(gpe_server *s, ShapeClass *c) {
   in.onchip = c->onchip;
   in.chunk = s->chunk;
   in.quantum_ms = s->quantum_ms;
+  if (gpe_sched::is_heavy(c->proto->sites, s->heavy_sites)) in.quantum_ms *= s->heavy_weight;
   in.main_round_ms = s->main_round_ms;
   in.sites = (double)c->proto->sites;
   in.esize = (double)c->proto->esize;
@@ -750,6 +754,10 @@ gpe_status gpe_server_create(uint64_t hbm_budget_bytes, int32_t max_slots, int32
   }
   if (const char *h = std::getenv("GPE_SERVER_HEAVY_SITES")) s->heavy_sites = std::atoll(h);
   if (const char *h = std::getenv("GPE_SERVER_HEAVY_ACTIVE")) s->heavy_active = std::atoi(h);
+  if (const char *h = std::getenv("GPE_SERVER_HEAVY_WEIGHT")) {
+    const double v = std::atof(h);
+    if (v > 0) s->heavy_weight = v;
+  }
   s->t0 = std::chrono::steady_clock::now();
   s->th = std::thread(scheduler, s);
   *out = s;

@@ -65,7 +65,7 @@ void defaults(const gpe_desc &d, int wreq[3], int xcd[3], int order[3], int plan
   order[2] = 0;
 }
 
-bool valid_tuning(int dim, const int *n, const gpe_tuning &t, std::string &msg) {
+bool valid_tuning(int dim, const int *n, int precision, const gpe_tuning &t, std::string &msg) {
   for (int j = 0; j < dim; ++j)
     if (!gpe::plan_available(n[j], t.plan[j])) {
       msg = "plan 1 exists only for 1024-point axes";
@@ -82,8 +82,10 @@ bool valid_tuning(int dim, const int *n, const gpe_tuning &t, std::string &msg) 
   }
   const int tiled = t.transpose ? dim : dim - 1;  // axes with tile widths
   for (int j = 0; j < tiled; ++j) {
-    if (t.width[j] != 8 && t.width[j] != 16) {
-      msg = "width must be 8 or 16 on the strided axes";
+    // 32: two 16-column halves per tile, in-place passes with FP32 storage
+    const bool halves = t.width[j] == 32 && !t.transpose && precision != GPE_FP64;
+    if (t.width[j] != 8 && t.width[j] != 16 && !halves) {
+      msg = "width must be 8 or 16 on the strided axes (or 32 with FP32 storage)";
       return false;
     }
     if (t.xcd_remap[j] != 0 && t.xcd_remap[j] != 1) {
@@ -314,7 +316,7 @@ gpe_status gpe_tuning_set(const gpe_desc *desc, const gpe_tuning *t) {
   std::string msg;
   gpe_status st = validate_desc(desc, msg);
   if (st != GPE_OK) return st;
-  if (!t || !valid_tuning(desc->dim, desc->n, *t, msg)) return GPE_EINVAL;
+  if (!t || !valid_tuning(desc->dim, desc->n, desc->precision, *t, msg)) return GPE_EINVAL;
   gpe_tuning v = *t;
   for (int j = v.transpose ? desc->dim : desc->dim - 1; j < 3; ++j) v.width[j] = v.xcd_remap[j] = 0;
   for (int i = desc->dim; i < 3; ++i) v.pass_order[i] = v.plan[i] = v.stream[i] = 0;
@@ -437,7 +439,7 @@ gpe_status gpe_tuning_load(const char *path) {
     const JVal *tp = e.get("transpose");  // optional likewise
     if (tp && (tp->kind != JVal::NUM || (tp->num != 0 && tp->num != 1))) return GPE_EINVAL;
     t.transpose = tp ? (int32_t)tp->num : 0;
-    if (validate_desc(&desc, msg) != GPE_OK || !valid_tuning(d, desc.n, t, msg))
+    if (validate_desc(&desc, msg) != GPE_OK || !valid_tuning(d, desc.n, desc.precision, t, msg))
       return GPE_EINVAL;
     t.ms_per_step = ms && ms->kind == JVal::NUM ? ms->num : 0;
     entries.emplace_back(desc, t);
@@ -522,9 +524,10 @@ gpe_status gpe_autotune(const gpe_desc *desc, int32_t steps, gpe_tuning *out) {
     for (int ax = off; ax < 3 && best > 0; ++ax) {
       for (int pl : {0, 1}) {
         if (!gpe::plan_available(c->n3[ax], pl)) continue;
-        for (int w : {8, 16}) {
+        for (int w : {8, 16, 32}) {
           // (a rotating pass has tiles on every axis, the in-place contiguous one none)
           const bool tiled = ax != 2 || bt;
+          if (w == 32 && (bt || d.precision == GPE_FP64)) continue;
           if (!tiled && w != bw[ax]) continue;
           if (tiled && gpe::pass_shape(d.precision, c->n3, ax, w, pl, false, bt).W != w) continue;
           for (int x : {0, 1}) {

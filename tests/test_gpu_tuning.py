@@ -127,3 +127,22 @@ def test_alternative_radix_plan_matches_oracle(prec, tol):
     ref = oracle.tssp_real(x, lo, hi, V, 2.0, 1e-3, 3)
     got = run(shape, lo, hi, 2.0, [1.0, 0.5, 0.5], x, 3, prec)
     assert rel(got, ref) < max(tol, 1e-12) * 10
+
+
+@pytest.mark.parametrize("prec", ["fp32s", "fp32"])
+@pytest.mark.parametrize("shape", [(256, 128, 64), (512, 32, 64)])
+def test_two_half_tiles_are_bitwise_neutral(prec, shape):
+    """Width 32 (FP32 storage): the plain step passes of the strided axes take
+    32-column tiles that go through the LDS as two 16-column halves; the
+    arithmetic of every line is that of the 16-column tiles."""
+    lo, hi = (-6.0,) * 3, (6.0,) * 3
+    trap = [1.0, 2.0, 3.0]
+    psi0 = I.noisy_gaussian(shape, lo, hi, seed=17)
+    d = gpe.make_desc(shape, lo, hi, 20.0, prec)
+    gpe.gpe_tuning_set(d, [16, 16, 0], [1, 1, 0], [2, 1, 0])
+    ref = run(shape, lo, hi, 20.0, trap, psi0, 9, prec)
+    for xcd, stream in [((1, 1, 0), (0, 0, 0)), ((0, 0, 0), (3, 1, 0)), ((1, 0, 0), (2, 3, 0))]:
+        gpe.gpe_tuning_set(d, [32, 32, 0], list(xcd), [2, 1, 0], stream=list(stream))
+        say(prec, shape, "two halves", xcd, stream)
+        got = run(shape, lo, hi, 20.0, trap, psi0, 9, prec)
+        assert np.array_equal(got, ref), (xcd, stream)

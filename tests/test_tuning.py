@@ -166,3 +166,14 @@ def test_rotating_passes_entry(tmp_path):
         with pytest.raises(gpe.GpeError) as e:
             gpe.gpe_tuning_set(bad["d"], bad["w"], bad["x"], bad["o"], transpose=bad["tr"])
         assert e.value.status == gpe.GPE_EINVAL
+
+
+def test_two_half_tiles_need_fp32_storage_and_in_place_passes():
+    for prec in ("fp32s", "fp32"):
+        d = desc((512, 512, 512), prec)
+        gpe.gpe_tuning_set(d, [32, 16, 0], [0, 1, 0], [2, 1, 0])
+        assert gpe.gpe_tuning_get(d)[0]["width"] == [32, 16, 0]
+    for d, tr in [(desc((512, 512, 512)), 0), (desc((512, 512, 512), "fp32s"), 1)]:
+        with pytest.raises(gpe.GpeError) as e:
+            gpe.gpe_tuning_set(d, [32, 16, 16], [0, 1, 1], [2, 0, 1], transpose=tr)
+        assert e.value.status == gpe.GPE_EINVAL
