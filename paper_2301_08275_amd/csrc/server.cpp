@@ -150,8 +150,11 @@ struct gpe_server {
   long long heavy_sites = 1LL << 23;
   int heavy_active = 1;
   // GPU time per round of a running heavy request, in quanta (a running
-  // light request gets one).
+  // light request gets one): at least heavy_weight, and at least
+  // heavy_share / (1 - heavy_share) times the light requests' total, so that
+  // the heavy tier keeps that fraction of each round (0: no such floor).
   double heavy_weight = 1.0;
+  double heavy_share = 0.0;
   std::mutex mu;
   std::condition_variable cv_work, cv_done;
   std::deque<uint64_t> queue;
@@ -265,7 +268,14 @@ int steps_for(gpe_server *s, ShapeClass *c) {
   in.onchip = c->onchip;
   in.chunk = s->chunk;
   in.quantum_ms = s->quantum_ms;
-  if (gpe_sched::is_heavy(c->proto->sites, s->heavy_sites)) in.quantum_ms *= s->heavy_weight;
+  if (gpe_sched::is_heavy(c->proto->sites, s->heavy_sites)) {
+    double w = s->heavy_weight;
+    if (s->heavy_share > 0 && s->heavy_share < 1) {
+      const int lights = s->running - s->running_heavy;
+      w = std::max(w, s->heavy_share / (1 - s->heavy_share) * lights);
+    }
+    in.quantum_ms *= w;
+  }
   in.main_round_ms = s->main_round_ms;
   in.sites = (double)c->proto->sites;
   in.esize = (double)c->proto->esize;
@@ -757,6 +767,10 @@ gpe_status gpe_server_create(uint64_t hbm_budget_bytes, int32_t max_slots, int32
   if (const char *h = std::getenv("GPE_SERVER_HEAVY_WEIGHT")) {
     const double v = std::atof(h);
     if (v > 0) s->heavy_weight = v;
+  }
+  if (const char *h = std::getenv("GPE_SERVER_HEAVY_SHARE")) {
+    const double v = std::atof(h);
+    if (v >= 0 && v < 1) s->heavy_share = v;
   }
   s->t0 = std::chrono::steady_clock::now();
   s->th = std::thread(scheduler, s);
