@@ -312,7 +312,8 @@ typedef struct {
                              FP32 storage (GPE_FP32, GPE_FP32_STATE) and in-place
                              passes also 32: the plain step passes take tiles of 32
                              columns that go through the LDS as two 16-column halves
-                             (the other passes take 16) */
+                             (the other passes take 16); with transpose = 1 also 4
+                             (4-line tiles, axes of 128 points or more) */
   int32_t xcd_remap[3];   /* strided axes: 1 = each XCD takes a contiguous run of tiles */
   int32_t pass_order[3];  /* the axes (0 = slowest) in the order a step visits them */
   int32_t plan[3];        /* radix plan per axis: 0 default; 1 the alternative (1024

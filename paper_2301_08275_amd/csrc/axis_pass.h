@@ -1077,6 +1077,14 @@ hipError_t launch_np(const PassArgs &a, const PassShape &sh, int mode, hipStream
     } else {
       return hipErrorInvalidValue;
     }
+  } else if (sh.W == 4) {
+    // 4-line tiles: rotating passes only (rows of 4 sites)
+    if constexpr (N >= 128) {
+      if (!a.trans) return hipErrorInvalidValue;
+      launch_mode<T, PL, 4, true, SX>(a, mode, grid, block, s);
+    } else {
+      return hipErrorInvalidValue;
+    }
   } else if (sh.W == 8) {
     launch_mode<T, PL, 8, true, SX>(a, mode, grid, block, s);
   } else if (sh.W == 16 && W16 == 16) {

@@ -120,8 +120,9 @@ PassShape pass_shape(int precision, const int n[3], int axis, int wreq, int plan
       ws = 8;
     if (trans) {
       // W lines at consecutive positions of the next axis, one tile per
-      // (third-axis position, run of W)
+      // (third-axis position, run of W); also 4 lines (N >= 128)
       const int nb = n[axis == 2 ? 0 : axis + 1], nc = n[3 - axis - (axis == 2 ? 0 : axis + 1)];
+      if (wreq == 4 && !narrow && sh.N >= 128) ws = 4;
       sh.W = nb >= ws ? ws : 8;
       sh.threads = tpl * sh.W;
       sh.blocks = (long long)nc * (nb / sh.W);

@@ -139,23 +139,6 @@ __global__ void __launch_bounds__(kShellThreads) shell_kernel(const ShellArgs a)
   for (long long s0 = (long long)blockIdx.x * blockDim.x * U; s0 < sites; s0 += step) {
     ShellSite q[U];
     cxs<T> zp[U][NF], zm[U][NF];
-    // Kind 1 on rows of at least 128 points: a wavefront's 64 sites past the
-    // Nyquist index of a row whose sites pair up with their mirrors have
-    // nothing to add (their mirrors count them), so the wavefront skips them
-    // whole (3 of 8 chunks of a 512-point row); the sums do not change.
-    bool skip[U];
-#pragma unroll
-    for (int u = 0; u < U; ++u) {
-      skip[u] = false;
-      if (KIND != 0 && !rows_apart) {
-        const long long sw = s0 + (long long)u * blockDim.x + (threadIdx.x & ~63);
-        const long long r = sw >> l2;
-        const int i1 = (int)(r & (a.n[1] - 1)), i0 = (int)(r >> l1);
-        const bool pairs = (2 * i0 != a.n[0] || a.kscale[0] == 0) &&
-                           (2 * i1 != a.n[1] || a.kscale[1] == 0);
-        skip[u] = sw >= sites || (pairs && 2 * (int)(sw & (n2 - 1)) > n2);
-      }
-    }
 #pragma unroll
     for (int u = 0; u < U; ++u)
       q[u] = shell_site<KIND>(a, s0 + (long long)u * blockDim.x + threadIdx.x, sites, l1, l2);
@@ -168,10 +151,6 @@ __global__ void __launch_bounds__(kShellThreads) shell_kernel(const ShellArgs a)
       if (fs[j]) {  // (uniform: a missing axis has no field)
 #pragma unroll
         for (int u = 0; u < U; ++u) {
-          if (skip[u]) {
-            zp[u][j] = zm[u][j] = cxs<T>{0, 0};
-            continue;
-          }
           zp[u][j] = fs[j][q[u].on ? q[u].s : 0];
           zm[u][j] = KIND != 0 ? fs[j][q[u].on ? q[u].ms : 0] : cxs<T>{0, 0};
         }
@@ -191,7 +170,6 @@ __global__ void __launch_bounds__(kShellThreads) shell_kernel(const ShellArgs a)
       en[u] = a.w * ((double)zp[u][0].x * zp[u][0].x + (double)zp[u][0].y * zp[u][0].y);
 #pragma unroll
     for (int u = 0; u < U; ++u) {
-      if (skip[u]) continue;  // (the whole wavefront)
       const int key_next = __shfl_down(q[u].key, 1, 64);
       const bool last = q[u].on && (lane == 63 || key_next != q[u].key);
       if constexpr (KIND == 0) {

@@ -84,8 +84,9 @@ bool valid_tuning(int dim, const int *n, int precision, const gpe_tuning &t, std
   for (int j = 0; j < tiled; ++j) {
     // 32: two 16-column halves per tile, in-place passes with FP32 storage
     const bool halves = t.width[j] == 32 && !t.transpose && precision != GPE_FP64;
-    if (t.width[j] != 8 && t.width[j] != 16 && !halves) {
-      msg = "width must be 8 or 16 on the strided axes (or 32 with FP32 storage)";
+    const bool quad = t.width[j] == 4 && t.transpose;
+    if (t.width[j] != 8 && t.width[j] != 16 && !halves && !quad) {
+      msg = "width must be 8 or 16 (32: in-place, FP32 storage; 4: rotating passes)";
       return false;
     }
     if (t.xcd_remap[j] != 0 && t.xcd_remap[j] != 1) {
@@ -524,10 +525,11 @@ gpe_status gpe_autotune(const gpe_desc *desc, int32_t steps, gpe_tuning *out) {
     for (int ax = off; ax < 3 && best > 0; ++ax) {
       for (int pl : {0, 1}) {
         if (!gpe::plan_available(c->n3[ax], pl)) continue;
-        for (int w : {8, 16, 32}) {
+        for (int w : {4, 8, 16, 32}) {
           // (a rotating pass has tiles on every axis, the in-place contiguous one none)
           const bool tiled = ax != 2 || bt;
           if (w == 32 && (bt || d.precision == GPE_FP64)) continue;
+          if (w == 4 && !bt) continue;
           if (!tiled && w != bw[ax]) continue;
           if (tiled && gpe::pass_shape(d.precision, c->n3, ax, w, pl, false, bt).W != w) continue;
           for (int x : {0, 1}) {

@@ -37,8 +37,9 @@ def clean_table():
     gpe.gpe_tuning_clear()
 
 
-def set_rotating(d, width=(8, 8, 8), xcd=(1, 1, 1), stream=(0, 0, 0)):
-    gpe.gpe_tuning_set(d, list(width), list(xcd), ORDER, stream=list(stream), transpose=1)
+def set_rotating(d, width=(8, 8, 8), xcd=(1, 1, 1), stream=(0, 0, 0), plan=None):
+    gpe.gpe_tuning_set(d, list(width), list(xcd), ORDER, stream=list(stream), transpose=1,
+                       plan=plan)
 
 
 def set_in_place(d):
@@ -74,7 +75,8 @@ def test_rotating_real_time_is_bitwise_the_in_place_passes(shape, prec):
     say("in place", shape, prec)
     ref = real_run(shape, lo, hi, 25.0, psi0, [3, 4, 1], prec, trap=trap)
     combos = [((8, 8, 8), (1, 1, 1), (0, 0, 0)), ((16, 16, 16), (0, 0, 0), (3, 1, 2)),
-              ((8, 16, 8), (0, 1, 0), (1, 2, 3))]
+              ((8, 16, 8), (0, 1, 0), (1, 2, 3)), ((4, 4, 4), (1, 1, 1), (3, 3, 1)),
+              ((4, 8, 16), (0, 1, 1), (0, 2, 0))]
     for width, xcd, stream in combos:
         set_rotating(d, width, xcd, stream)
         t, found = gpe.gpe_tuning_get(d)
@@ -158,3 +160,24 @@ def test_rotating_is_refused_where_it_does_not_apply():
     set_rotating(d)
     got = real_run(shape, lo, hi, 5.0, psi0, [40], trap=[1.0, 1.0, 1.0])[0][0]
     assert np.array_equal(got, ref)
+
+
+@pytest.mark.parametrize("shape,prec", [((1024, 32, 64), "fp64"), ((32, 64, 1024), "fp32s"),
+                                        ((64, 1024, 32), "fp32")])
+def test_rotating_passes_on_1024_point_axes(shape, prec):
+    """A 1024-point axis in the rotating form, with either radix plan (16
+    points per thread, or 8 with one more exchange each way)."""
+    lo, hi = (-6.0, -7.0, -8.0), (6.0, 7.0, 8.0)
+    trap = [1.0, 1.5, 2.0]
+    psi0 = I.noisy_gaussian(shape, lo, hi, seed=56)
+    d = gpe.make_desc(shape, lo, hi, 25.0, prec)
+    big = [int(n == 1024) for n in shape]
+    for plan in ([0, 0, 0], big):
+        gpe.gpe_tuning_set(d, [16, 8, 0], [1, 1, 0], ORDER, plan=plan)
+        say("in place", shape, prec, "plan", plan)
+        ref = real_run(shape, lo, hi, 25.0, psi0, [3, 2], prec, trap=trap)
+        set_rotating(d, plan=plan)
+        say("rotating", shape, prec, "plan", plan)
+        got = real_run(shape, lo, hi, 25.0, psi0, [3, 2], prec, trap=trap)
+        for (a, _, _), (b, _, _) in zip(got, ref):
+            assert np.array_equal(a, b), plan

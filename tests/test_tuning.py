@@ -161,7 +161,7 @@ def test_rotating_passes_entry(tmp_path):
     assert t["transpose"] == 0 and t["width"] == [16, 8, 0]
     assert gpe.gpe_tuning_get(desc((512, 512, 512)))[0]["transpose"] == 0
     for bad in [dict(d=desc((64, 64)), w=[8, 8], x=[0, 0], o=[0, 1], tr=1),
-                dict(d=d, w=[16, 8, 4], x=[0, 1, 1], o=[2, 0, 1], tr=1),
+                dict(d=d, w=[16, 8, 2], x=[0, 1, 1], o=[2, 0, 1], tr=1),
                 dict(d=d, w=[16, 8, 8], x=[0, 1, 1], o=[2, 0, 1], tr=2)]:
         with pytest.raises(gpe.GpeError) as e:
             gpe.gpe_tuning_set(bad["d"], bad["w"], bad["x"], bad["o"], transpose=bad["tr"])
@@ -177,3 +177,12 @@ def test_two_half_tiles_need_fp32_storage_and_in_place_passes():
         with pytest.raises(gpe.GpeError) as e:
             gpe.gpe_tuning_set(d, [32, 16, 16], [0, 1, 1], [2, 0, 1], transpose=tr)
         assert e.value.status == gpe.GPE_EINVAL
+
+
+def test_four_line_tiles_only_for_rotating_passes():
+    d = desc((512, 512, 512))
+    gpe.gpe_tuning_set(d, [4, 8, 4], [1, 1, 1], [2, 0, 1], transpose=1)
+    assert gpe.gpe_tuning_get(d)[0]["width"] == [4, 8, 4]
+    with pytest.raises(gpe.GpeError) as e:
+        gpe.gpe_tuning_set(d, [4, 8, 0], [1, 1, 0], [2, 1, 0])
+    assert e.value.status == gpe.GPE_EINVAL
