@@ -176,8 +176,9 @@ def test_rotating_passes_on_1024_point_axes(shape, prec):
         gpe.gpe_tuning_set(d, [16, 8, 0], [1, 1, 0], ORDER, plan=plan)
         say("in place", shape, prec, "plan", plan)
         ref = real_run(shape, lo, hi, 25.0, psi0, [3, 2], prec, trap=trap)
-        set_rotating(d, plan=plan)
-        say("rotating", shape, prec, "plan", plan)
-        got = real_run(shape, lo, hi, 25.0, psi0, [3, 2], prec, trap=trap)
-        for (a, _, _), (b, _, _) in zip(got, ref):
-            assert np.array_equal(a, b), plan
+        for width in ((8, 8, 8), (4, 4, 4)):
+            set_rotating(d, width=width, plan=plan)
+            say("rotating", shape, prec, "plan", plan, "width", width)
+            got = real_run(shape, lo, hi, 25.0, psi0, [3, 2], prec, trap=trap)
+            for (a, _, _), (b, _, _) in zip(got, ref):
+                assert np.array_equal(a, b), (plan, width)
