@@ -602,6 +602,11 @@ enum PassMode : int {
 // (non-temporal) loads, stores or both: mode | STREAM_LOAD and/or
 // | STREAM_STORE.
 constexpr int STREAM_LOAD = 16, STREAM_STORE = 32;
+// The batched slot modes also come with the role of the pass in the step
+// fixed at compile time (first: the opening phase, and in imaginary time the
+// pending scale; last: the closing phase and the norm sums; neither: plain):
+// mode | SLOT_ROLE, plus SLOT_FIRST and/or SLOT_LAST.
+constexpr int SLOT_FIRST = 64, SLOT_LAST = 128, SLOT_ROLE = 256;
 __host__ __device__ constexpr int base_mode(int m) { return m & 15; }
 
 // Storage type of the state in HBM, converted on load and store: the
@@ -661,7 +666,9 @@ axis_pass_kernel(const PassArgs a) {
     const int step = sl.steps_done + a.slot_step;
     if (sl.mode == SLOT_FREE || step >= sl.steps_total) return;
     constexpr bool im = SLI;
-    const bool first = a.slot_pass & SLOT_PASS_FIRST, last = a.slot_pass & SLOT_PASS_LAST;
+    constexpr bool ROLE = (MODE_ARG & SLOT_ROLE) != 0;
+    const bool first = ROLE ? (MODE_ARG & SLOT_FIRST) != 0 : (a.slot_pass & SLOT_PASS_FIRST) != 0;
+    const bool last = ROLE ? (MODE_ARG & SLOT_LAST) != 0 : (a.slot_pass & SLOT_PASS_LAST) != 0;
     psrc = sl.psi;
     pdst = sl.psi;
     ptab = im ? a.mtab_imag : a.mtab;
@@ -1005,14 +1012,27 @@ void launch_mode(const PassArgs &a, int mode, dim3 grid, dim3 block, hipStream_t
       hipLaunchKernelGGL((axis_pass_kernel<T, PL, W, STRIDED, MODE_POST_IMAG_RED, SX>), grid,
                          block, 0, s, a);
       break;
-    case MODE_SLOTS_REAL:
-      hipLaunchKernelGGL((axis_pass_kernel<T, PL, W, STRIDED, MODE_SLOTS_REAL, SX>), grid, block,
-                         0, s, a);
-      break;
-    case MODE_SLOTS_IMAG:
-      hipLaunchKernelGGL((axis_pass_kernel<T, PL, W, STRIDED, MODE_SLOTS_IMAG, SX>), grid, block,
-                         0, s, a);
-      break;
+#define GPE_SLOT_CASES(M)                                                                     \
+  case M | SLOT_ROLE:                                                                           \
+    hipLaunchKernelGGL((axis_pass_kernel<T, PL, W, STRIDED, M | SLOT_ROLE, SX>), grid, block, 0, \
+                       s, a);                                                                   \
+    break;                                                                                      \
+  case M | SLOT_ROLE | SLOT_FIRST:                                                              \
+    hipLaunchKernelGGL((axis_pass_kernel<T, PL, W, STRIDED, M | SLOT_ROLE | SLOT_FIRST, SX>),    \
+                       grid, block, 0, s, a);                                                   \
+    break;                                                                                      \
+  case M | SLOT_ROLE | SLOT_LAST:                                                               \
+    hipLaunchKernelGGL((axis_pass_kernel<T, PL, W, STRIDED, M | SLOT_ROLE | SLOT_LAST, SX>),     \
+                       grid, block, 0, s, a);                                                   \
+    break;                                                                                      \
+  case M | SLOT_ROLE | SLOT_FIRST | SLOT_LAST:                                                  \
+    hipLaunchKernelGGL(                                                                         \
+        (axis_pass_kernel<T, PL, W, STRIDED, M | SLOT_ROLE | SLOT_FIRST | SLOT_LAST, SX>), grid,  \
+        block, 0, s, a);                                                                        \
+    break;
+    GPE_SLOT_CASES(MODE_SLOTS_REAL)
+    GPE_SLOT_CASES(MODE_SLOTS_IMAG)
+#undef GPE_SLOT_CASES
     case MODE_FWD:
       hipLaunchKernelGGL((axis_pass_kernel<T, PL, W, STRIDED, MODE_FWD, SX>), grid, block, 0, s,
                          a);

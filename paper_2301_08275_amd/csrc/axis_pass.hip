@@ -35,7 +35,10 @@ int stream_bits(const PassArgs &a) {
 }
 
 int pick_mode(const PassArgs &a, const PassShape &sh) {
-  if (a.slots) return a.slot_imag ? MODE_SLOTS_IMAG : MODE_SLOTS_REAL;
+  if (a.slots)
+    return (a.slot_imag ? MODE_SLOTS_IMAG : MODE_SLOTS_REAL) | SLOT_ROLE |
+           ((a.slot_pass & SLOT_PASS_FIRST) ? SLOT_FIRST : 0) |
+           ((a.slot_pass & SLOT_PASS_LAST) ? SLOT_LAST : 0);
   const bool full = sh.strided || ((long long)a.n[0] * a.n[1]) % sh.W == 0;
   if (!full || !a.forward) return MODE_GENERIC;
   if (!a.store) {
