@@ -374,7 +374,14 @@ gpe_status gpe_tuning_load(const char *path);
  * nor on how its steps are cut into chunks.  Requests of 2^23 grid points or
  * more (the heavy tier) run first come, first served among themselves, one
  * at a time, beside the lighter requests: a heavy request waiting for the
- * tier does not hold back the requests queued behind it.
+ * tier does not hold back the requests queued behind it.  Environment
+ * settings read at gpe_server_create: GPE_SERVER_HEAVY_SITES (tier
+ * threshold, 0 turns the tier off), GPE_SERVER_HEAVY_ACTIVE (heavy requests
+ * running at once), GPE_SERVER_HEAVY_WEIGHT (GPU time per round of a heavy
+ * request, in light-request quanta; default 1), GPE_SERVER_HEAVY_SHARE
+ * (0 <= f < 1: the heavy tier keeps at least that fraction of each round;
+ * default 0) and GPE_SERVER_QUANTUM_MS (GPU time per running request per
+ * round; default 1).
  *
  * Beyond the request/poll/cancel calls a plain submit-and-wait interface
  * needs, this interface adds: max_active and chunk_steps at creation,
