@@ -10,8 +10,10 @@
 // (pre), runs the forward DFT of every line through registers and LDS,
 // multiplies by a per-frequency table (kinetic factor with 1/N, a spectral
 // derivative, ...), runs the inverse DFT, optionally applies the phase again
-// (post) and accumulates sums, and stores the lines back.  A 3D real-time step
-// is three such launches: 32 bytes of HBM traffic per site per launch in FP64.
+// (post) and accumulates sums, and stores the lines back (or, in the rotating
+// form, into a second array in the layout the next pass reads).  A 3D
+// real-time step is three such launches: 32 bytes of HBM traffic per site per
+// launch in FP64.
 //
 // FFT: mixed-radix (2/4/8/16) Cooley-Tukey, decimation in frequency for the
 // forward transform (digit-reversed spectrum, never reordered) and the exact

@@ -112,13 +112,18 @@ struct PassShape {
 // Launch geometry the kernels are built for (must match the template choice).
 // plan: 0 the default radix plan of the axis length, 1 the alternative
 // (only 1024 points has one; elsewhere 1 means 0).
+// wreq: columns (or rotating lines) per tile, 8 or 16; 32 gives the plain
+// in-place step pass of an FP32-storage strided axis tiles of two 16-column
+// halves (PassShape::W = 32; other passes use 16); 4 gives rotating passes on
+// axes of 128 points or more 4-line tiles.
 // narrow: the pass runs one of the register-heavy operation sets (closing
 // real-time phase, imaginary-time pre and post passes, batched slots, the
 // spectral derivative, generic; also the exact imaginary-time pre pass, which
 // is compute-bound there).  Where a 16-column strided tile would take
 // 1024 threads (128 VGPRs each) with FP64 arithmetic or 16 points per thread,
-// those kernels spill to scratch, so they take 8-column tiles there.  Block
-// counts with narrow = true are never smaller than without.
+// those kernels take 8-column tiles (measured faster; the generic and
+// derivative sets would also spill).  Block counts with narrow = true are
+// never smaller than without.
 // trans: the rotating form of the pass (PassArgs::trans; 3D only): tiles of
 // W whole lines of the axis at consecutive positions of the next axis.
 PassShape pass_shape(int precision, const int n[3], int axis, int wreq, int plan = 0,
@@ -128,7 +133,7 @@ PassShape pass_shape(int precision, const int n[3], int axis, int wreq, int plan
 PassShape launch_shape(int precision, const PassArgs &a);
 inline bool plan_available(int n, int plan) { return plan == 0 || (plan == 1 && n == 1024); }
 
-// Launch one axis pass; precision 0 = FP64, 1 = FP32.
+// Launch one axis pass; precision 0 = FP64, 1 = FP32, 2 = FP32 state.
 hipError_t launch_axis_pass(int precision, const PassArgs &a, hipStream_t s);
 
 // Sum `count` partial blocks of kRedSlots doubles in fixed order into
