@@ -761,14 +761,24 @@ axis_pass_kernel(const PassArgs a) {
   for (int k = 0; k < kRedSlots; ++k) acc[k] = 0;
 
   cx<T> v[E];
+  // The derivative pass combines its result with the state at the same
+  // positions it loaded: it keeps the loaded values (in the storage type)
+  // instead of reading them again.
+  cx<SX> kept[DER ? E : 1];
   if (forward) {
 #pragma unroll
     for (int b = 0; b < E / R0; ++b)
 #pragma unroll
       for (int d = 0; d < R0; ++d) {
         const int p = PL::pos(0, t + TPL * b, d);
-        if constexpr (SLOAD) v[b * R0 + d] = cvt<T>(load_stream(&src[bin + p * Sin]));
-        else v[b * R0 + d] = valid ? cvt<T>(src[bin + p * Sin]) : cx<T>{0, 0};
+        if constexpr (SLOAD) {
+          v[b * R0 + d] = cvt<T>(load_stream(&src[bin + p * Sin]));
+        } else if constexpr (DER) {
+          kept[b * R0 + d] = valid ? src[bin + p * Sin] : cx<SX>{0, 0};
+          v[b * R0 + d] = cvt<T>(kept[b * R0 + d]);
+        } else {
+          v[b * R0 + d] = valid ? cvt<T>(src[bin + p * Sin]) : cx<T>{0, 0};
+        }
       }
     if (has_scale || pre != PH_NONE || (red & RED_REAL)) {
       const double sc = has_scale ? *pscale : 1.0;
@@ -837,8 +847,11 @@ axis_pass_kernel(const PassArgs a) {
           const int p = PL::pos(0, t + TPL * b, d);
           cx<T> u = v[b * R0 + d];
           if (post == PH_DERIV) {
-            // combine the derivative with the state at this site (re-read)
-            const cx<T> q = valid ? cvt<T>(src[bin + p * Sin]) : cx<T>{0, 0};
+            // combine the derivative with the state at this site (kept from
+            // the load, or read again in the generic mode)
+            cx<T> q;
+            if constexpr (DER) q = cvt<T>(kept[b * R0 + d]);
+            else q = valid ? cvt<T>(src[bin + p * Sin]) : cx<T>{0, 0};
             const double qr = q.x, qi = q.y, dr = u.x, di = u.y;
             const double mag = sqrt(qr * qr + qi * qi);
             const double zr = qr * dr + qi * di, zi = qr * di - qi * dr;  // conj(q) d

@@ -218,7 +218,7 @@ gpe_status launch_pass(gpe_ctx *c, const gpe::PassArgs &a) {
     }
     double bytes = (double)c->sites * c->esize;  // every pass reads the state once
     bytes += a.store ? (double)c->sites * c->esize : 0;
-    if (a.post == gpe::PH_DERIV) bytes += (double)c->sites * c->esize;  // re-reads psi
+    // (the derivative pass combines with the state it loaded: no second read)
     if (c->V && (a.pre != gpe::PH_NONE || a.post != gpe::PH_NONE)) bytes += 8.0 * c->sites;
     c->kinds[kind].bytes = bytes;
     if (!c->event_pool.empty()) {
