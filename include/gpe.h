@@ -380,8 +380,14 @@ gpe_status gpe_tuning_load(const char *path);
  * running at once), GPE_SERVER_HEAVY_WEIGHT (GPU time per round of a heavy
  * request, in light-request quanta; default 1), GPE_SERVER_HEAVY_SHARE
  * (0 <= f < 1: the heavy tier keeps at least that fraction of each round;
- * default 0) and GPE_SERVER_QUANTUM_MS (GPU time per running request per
- * round; default 1).
+ * default 0), GPE_SERVER_QUANTUM_MS (GPU time per running request per
+ * round; default 1), GPE_SERVER_HEAVY_BESIDE (1, the default: heavy
+ * requests run on a stream of their own, concurrently with the lighter
+ * classes, each chunk lasting about as long as the lighter classes' round;
+ * 0: they take their quanta in turn with the others), GPE_SERVER_ONCHIP
+ * (0 routes no class to the on-chip kernel) and GPE_SERVER_ONCHIP_MAX_N
+ * (largest square 2D edge routed there, default 64; the kernel itself holds
+ * up to 64 in FP64 and 128 in FP32).
  *
  * Beyond the request/poll/cancel calls a plain submit-and-wait interface
  * needs, this interface adds: max_active and chunk_steps at creation,

@@ -16,7 +16,10 @@
 //     form on-chip classes instead: one workgroup per request holds the whole
 //     grid in LDS and runs the chunk's steps in one launch, on a side stream,
 //     so they occupy a few CUs beside the large classes and are paced to
-//     last about as long as the main stream's round;
+//     last about as long as the main stream's round.  Heavy-tier classes
+//     (the largest grids, first come, first served) run on a stream of their
+//     own in the same way: concurrently with the lighter classes, so a
+//     heavy solve is not held to one quantum per round beside them;
 //  3. copies the slot tables back and only then waits for the previous
 //     round's chunk, and finishes the requests that chunk completed (final
 //     imaginary-time scaling, observables, optional state download, all on the
@@ -114,6 +117,7 @@ struct ShapeClass {
   hipGraphExec_t graph = nullptr;
   bool use_graph = false;               // small grids: replay a chunk graph over all slots
   bool onchip = false;                  // square 2D grid held in LDS, steps looped in-kernel
+  bool paced = false;                   // beside the main stream, paced to its round
   hipStream_t strm = nullptr;           // stream of the class's launches and table writes
   int *d_map = nullptr;                 // large grids: rows for the owned slots only
   int rows = 0;
@@ -133,9 +137,12 @@ struct gpe_server {
   hipStream_t stream = nullptr;  // batched steps and slot-table writes
   hipStream_t aux = nullptr;     // uploads, final scaling, observables, downloads
   hipStream_t side = nullptr;    // on-chip classes (beside the main stream)
-  hipEvent_t done[2] = {nullptr, nullptr};       // end of a round's main-stream work
-  hipEvent_t done_side[2] = {nullptr, nullptr};  // end of a round's side-stream work
+  hipStream_t heavy = nullptr;   // heavy-tier classes (beside the main stream)
+  hipEvent_t done[2] = {nullptr, nullptr};        // end of a round's main-stream work
+  hipEvent_t done_side[2] = {nullptr, nullptr};   // end of a round's side-stream work
+  hipEvent_t done_heavy[2] = {nullptr, nullptr};  // end of a round's heavy-stream work
   bool used_main[2] = {false, false}, used_side[2] = {false, false};
+  bool used_heavy[2] = {false, false};
   double main_round_ms = 0;      // GPU time of the main stream's last retired round
   hipEvent_t ev_up = nullptr;
   int device = 0;
@@ -144,6 +151,11 @@ struct gpe_server {
   int max_slots = 1, max_active = 0, chunk = 16;
   bool use_graph = true;
   bool use_onchip = true;
+  // Largest edge routed to the on-chip class.  One workgroup holds a whole
+  // grid, so its step time grows with the grid on one CU: a lone 128^2 FP32
+  // request took 48 us per step there against 12 us in the streaming
+  // batched passes, while 64^2 grids run as fast or faster on chip.
+  int onchip_max_n = 64;
   double quantum_ms = 1.0;  // GPU time per running request per round
   // Heavy tier: requests of at least heavy_sites points run first come,
   // first served, at most heavy_active at once, beside the lighter ones.
@@ -155,6 +167,10 @@ struct gpe_server {
   // the heavy tier keeps that fraction of each round (0: no such floor).
   double heavy_weight = 1.0;
   double heavy_share = 0.0;
+  // Heavy classes run on a stream of their own, concurrently with the
+  // lighter classes of the round and paced to last as long as the main
+  // stream's round (else they take their quanta on the main stream).
+  bool heavy_beside = true;
   std::mutex mu;
   std::condition_variable cv_work, cv_done;
   std::deque<uint64_t> queue;
@@ -185,6 +201,7 @@ long long sites_of(const gpe_desc &d) {
 void destroy_class(gpe_server *s, ShapeClass *c) {
   (void)hipStreamSynchronize(s->stream);
   (void)hipStreamSynchronize(s->side);
+  (void)hipStreamSynchronize(s->heavy);
   (void)hipStreamSynchronize(s->aux);
   if (c->graph) (void)hipGraphExecDestroy(c->graph);
   for (gpe_ctx *x : c->ctx)
@@ -265,7 +282,7 @@ int steps_for(gpe_server *s, ShapeClass *c) {
   in.step_ms = c->step_ms;
   in.step_running = c->step_running;
   in.use_graph = c->use_graph;
-  in.onchip = c->onchip;
+  in.onchip = c->paced;
   in.chunk = s->chunk;
   in.quantum_ms = s->quantum_ms;
   if (gpe_sched::is_heavy(c->proto->sites, s->heavy_sites)) {
@@ -374,9 +391,11 @@ gpe_status create_class(gpe_server *s, const gpe_request &r, ShapeClass **out) {
   // negligible for small grids (where launch latency dominates) and not for
   // large ones.
   c->onchip = s->use_onchip && p->dim == 2 && p->n3[1] == p->n3[2] &&
-              gpe::onchip_supported(p->prec, p->n3[2]);
+              p->n3[2] <= s->onchip_max_n && gpe::onchip_supported(p->prec, p->n3[2]);
   c->use_graph = !c->onchip && s->use_graph && p->sites * c->S <= (1LL << 22);
-  c->strm = c->onchip ? s->side : s->stream;
+  const bool heavy_beside = s->heavy_beside && gpe_sched::is_heavy(p->sites, s->heavy_sites);
+  c->paced = c->onchip || heavy_beside;
+  c->strm = c->onchip ? s->side : heavy_beside ? s->heavy : s->stream;
   c->owner.assign(c->S, 0);
   c->sstate.assign(c->S, SS_FREE);
   c->steps_total.assign(c->S, 0);
@@ -563,7 +582,7 @@ void retire(gpe_server *s, long long q, long long now) {
         hipEventElapsedTime(&ms, c->ev0[par], c->ev1[par]) == hipSuccess && ms > 0) {
       c->step_ms = ms / c->timed_steps[par];
       c->step_running = c->timed_running[par];
-      if (!c->onchip) main_ms += ms;
+      if (c->strm == s->stream) main_ms += ms;
     }
     for (int i = 0; i < c->S; ++i) {
       if (!c->owner[i]) continue;
@@ -665,12 +684,13 @@ void scheduler(gpe_server *s) {
     admit_queued(s, round);
     const int par = (int)(round & 1);
     bool any = false;
-    s->used_main[par] = s->used_side[par] = false;
+    s->used_main[par] = s->used_side[par] = s->used_heavy[par] = false;
     for (ShapeClass *c : s->classes) {
       c->hp_valid[par] = false;
       if (!c->owned) continue;
       any = true;
-      (c->onchip ? s->used_side : s->used_main)[par] = true;
+      (c->strm == s->side ? s->used_side : c->strm == s->heavy ? s->used_heavy : s->used_main)[par] =
+          true;
       const int steps = steps_for(s, c);
       (void)hipEventRecord(c->ev0[par], c->strm);
       c->failed[par] = run_chunk(s, c, steps) != GPE_OK;
@@ -683,9 +703,11 @@ void scheduler(gpe_server *s) {
     }
     if (s->used_main[par]) (void)hipEventRecord(s->done[par], s->stream);
     if (s->used_side[par]) (void)hipEventRecord(s->done_side[par], s->side);
+    if (s->used_heavy[par]) (void)hipEventRecord(s->done_heavy[par], s->heavy);
     if (pending) {
       if (s->used_main[par ^ 1]) (void)hipEventSynchronize(s->done[par ^ 1]);
       if (s->used_side[par ^ 1]) (void)hipEventSynchronize(s->done_side[par ^ 1]);
+      if (s->used_heavy[par ^ 1]) (void)hipEventSynchronize(s->done_heavy[par ^ 1]);
       retire(s, round - 1, round);
     }
     pending = any;
@@ -701,6 +723,7 @@ void scheduler(gpe_server *s) {
   // Shutting down: let the GPU finish, then cancel whatever is still held.
   (void)hipStreamSynchronize(s->stream);
   (void)hipStreamSynchronize(s->side);
+  (void)hipStreamSynchronize(s->heavy);
   (void)hipStreamSynchronize(s->aux);
   for (ShapeClass *c : s->classes)
     for (int i = 0; i < c->S; ++i)
@@ -715,12 +738,15 @@ void scheduler(gpe_server *s) {
 void release_server(gpe_server *s) {
   if (s->stream) (void)hipStreamSynchronize(s->stream);
   if (s->side) (void)hipStreamSynchronize(s->side);
+  if (s->heavy) (void)hipStreamSynchronize(s->heavy);
   if (s->aux) (void)hipStreamSynchronize(s->aux);
   for (ShapeClass *c : s->classes) destroy_class(s, c);
   s->classes.clear();
-  for (hipEvent_t e : {s->done[0], s->done[1], s->done_side[0], s->done_side[1], s->ev_up})
+  for (hipEvent_t e : {s->done[0], s->done[1], s->done_side[0], s->done_side[1],
+                       s->done_heavy[0], s->done_heavy[1], s->ev_up})
     if (e) (void)hipEventDestroy(e);
   if (s->aux) (void)hipStreamDestroy(s->aux);
+  if (s->heavy) (void)hipStreamDestroy(s->heavy);
   if (s->side) (void)hipStreamDestroy(s->side);
   if (s->stream) (void)hipStreamDestroy(s->stream);
   delete s;
@@ -740,8 +766,11 @@ gpe_status gpe_server_create(uint64_t hbm_budget_bytes, int32_t max_slots, int32
       hipStreamCreateWithFlags(&s->stream, hipStreamNonBlocking) != hipSuccess ||
       hipStreamCreateWithFlags(&s->aux, hipStreamNonBlocking) != hipSuccess ||
       hipStreamCreateWithFlags(&s->side, hipStreamNonBlocking) != hipSuccess ||
+      hipStreamCreateWithFlags(&s->heavy, hipStreamNonBlocking) != hipSuccess ||
       hipEventCreateWithFlags(&s->done_side[0], hipEventDisableTiming) != hipSuccess ||
       hipEventCreateWithFlags(&s->done_side[1], hipEventDisableTiming) != hipSuccess ||
+      hipEventCreateWithFlags(&s->done_heavy[0], hipEventDisableTiming) != hipSuccess ||
+      hipEventCreateWithFlags(&s->done_heavy[1], hipEventDisableTiming) != hipSuccess ||
       hipEventCreateWithFlags(&s->done[0], hipEventDisableTiming) != hipSuccess ||
       hipEventCreateWithFlags(&s->done[1], hipEventDisableTiming) != hipSuccess ||
       hipEventCreateWithFlags(&s->ev_up, hipEventDisableTiming) != hipSuccess) {
@@ -758,6 +787,10 @@ gpe_status gpe_server_create(uint64_t hbm_budget_bytes, int32_t max_slots, int32
   // GPU time per running request per round.
   if (const char *g = std::getenv("GPE_SERVER_GRAPH")) s->use_graph = std::atoi(g) != 0;
   if (const char *o = std::getenv("GPE_SERVER_ONCHIP")) s->use_onchip = std::atoi(o) != 0;
+  if (const char *o = std::getenv("GPE_SERVER_ONCHIP_MAX_N")) {
+    const int v = std::atoi(o);
+    if (v > 0) s->onchip_max_n = v;
+  }
   if (const char *q = std::getenv("GPE_SERVER_QUANTUM_MS")) {
     const double v = std::atof(q);
     if (v > 0) s->quantum_ms = v;
@@ -772,6 +805,7 @@ gpe_status gpe_server_create(uint64_t hbm_budget_bytes, int32_t max_slots, int32
     const double v = std::atof(h);
     if (v >= 0 && v < 1) s->heavy_share = v;
   }
+  if (const char *h = std::getenv("GPE_SERVER_HEAVY_BESIDE")) s->heavy_beside = std::atoi(h) != 0;
   s->t0 = std::chrono::steady_clock::now();
   s->th = std::thread(scheduler, s);
   *out = s;

@@ -47,6 +47,8 @@ def single(req):
 
 def serve(reqs, onchip=True, chunk=8, timeout=120):
     os.environ["GPE_SERVER_ONCHIP"] = "1" if onchip else "0"
+    # every edge the kernel holds (the server's default routes up to 64 there)
+    os.environ["GPE_SERVER_ONCHIP_MAX_N"] = "128"
     try:
         with gpe.Server(max_slots=8, chunk_steps=chunk) as srv:
             ids = [srv.submit(**r) for r in reqs]
@@ -56,6 +58,7 @@ def serve(reqs, onchip=True, chunk=8, timeout=120):
             return [srv.poll(i) for i in ids]
     finally:
         os.environ.pop("GPE_SERVER_ONCHIP", None)
+        os.environ.pop("GPE_SERVER_ONCHIP_MAX_N", None)
 
 
 CASES = [(8, "fp64"), (16, "fp64"), (32, "fp64"), (64, "fp64"),
