@@ -153,6 +153,26 @@ def test_heavy_requests_are_first_come_first_served():
     assert rl["t_done"] < r2["t_start"] + 1e-3
 
 
+def test_heavy_stream_is_bitwise_neutral(monkeypatch):
+    """A heavy request on the stream of its own (concurrent with the lighter
+    classes) gives the same bits as when it takes its quanta on the main
+    stream, and so do the lighter requests beside it."""
+    reqs = [make_req(60, (256, 256, 128), "imag", nsteps=40),
+            make_req(61, (128, 128), "real", nsteps=200),
+            make_req(62, (64, 64, 64), "imag", "fp32s", nsteps=150),
+            make_req(63, (64, 64), "real", "fp32", nsteps=300)]
+    out = {}
+    for beside in ("1", "0"):
+        monkeypatch.setenv("GPE_SERVER_HEAVY_BESIDE", beside)
+        say("heavy beside", beside)
+        with gpe.Server(max_slots=4, chunk_steps=8) as srv:
+            out[beside] = run_all(srv, reqs, timeout=300)
+    for r, a, b in zip(reqs, out["1"], out["0"]):
+        assert a["status"] == b["status"] == gpe.GPE_OK
+        assert np.array_equal(a["psi"], b["psi"]), r["shape"]
+        assert a["obs"]["energy"] == b["obs"]["energy"]
+
+
 def test_result_is_identical_alone_and_in_the_mix():
     reqs = mix()
     probe = [reqs[1], reqs[4], reqs[3]]
