@@ -30,16 +30,52 @@ __device__ __forceinline__ int mode_of(int i, int n) { return i < (n + 1) / 2 ? 
 
 __device__ __forceinline__ int log2_of(int n) { return 31 - __clz(n); }
 
-// Inclusive sum of x over the run of equal keys that ends at this lane (runs
-// of a key are contiguous in lane order): a segmented Hillis-Steele scan.
-__device__ __forceinline__ double run_sum(double x, int key, int lane) {
+// Lane moves of the wavefront scan (DPP: register reads across lanes, no
+// LDS): row_shr:d takes lane i - d within a row of 16 lanes, row_bcast:15
+// gives lane 15 of each row to the next row (written into rows 1 and 3),
+// row_bcast:31 gives lane 31 to rows 2 and 3.  A lane without a source (or
+// outside the rows written) gets `old`.
+template <int CTRL, int ROWS>
+__device__ __forceinline__ int dpp_move(int v, int old) {
+  return __builtin_amdgcn_update_dpp(old, v, CTRL, ROWS, 0xf, false);
+}
+template <int CTRL, int ROWS>
+__device__ __forceinline__ double dpp_move(double v) {
+  const long long b = __double_as_longlong(v);
+  const unsigned lo = (unsigned)dpp_move<CTRL, ROWS>((int)b, 0);
+  const int hi = dpp_move<CTRL, ROWS>((int)(b >> 32), 0);
+  return __longlong_as_double((long long)(((unsigned long long)(unsigned)hi << 32) | lo));
+}
+
+// One step of the segmented scan: add the moved partial sums whose key (the
+// run they belong to) equals this lane's.  A lane with no source gets key -2,
+// which no lane carries.
+template <int NV, int CTRL, int ROWS>
+__device__ __forceinline__ void scan_step(double (&x)[NV], int key) {
+  const int ky = dpp_move<CTRL, ROWS>(key, -2);
+  double y[NV];
 #pragma unroll
-  for (int d = 1; d < 64; d *= 2) {
-    const double y = __shfl_up(x, d, 64);
-    const int ky = __shfl_up(key, d, 64);
-    if (lane >= d && ky == key) x += y;
-  }
-  return x;
+  for (int v = 0; v < NV; ++v) y[v] = dpp_move<CTRL, ROWS>(x[v]);
+  if (ky == key)
+#pragma unroll
+    for (int v = 0; v < NV; ++v) x[v] += y[v];
+}
+
+// Inclusive sums of x over the run of equal keys that ends at this lane (runs
+// of a key are contiguous in lane order): a segmented scan, first within
+// rows of 16 lanes (shifts by 1, 2, 4, 8), then across rows (lane 15 into
+// the next row, lane 31 into the upper half).  After a step a lane holds the
+// sum over its run within a window ending at the lane; since a run is
+// contiguous, a partial sum with the same key belongs to the lane's run.
+// Every lane must be active; the order of the additions is fixed.
+template <int NV>
+__device__ __forceinline__ void run_sums(double (&x)[NV], int key) {
+  scan_step<NV, 0x111, 0xf>(x, key);
+  scan_step<NV, 0x112, 0xf>(x, key);
+  scan_step<NV, 0x114, 0xf>(x, key);
+  scan_step<NV, 0x118, 0xf>(x, key);
+  scan_step<NV, 0x142, 0xa>(x, key);
+  scan_step<NV, 0x143, 0xc>(x, key);
 }
 
 // Site geometry: indices, wavevector, shell and run key (see shell_kernel).
@@ -51,7 +87,7 @@ struct ShellSite {
 };
 
 template <int KIND>
-__device__ __forceinline__ ShellSite shell_site(const ShellArgs &a, long long s, long long sites,
+__device__ __forceinline__ ShellSite shell_site(const ShellArgs &a, long long s, bool valid,
                                                 int l1, int l2) {
   const int n0 = a.n[0], n1 = a.n[1], n2 = a.n[2];
   ShellSite q;
@@ -63,9 +99,10 @@ __device__ __forceinline__ ShellSite shell_site(const ShellArgs &a, long long s,
   // those at i when the mirror's wavevector is -k (u and w are transforms
   // of real fields); that fails only on a Nyquist index (n/2 is its own
   // mirror with the same k) of a used axis.  Such pairs count once from the
-  // half i2 <= n2/2, twice for 0 < i2 < n2/2; other sites count once.
+  // half i2 <= n2/2, twice for 0 < i2 < n2/2; other sites count once (the
+  // index ranges of kind 1 visit exactly these sites, see shell_range).
   q.pairs = (2 * i0 != n0 || a.kscale[0] == 0) && (2 * i1 != n1 || a.kscale[1] == 0);
-  q.on = s < sites && !(KIND != 0 && q.pairs && 2 * q.i2 > n2);
+  q.on = valid;
   const int m0 = mode_of(i0, n0), m1 = mode_of(i1, n1), m2 = mode_of(q.i2, n2);
   q.k[0] = a.kscale[0] * m0;
   q.k[1] = a.kscale[1] * m1;
@@ -109,39 +146,86 @@ __device__ __forceinline__ void add_run(double *h, int bin, double v, bool last,
   }
 }
 
+// Index ranges of a shell launch.  Kind 0 visits every site (RANGE_ALL).
+// Kind 1 counts each pair of wavevectors k, -k once: RANGE_HALF visits the
+// lower half-row i2 < n2/2 of every row (index e: row e / (n2/2), i2 =
+// e mod (n2/2)); RANGE_EXTRA then visits the column i2 = n2/2 of every row,
+// and the upper half-row of each row with a Nyquist index on a used axis
+// (such a row is its own mirror, so all of its sites count).
+enum { RANGE_ALL = 0, RANGE_HALF = 1, RANGE_EXTRA = 2 };
+
+// Rows with a Nyquist index on a used axis: i0 = n0/2 (n1 rows), then
+// i1 = n1/2 (n0 rows, less the one already listed).
+__device__ __forceinline__ long long nyquist_rows(const ShellArgs &a) {
+  const bool u0 = a.kscale[0] != 0, u1 = a.kscale[1] != 0;
+  return (u0 ? a.n[1] : 0) + (u1 ? a.n[0] : 0) - (u0 && u1 ? 1 : 0);
+}
+
+__device__ __forceinline__ long long range_count(const ShellArgs &a, int range) {
+  const long long rows = (long long)a.n[0] * a.n[1];
+  if (range == RANGE_ALL) return rows * a.n[2];
+  if (range == RANGE_HALF) return rows * (a.n[2] / 2);
+  return rows + nyquist_rows(a) * (a.n[2] / 2 - 1);
+}
+
+template <int RANGE>
+__device__ __forceinline__ long long site_of(const ShellArgs &a, long long e, int l2) {
+  if constexpr (RANGE == RANGE_ALL) {
+    return e;
+  } else if constexpr (RANGE == RANGE_HALF) {
+    const int h2 = l2 - 1;
+    return ((e >> h2) << l2) | (e & ((1LL << h2) - 1));
+  } else {
+    const int n0 = a.n[0], n1 = a.n[1], n2 = a.n[2];
+    const long long rows = (long long)n0 * n1;
+    if (e < rows) return (e << l2) | (n2 / 2);
+    e -= rows;
+    const long long per = n2 / 2 - 1;
+    const long long r = e / per;
+    const int t = (int)(e - r * per);
+    const bool u0 = a.kscale[0] != 0;
+    int i0, i1;
+    if (u0 && r < n1) {
+      i0 = n0 / 2;
+      i1 = (int)r;
+    } else {
+      const int r2 = (int)(r - (u0 ? n1 : 0));
+      i1 = n1 / 2;
+      i0 = (u0 && r2 >= n0 / 2) ? r2 + 1 : r2;
+    }
+    return (((long long)i0 * n1 + i1) << l2) | (n2 / 2 + 1 + t);
+  }
+}
+
 // Every lane of a wavefront runs the same number of iterations (the shuffles
-// need them all); a lane past the end or with nothing to add carries key -1.
-// Within a wavefront the sites are consecutive: within one row (fixed i0, i1)
-// and one half of the last axis the shell index is monotone in i2, so equal
-// bins form contiguous runs keyed by (row, half, bin); each run is summed
-// across lanes in fixed order and added to the wavefront's histogram by its
-// last lane.  Each iteration takes U blocks of sites and issues all their
-// loads before any arithmetic.
-template <typename T, int KIND, int U>
-__global__ void __launch_bounds__(kShellThreads) shell_kernel(const ShellArgs a) {
-  // one histogram (kind 0) or three (kind 1: compressible, incompressible,
-  // quantum pressure) of nbins per wavefront
-  constexpr int NH = KIND == 0 ? 1 : 3;
-  extern __shared__ double hist[];
-  const int nb = a.nbins, nw = blockDim.x >> 6;
-  for (int i = threadIdx.x; i < nw * NH * nb; i += blockDim.x) hist[i] = 0;
-  __syncthreads();
-  double *h = hist + (threadIdx.x >> 6) * NH * nb;
-  const bool rows_apart = a.n[2] < 128;
-  const int l1 = log2_of(a.n[1]), l2 = log2_of(a.n[2]), n2 = a.n[2];
-  const long long sites = (long long)a.n[0] * a.n[1] * a.n[2];
-  const int lane = threadIdx.x & 63;
+// need them all); a lane past the end of the range carries key -1.  Within a
+// wavefront the sites are consecutive indices of the range: for RANGE_ALL
+// and RANGE_HALF, within one row (fixed i0, i1) and one half of the last
+// axis the shell index is monotone in i2, so equal bins form contiguous runs
+// keyed by (row, half, bin); each run is summed across lanes in fixed order
+// and added to the wavefront's histogram by its last lane.  The few sites of
+// RANGE_EXTRA lie in different rows, and their last lanes add one at a time.
+// Each iteration takes U blocks of sites and issues all their loads before
+// any arithmetic.
+template <typename T, int KIND, int U, int RANGE>
+__device__ __forceinline__ void shell_range(const ShellArgs &a, double *h, bool rows_apart,
+                                            int l1, int l2, int lane) {
   constexpr int NF = KIND == 0 ? 1 : 3;
+  const int nb = a.nbins, n2 = a.n[2];
+  const long long count = range_count(a, RANGE);
   const cxs<T> *fs[3] = {static_cast<const cxs<T> *>(a.f[0]),
                          static_cast<const cxs<T> *>(a.f[1]),
                          static_cast<const cxs<T> *>(a.f[2])};
   const long long step = (long long)gridDim.x * blockDim.x * U;
-  for (long long s0 = (long long)blockIdx.x * blockDim.x * U; s0 < sites; s0 += step) {
+  for (long long e0 = (long long)blockIdx.x * blockDim.x * U; e0 < count; e0 += step) {
     ShellSite q[U];
     cxs<T> zp[U][NF], zm[U][NF];
 #pragma unroll
-    for (int u = 0; u < U; ++u)
-      q[u] = shell_site<KIND>(a, s0 + (long long)u * blockDim.x + threadIdx.x, sites, l1, l2);
+    for (int u = 0; u < U; ++u) {
+      const long long e = e0 + (long long)u * blockDim.x + threadIdx.x;
+      const bool valid = e < count;
+      q[u] = shell_site<KIND>(a, valid ? site_of<RANGE>(a, e, l2) : 0, valid, l1, l2);
+    }
     // Every lane loads (a lane with nothing to add reads element 0) and the
     // values are zeroed afterwards: loads under per-lane branches end up in
     // blocks of their own, each waiting for its data before the next load
@@ -173,8 +257,9 @@ __global__ void __launch_bounds__(kShellThreads) shell_kernel(const ShellArgs a)
       const int key_next = __shfl_down(q[u].key, 1, 64);
       const bool last = q[u].on && (lane == 63 || key_next != q[u].key);
       if constexpr (KIND == 0) {
-        const double e = run_sum(en[u], q[u].key, lane);
-        add_run(h, q[u].bin, e, last, rows_apart, lane);
+        double e[1] = {en[u]};
+        run_sums(e, q[u].key);
+        add_run(h, q[u].bin, e[0], last, rows_apart, lane);
       } else {
         double csum = 0, isum = 0, qsum = 0;
         if (q[u].on) {
@@ -207,14 +292,34 @@ __global__ void __launch_bounds__(kShellThreads) shell_kernel(const ShellArgs a)
           isum *= wgt;
           qsum *= wgt;
         }
-        csum = run_sum(csum, q[u].key, lane);
-        isum = run_sum(isum, q[u].key, lane);
-        qsum = run_sum(qsum, q[u].key, lane);
-        add_run(h, q[u].bin, csum, last, rows_apart, lane);
-        add_run(h + nb, q[u].bin, isum, last, rows_apart, lane);
-        add_run(h + 2 * nb, q[u].bin, qsum, last, rows_apart, lane);
+        double sums[3] = {csum, isum, qsum};
+        run_sums(sums, q[u].key);
+        add_run(h, q[u].bin, sums[0], last, rows_apart, lane);
+        add_run(h + nb, q[u].bin, sums[1], last, rows_apart, lane);
+        add_run(h + 2 * nb, q[u].bin, sums[2], last, rows_apart, lane);
       }
     }
+  }
+}
+
+template <typename T, int KIND, int U>
+__global__ void __launch_bounds__(kShellThreads) shell_kernel(const ShellArgs a) {
+  // one histogram (kind 0) or three (kind 1: compressible, incompressible,
+  // quantum pressure) of nbins per wavefront
+  constexpr int NH = KIND == 0 ? 1 : 3;
+  extern __shared__ double hist[];
+  const int nb = a.nbins, nw = blockDim.x >> 6;
+  for (int i = threadIdx.x; i < nw * NH * nb; i += blockDim.x) hist[i] = 0;
+  __syncthreads();
+  double *h = hist + (threadIdx.x >> 6) * NH * nb;
+  const int l1 = log2_of(a.n[1]), l2 = log2_of(a.n[2]);
+  const int lane = threadIdx.x & 63;
+  if constexpr (KIND == 0) {
+    shell_range<T, 0, U, RANGE_ALL>(a, h, a.n[2] < 128, l1, l2, lane);
+  } else {
+    // a wavefront's 64 half-row indices share one half-row when n2/2 >= 64
+    shell_range<T, 1, U, RANGE_HALF>(a, h, a.n[2] < 128, l1, l2, lane);
+    shell_range<T, 1, 1, RANGE_EXTRA>(a, h, true, l1, l2, lane);
   }
   __syncthreads();
   // row of this workgroup: N(n) in [0, nb), the energies in [nb, 4 nb)
