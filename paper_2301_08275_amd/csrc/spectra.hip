@@ -92,8 +92,10 @@ __device__ __forceinline__ ShellSite shell_site(const ShellArgs &a, long long s,
   const int n0 = a.n[0], n1 = a.n[1], n2 = a.n[2];
   ShellSite q;
   q.s = s;
-  q.i2 = (int)(s & (n2 - 1));
-  const long long r = s >> l2;
+  // (grids hold at most 2^30 sites: the index fits 32 bits)
+  const unsigned su = (unsigned)s;
+  q.i2 = (int)(su & (n2 - 1));
+  const unsigned r = su >> l2;
   const int i1 = (int)(r & (n1 - 1)), i0 = (int)(r >> l1);
   // Kind 1: the decomposed energies at the mirror site (index -i) equal
   // those at i when the mirror's wavevector is -k (u and w are transforms
@@ -110,18 +112,21 @@ __device__ __forceinline__ ShellSite shell_site(const ShellArgs &a, long long s,
   q.kk = q.k[0] * q.k[0] + q.k[1] * q.k[1] + q.k[2] * q.k[2];
   int bin;
   if (a.integer_shells) {
-    const long long M = (long long)m0 * m0 + (long long)m1 * m1 + (long long)m2 * m2;
-    long long t = (long long)sqrt((double)M);
+    // shell t: (2t - 1)^2 <= 4 M < (2t + 1)^2, settled in integers from an
+    // FP32 root (|m_j| <= 512, so M < 2^20 and 4 M and the squares fit in
+    // 32 bits; the root is off by at most one)
+    const int M = m0 * m0 + m1 * m1 + m2 * m2;
+    int t = (int)sqrtf((float)M);
     while ((2 * t + 1) * (2 * t + 1) <= 4 * M) ++t;
     while (t > 0 && 4 * M < (2 * t - 1) * (2 * t - 1)) --t;
-    bin = (int)t;
+    bin = t;
   } else {
     bin = (int)floor(sqrt(q.kk) / a.dk + 0.5);
   }
   q.bin = bin < a.nbins ? bin : a.nbins - 1;  // the clamp is unreachable for the shell count used
   q.key = q.on ? (int)(((r & 0x3fff) << 13) | ((2 * q.i2 >= n2) ? 1 << 12 : 0) | q.bin) : -1;
-  q.ms = ((((long long)((n0 - i0) & (n0 - 1)) * n1 + ((n1 - i1) & (n1 - 1))) * n2) +
-          ((n2 - q.i2) & (n2 - 1)));
+  q.ms = (long long)(((((unsigned)((n0 - i0) & (n0 - 1)) * n1 + ((n1 - i1) & (n1 - 1))) << l2) |
+                      ((n2 - q.i2) & (n2 - 1))));
   return q;
 }
 
