@@ -112,14 +112,16 @@ __device__ __forceinline__ ShellSite shell_site(const ShellArgs &a, long long s,
   q.kk = q.k[0] * q.k[0] + q.k[1] * q.k[1] + q.k[2] * q.k[2];
   int bin;
   if (a.integer_shells) {
-    // shell t: (2t - 1)^2 <= 4 M < (2t + 1)^2, settled in integers from an
-    // FP32 root (|m_j| <= 512, so M < 2^20 and 4 M and the squares fit in
-    // 32 bits; the root is off by at most one)
+    // shell t: (2t - 1)^2 <= 4 M < (2t + 1)^2, i.e. t = floor(sqrt(M) + 1/2),
+    // settled in integers without branches (|m_j| <= 512, so M < 2^20 and
+    // 4 M and the squares fit in 32 bits): r = floor(sqrt(M)) from an FP32
+    // root (off by at most one; checked both ways), then t = r + 1 exactly
+    // when 4 M > (2r + 1)^2 (they cannot be equal: one is even, one odd)
     const int M = m0 * m0 + m1 * m1 + m2 * m2;
-    int t = (int)sqrtf((float)M);
-    while ((2 * t + 1) * (2 * t + 1) <= 4 * M) ++t;
-    while (t > 0 && 4 * M < (2 * t - 1) * (2 * t - 1)) --t;
-    bin = t;
+    int r = (int)sqrtf((float)M);
+    r -= r * r > M ? 1 : 0;
+    r += (r + 1) * (r + 1) <= M ? 1 : 0;
+    bin = r + ((2 * r + 1) * (2 * r + 1) < 4 * M ? 1 : 0);
   } else {
     bin = (int)floor(sqrt(q.kk) / a.dk + 0.5);
   }
