@@ -855,7 +855,8 @@ axis_pass_kernel(const PassArgs a) {
             const double qr = q.x, qi = q.y, dr = u.x, di = u.y;
             const double mag = sqrt(qr * qr + qi * qi);
             const double zr = qr * dr + qi * di, zi = qr * di - qi * dr;  // conj(q) d
-            u = mag > 0 ? cx<T>{(T)(zi / mag), (T)(zr / mag)} : cx<T>{0, 0};
+            const double inv = mag > 0 ? 1.0 / mag : 0.0;  // one division per site
+            u = cx<T>{(T)(zi * inv), (T)(zr * inv)};
           } else if (post != PH_NONE) {
             const int k0 = axis == 0 ? p : j0, k1 = axis == 1 ? p : j1, k2 = axis == 2 ? p : j2;
             const double V =
