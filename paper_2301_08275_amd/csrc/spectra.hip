@@ -283,8 +283,9 @@ __device__ __forceinline__ void shell_range(const ShellArgs &a, double *h, bool 
           }
           const double *kv = q[u].k, kk = q[u].kk;
           if (kk > 0) {
-            const double pr = (kv[0] * ur[0] + kv[1] * ur[1] + kv[2] * ur[2]) / kk;
-            const double pi = (kv[0] * ui[0] + kv[1] * ui[1] + kv[2] * ui[2]) / kk;
+            const double ikk = 1.0 / kk;  // one division per site
+            const double pr = (kv[0] * ur[0] + kv[1] * ur[1] + kv[2] * ur[2]) * ikk;
+            const double pi = (kv[0] * ui[0] + kv[1] * ui[1] + kv[2] * ui[2]) * ikk;
 #pragma unroll
             for (int j = 0; j < 3; ++j) {
               const double cr = kv[j] * pr, ci = kv[j] * pi;
