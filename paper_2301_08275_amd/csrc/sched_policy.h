@@ -56,23 +56,24 @@ struct ChunkInput {
   double step_ms;          // measured GPU ms per batched step (<= 0: unknown)
   int step_running;        // running slots when step_ms was measured
   bool use_graph;          // chunks are whole replays of a chunk_steps graph
-  bool onchip;             // the class runs beside the main stream
+  bool paced;              // the class runs beside the main stream (on-chip or heavy)
   int chunk;               // steps per graph replay
   double quantum_ms;       // GPU time per running request per round
-  double main_round_ms;    // the main stream's last round (on-chip pacing)
+  double main_round_ms;    // the main stream's last round (pacing)
   double sites, esize;     // grid points and bytes per point of the class
 };
 
 // Steps for a class in one round: about quantum_ms of GPU time per running
 // request.  Large grids are bandwidth-bound (a step's time grows with the
 // running slots); small ones are launch-bound (it does not), and run whole
-// graph replays.  On-chip classes run beside the main stream on a few CUs and
-// are paced to last about as long as the main stream's last round.  An
+// graph replays.  Classes beside the main stream (on-chip classes on a few
+// CUs, heavy classes on a stream of their own) are paced to last about as
+// long as the main stream's last round.  An
 // unmeasured class assumes about 4 TB/s over three passes of reads and writes.
 inline int chunk_steps(const ChunkInput &in) {
   const int run = std::max(1, in.running);
   double ms = in.step_ms;
-  if (in.onchip) {
+  if (in.paced) {
     if (!(ms > 0)) return in.chunk;
     const double target = std::max(in.quantum_ms * run, in.main_round_ms);
     return (int)std::max(1LL, std::min(65536LL, std::llround(target / ms)));

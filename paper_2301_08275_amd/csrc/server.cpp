@@ -282,7 +282,7 @@ int steps_for(gpe_server *s, ShapeClass *c) {
   in.step_ms = c->step_ms;
   in.step_running = c->step_running;
   in.use_graph = c->use_graph;
-  in.onchip = c->paced;
+  in.paced = c->paced;
   in.chunk = s->chunk;
   in.quantum_ms = s->quantum_ms;
   if (gpe_sched::is_heavy(c->proto->sites, s->heavy_sites)) {

@@ -122,7 +122,7 @@ int main() {
   c.step_ms = 0.5;
   c.step_running = 4;
   c.use_graph = false;
-  c.onchip = false;
+  c.paced = false;
   c.chunk = 16;
   c.quantum_ms = 1.0;
   c.sites = 1 << 24;
@@ -139,7 +139,7 @@ int main() {
   c.step_ms = 0.01;
   c.step_running = 4;
   CHECK(chunk_steps(c) % 16 == 0 && chunk_steps(c) >= 16);
-  c.onchip = true;             // paced to the main stream's round
+  c.paced = true;              // paced to the main stream's round
   c.main_round_ms = 10.0;
   c.step_ms = 0.1;
   CHECK(chunk_steps(c) == 100);
