@@ -236,7 +236,10 @@ gpe_status gpe_ground_state(gpe_ctx *ctx, double dt, double tol,
 
 /* Observables of the current state (see gpe_obs) and, if spec is not NULL,
  * the shell spectra (see gpe_spectra).  Synchronous.  GPE_ENONFINITE if a sum
- * is not finite. */
+ * is not finite.  With spec, the observables come out of the same sweep as
+ * the spectra (E_kin from the full transform by Parseval's identity instead
+ * of per-axis transforms), so they can differ from a call without spec in
+ * the last bits. */
 gpe_status gpe_observables(gpe_ctx *ctx, gpe_obs *out, gpe_spectra *spec);
 
 /* Number of |k| shells for this context's grid. */

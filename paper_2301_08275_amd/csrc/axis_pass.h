@@ -598,6 +598,7 @@ enum PassMode : int {
   MODE_PRE_IMAG_EXACT = 11,       // MODE_PRE_IMAG with the exact substep
   MODE_POST_IMAG_RED_EXACT = 12,  // MODE_POST_IMAG_RED with the exact substep
   MODE_POST_REAL = 13,     // forward, table, inverse, closing real-time phase
+  MODE_FWD_REAL = 14,      // MODE_FWD plus the real-space sums of the input
 };
 
 // The step modes (MODE_PLAIN, MODE_PRE_REAL) also come with streaming
@@ -631,7 +632,7 @@ axis_pass_kernel(const PassArgs a) {
   constexpr bool G = MODE == MODE_GENERIC;
   constexpr bool SLI = MODE == MODE_SLOTS_IMAG;
   constexpr bool SL = MODE == MODE_SLOTS_REAL || SLI;
-  constexpr bool FWD = MODE == MODE_FWD, DER = MODE == MODE_DERIV;
+  constexpr bool FWD = MODE == MODE_FWD || MODE == MODE_FWD_REAL, DER = MODE == MODE_DERIV;
   constexpr bool OBS = MODE == MODE_OBS || MODE == MODE_OBS_REAL;
   const int forward = G ? a.forward : 1;
   const int inverse = G ? a.inverse : (FWD || OBS ? 0 : 1);
@@ -649,6 +650,7 @@ axis_pass_kernel(const PassArgs a) {
               : (POST_IM                    ? RED_NORM_OUT
                  : MODE == MODE_OBS         ? RED_KIN
                  : MODE == MODE_OBS_REAL    ? (RED_KIN | RED_REAL)
+                 : MODE == MODE_FWD_REAL    ? RED_REAL
                                             : RED_NONE);
   bool has_scale = G || OBS ? a.scale != nullptr : PRE_IM;
   // Per-block parameters: from the arguments, or (batched) from this block's slot.
@@ -1091,6 +1093,10 @@ void launch_mode(const PassArgs &a, int mode, dim3 grid, dim3 block, hipStream_t
       break;
     case MODE_OBS_REAL:
       hipLaunchKernelGGL((axis_pass_kernel<T, PL, W, STRIDED, MODE_OBS_REAL, SX>), grid, block, 0,
+                         s, a);
+      break;
+    case MODE_FWD_REAL:
+      hipLaunchKernelGGL((axis_pass_kernel<T, PL, W, STRIDED, MODE_FWD_REAL, SX>), grid, block, 0,
                          s, a);
       break;
     default:

@@ -49,8 +49,12 @@ int pick_mode(const PassArgs &a, const PassShape &sh) {
     return MODE_GENERIC;
   }
   const bool bare = !a.scale && a.pre == PH_NONE && a.red == RED_NONE;
-  if (!a.inverse)
-    return bare && a.mid == MID_NONE && a.post == PH_NONE && !a.refwd ? MODE_FWD : MODE_GENERIC;
+  if (!a.inverse) {
+    if (a.mid != MID_NONE || a.post != PH_NONE || a.refwd) return MODE_GENERIC;
+    if (bare) return MODE_FWD;
+    const bool real_sums = !a.scale && a.pre == PH_NONE && a.red == RED_REAL;
+    return real_sums ? MODE_FWD_REAL : MODE_GENERIC;
+  }
   if (a.mid != MID_TABLE) return MODE_GENERIC;
   if (a.refwd) return bare && a.post == PH_DERIV ? MODE_DERIV : MODE_GENERIC;
   if (a.pre == PH_NONE && a.post == PH_NONE && a.red == RED_NONE && !a.scale)

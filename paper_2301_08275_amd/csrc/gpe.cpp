@@ -479,7 +479,11 @@ int shell_count(const gpe_ctx *c) {
 
 // Forward transform along every axis, src -> dst (then in place on dst).
 // Forward transforms along every axis except view axis `skip` (-1: none).
-gpe_status forward_all(gpe_ctx *c, const void *src, void *dst, int skip = -1) {
+// Forward transform of src into dst along every axis but `skip`; with
+// real_sums, the first pass also takes the real-space sums of src
+// (finalized into real_sums, kRedSlots doubles).
+gpe_status forward_all(gpe_ctx *c, const void *src, void *dst, int skip = -1,
+                       double *real_sums = nullptr) {
   bool first = true;
   for (int i = 0; i < n_axes(c); ++i) {
     const int ax = order_axis(c, i);
@@ -488,15 +492,29 @@ gpe_status forward_all(gpe_ctx *c, const void *src, void *dst, int skip = -1) {
     a.src = first ? src : dst;
     a.dst = dst;
     a.inverse = 0;
+    if (first && real_sums) {
+      a.red = gpe::RED_REAL;
+      a.partial = c->partial;
+    }
     gpe_status st = launch_pass(c, a);
     if (st != GPE_OK) return st;
+    if (first && real_sums) {
+      const gpe::PassShape sh = gpe::launch_shape(c->prec, a);
+      HIPCHK(c, gpe::launch_finalize(a.partial, sh.blocks, real_sums, nullptr, 0, 1, c->stream,
+                                     c->fin), "finalize launch");
+    }
     first = false;
   }
   return GPE_OK;
 }
 
-// Shell spectra of the current state (see gpe_spectra).
-gpe_status compute_spectra(gpe_ctx *c, gpe_spectra *spec) {
+// Shell spectra of the current state (see gpe_spectra); with obs, also the
+// observables: the first pass of the transform behind N(n) takes the
+// real-space sums and the particle-number shell kernel sums
+// |k|^2 |psi_hat|^2 / N_tot per shell, which over all shells is the kinetic
+// sum by Parseval's identity on the whole grid, so the read-only observable
+// passes do not run.
+gpe_status compute_spectra(gpe_ctx *c, gpe_spectra *spec, gpe_obs *obs = nullptr) {
   const int nb = shell_count(c);
   if (spec->nbins != nb) return fail(c, GPE_EINVAL, "spec->nbins must equal gpe_spectra_bins()");
   for (int j = 0; j < c->dim; ++j) {
@@ -524,9 +542,14 @@ gpe_status compute_spectra(gpe_ctx *c, gpe_spectra *spec) {
   sa.integer_shells = equal_lengths(c) ? 1 : 0;
   sa.nbins = nb;
   sa.w = c->dV / (double)c->sites;
+  sa.wk = 1.0 / (double)c->sites;
   sa.partial = c->hist_partial;
+  if (obs) {
+    gpe_status vst = vtables_at(c, VAt{c->time, 1.0, 0.0, 0.0});  // E_pot at the clock
+    if (vst != GPE_OK) return vst;
+  }
   // particle-number spectrum from the transform of psi
-  gpe_status st = forward_all(c, c->psi, c->work[0]);
+  gpe_status st = forward_all(c, c->psi, c->work[0], -1, obs ? c->sums : nullptr);
   if (st != GPE_OK) return st;
   sa.kind = 0;
   sa.f[0] = c->work[0];
@@ -560,7 +583,18 @@ gpe_status compute_spectra(gpe_ctx *c, gpe_spectra *spec) {
   std::vector<double> h(8 * (size_t)nb);
   HIPCHK(c, hipMemcpyAsync(h.data(), c->hist, h.size() * sizeof(double), hipMemcpyDeviceToHost,
                            c->stream), "histogram download");
+  std::vector<double> sums(3 * gpe::kRedSlots, 0.0);
+  if (obs)
+    HIPCHK(c, hipMemcpyAsync(sums.data(), c->sums, gpe::kRedSlots * sizeof(double),
+                             hipMemcpyDeviceToHost, c->stream), "sums download");
   HIPCHK(c, hipStreamSynchronize(c->stream), "stream sync");
+  if (obs) {
+    double kin = 0;  // shells in order
+    for (int b = 0; b < nb; ++b) kin += h[nb + b];
+    sums[gpe::kSlotKin] = kin;
+    gpe_status ost = obs_from_sums(c, sums.data(), obs);
+    if (ost != GPE_OK) return ost;
+  }
   for (int b = 0; b < nb; ++b) {
     if (spec->n_k) spec->n_k[b] = h[b];
     if (spec->e_comp) spec->e_comp[b] = h[4 * nb + nb + b];
@@ -1155,9 +1189,8 @@ gpe_status gpe_ground_state(gpe_ctx *c, double dt, double tol, int32_t check_eve
 gpe_status gpe_observables(gpe_ctx *c, gpe_obs *out, gpe_spectra *spec) {
   if (!c) return GPE_EINVAL;
   if (!out) return fail(c, GPE_EINVAL, "out is NULL");
-  gpe_status st = compute_obs(c, nullptr, out);
-  if (st != GPE_OK || !spec) return st;
-  return compute_spectra(c, spec);
+  if (!spec) return compute_obs(c, nullptr, out);
+  return compute_spectra(c, spec, out);
 }
 
 int32_t gpe_spectra_bins(const gpe_ctx *c) {

@@ -165,6 +165,7 @@ struct ShellArgs {
   int integer_shells;  // equal box lengths: shells from the integer sum of m_j^2
   int nbins;
   double w;          // dV / N_tot
+  double wk;         // 1 / N_tot (kind 0: the |k|^2 |psi_hat|^2 sums)
   double *partial;   // [gridDim][4][nbins]
 };
 // Workgroups of a shell launch of this kind on the current device (at most

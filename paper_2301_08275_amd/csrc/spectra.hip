@@ -1,5 +1,7 @@
 // |k|-shell spectra: particle number, compressible and incompressible kinetic
-// energy, and the quantum-pressure part.
+// energy, and the quantum-pressure part.  The particle-number kernel also
+// sums |k|^2 |psi_hat|^2 per shell: over all shells, the kinetic energy by
+// Parseval's identity on the whole grid.
 //
 // The spectra of Z_j = u_j + i w_j (two real fields packed in one complex FFT)
 // are unpacked per wavenumber from Z_j(k) and Z_j(-k):
@@ -255,18 +257,24 @@ __device__ __forceinline__ void shell_range(const ShellArgs &a, double *h, bool 
 #pragma unroll
       for (int j = 0; j < NF; ++j)
         if (!q[u].on) zp[u][j] = zm[u][j] = cxs<T>{0, 0};
-    double en[U];  // kind 0: the weighted |Z|^2 of each site, formed once all loads are issued
+    // kind 0: the weighted |Z|^2 of each site and its |k|^2 multiple, formed
+    // once all loads are issued
+    double en[U], ek[U];
 #pragma unroll
-    for (int u = 0; u < U; ++u)
-      en[u] = a.w * ((double)zp[u][0].x * zp[u][0].x + (double)zp[u][0].y * zp[u][0].y);
+    for (int u = 0; u < U; ++u) {
+      const double z2 = (double)zp[u][0].x * zp[u][0].x + (double)zp[u][0].y * zp[u][0].y;
+      en[u] = a.w * z2;
+      ek[u] = a.wk * q[u].kk * z2;
+    }
 #pragma unroll
     for (int u = 0; u < U; ++u) {
       const int key_next = __shfl_down(q[u].key, 1, 64);
       const bool last = q[u].on && (lane == 63 || key_next != q[u].key);
       if constexpr (KIND == 0) {
-        double e[1] = {en[u]};
+        double e[2] = {en[u], ek[u]};
         run_sums(e, q[u].key);
         add_run(h, q[u].bin, e[0], last, rows_apart, lane);
+        add_run(h + nb, q[u].bin, e[1], last, rows_apart, lane);
       } else {
         double csum = 0, isum = 0, qsum = 0;
         if (q[u].on) {
@@ -312,9 +320,9 @@ __device__ __forceinline__ void shell_range(const ShellArgs &a, double *h, bool 
 
 template <typename T, int KIND, int U>
 __global__ void __launch_bounds__(kShellThreads) shell_kernel(const ShellArgs a) {
-  // one histogram (kind 0) or three (kind 1: compressible, incompressible,
-  // quantum pressure) of nbins per wavefront
-  constexpr int NH = KIND == 0 ? 1 : 3;
+  // two histograms (kind 0: particle number, |k|^2-weighted) or three (kind
+  // 1: compressible, incompressible, quantum pressure) of nbins per wavefront
+  constexpr int NH = KIND == 0 ? 2 : 3;
   extern __shared__ double hist[];
   const int nb = a.nbins, nw = blockDim.x >> 6;
   for (int i = threadIdx.x; i < nw * NH * nb; i += blockDim.x) hist[i] = 0;
@@ -330,7 +338,8 @@ __global__ void __launch_bounds__(kShellThreads) shell_kernel(const ShellArgs a)
     shell_range<T, 1, 1, RANGE_EXTRA>(a, h, true, l1, l2, lane);
   }
   __syncthreads();
-  // row of this workgroup: N(n) in [0, nb), the energies in [nb, 4 nb)
+  // row of this workgroup: kind 0 N(n) in [0, nb) and the |k|^2 sums in
+  // [nb, 2 nb); kind 1 the energies in [nb, 4 nb)
   double *out = a.partial + (long long)blockIdx.x * 4 * nb;
   for (int i = threadIdx.x; i < 4 * nb; i += blockDim.x) {
     const int j = KIND == 0 ? i : i - nb;  // index within the wavefront histograms
@@ -371,7 +380,7 @@ struct ShellShape {
   size_t lds;
 };
 ShellShape shell_shape(int kind, int nbins) {
-  const size_t per_wave = (kind == 0 ? 1 : 3) * (size_t)nbins * sizeof(double);
+  const size_t per_wave = (kind == 0 ? 2 : 3) * (size_t)nbins * sizeof(double);
   int waves = (int)((64 * 1024) / per_wave);
   if (waves > kShellThreads / 64) waves = kShellThreads / 64;
   return {waves, waves > 0 ? waves * per_wave : 0};
