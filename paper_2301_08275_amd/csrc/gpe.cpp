@@ -477,11 +477,9 @@ int shell_count(const gpe_ctx *c) {
   return (int)std::floor(std::sqrt(q) + 0.5) + 1;
 }
 
-// Forward transform along every axis, src -> dst (then in place on dst).
-// Forward transforms along every axis except view axis `skip` (-1: none).
-// Forward transform of src into dst along every axis but `skip`; with
-// real_sums, the first pass also takes the real-space sums of src
-// (finalized into real_sums, kRedSlots doubles).
+// Forward transform of src into dst (then in place on dst) along every axis
+// but view axis `skip` (-1: none); with real_sums, the first pass also takes
+// the real-space sums of src (finalized into real_sums, kRedSlots doubles).
 gpe_status forward_all(gpe_ctx *c, const void *src, void *dst, int skip = -1,
                        double *real_sums = nullptr) {
   bool first = true;
