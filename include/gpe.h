@@ -239,7 +239,8 @@ gpe_status gpe_ground_state(gpe_ctx *ctx, double dt, double tol,
  * is not finite.  With spec, the observables come out of the same sweep as
  * the spectra (E_kin from the full transform by Parseval's identity instead
  * of per-axis transforms), so they can differ from a call without spec in
- * the last bits. */
+ * the last bits (FP64), or by the FP32 rounding of the stored intermediate
+ * transform (FP32 storage: about 1e-9 relative in E_kin). */
 gpe_status gpe_observables(gpe_ctx *ctx, gpe_obs *out, gpe_spectra *spec);
 
 /* Number of |k| shells for this context's grid. */

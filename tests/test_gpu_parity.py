@@ -148,6 +148,36 @@ def test_observables_parity():
             assert abs(got[k] - ref[k]) <= 1e-12 * max(1.0, abs(ref[k])), (k, got[k], ref[k])
 
 
+@pytest.mark.parametrize("shape,lo,hi,prec", [
+    ((32, 64, 16), (-6.0, -7.0, -3.0), (6.0, 7.0, 3.0), "fp64"),   # unequal lengths
+    ((32, 32, 32), (-5.0,) * 3, (5.0,) * 3, "fp64"),                 # integer shells
+    ((64, 128), (-6.0, -8.0), (6.0, 8.0), "fp64"),
+    ((256,), (-10.0,), (10.0,), "fp64"),
+    ((32, 32, 32), (-5.0,) * 3, (5.0,) * 3, "fp32s"),
+])
+def test_observables_with_spectra_parity(shape, lo, hi, prec):
+    """Observables taken in the spectra sweep (real-space sums in the first
+    forward pass, E_kin from the shell kernel by Parseval's identity on the
+    whole grid) against the oracle and against a call without spectra."""
+    w = [1.0, 2.0, 4.0][:len(shape)]
+    V = I.harmonic(shape, lo, hi, w)
+    psi = I.noisy_gaussian(shape, lo, hi, seed=4, amp=0.2)
+    ref = oracle.observables(psi, lo, hi, V, 7.5)
+    say("observables with spectra", shape, prec)
+    with gpe.Context(shape, lo, hi, 7.5, harmonic=w, precision=prec) as ctx:
+        ctx.set_state(psi)
+        _, fused = ctx.spectra(with_obs=True)
+        alone = ctx.observables()
+    tol = 1e-12 if prec == "fp64" else 1e-6
+    # (with FP32 storage the full transform behind E_kin is stored in FP32
+    # after each axis, the per-axis passes of a call without spectra are not)
+    same = 1e-13 if prec == "fp64" else 1e-8
+    for k in gpe.OBS_KEYS:
+        scale = max(1.0, abs(ref[k]))
+        assert abs(fused[k] - ref[k]) <= tol * scale, (k, fused[k], ref[k])
+        assert abs(fused[k] - alone[k]) <= same * scale, (k, fused[k], alone[k])
+
+
 def test_imag_time_fixed_steps_parity():
     shape, lo, hi = (32, 64, 16), (-8.0, -8.0, -4.0), (8.0, 8.0, 4.0)
     V = I.harmonic(shape, lo, hi, [1.0, 2.0, 4.0])
