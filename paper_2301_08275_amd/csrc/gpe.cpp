@@ -509,9 +509,8 @@ gpe_status forward_all(gpe_ctx *c, const void *src, void *dst, int skip = -1,
 // Shell spectra of the current state (see gpe_spectra); with obs, also the
 // observables: the first pass of the transform behind N(n) takes the
 // real-space sums and the particle-number shell kernel sums
-// |k|^2 |psi_hat|^2 / N_tot per shell, which over all shells is the kinetic
-// sum by Parseval's identity on the whole grid, so the read-only observable
-// passes do not run.
+// |k|^2 |psi_hat|^2 / N_tot over the grid, the kinetic sum by Parseval's
+// identity on the whole grid, so the read-only observable passes do not run.
 gpe_status compute_spectra(gpe_ctx *c, gpe_spectra *spec, gpe_obs *obs = nullptr) {
   const int nb = shell_count(c);
   if (spec->nbins != nb) return fail(c, GPE_EINVAL, "spec->nbins must equal gpe_spectra_bins()");
@@ -587,9 +586,7 @@ gpe_status compute_spectra(gpe_ctx *c, gpe_spectra *spec, gpe_obs *obs = nullptr
                              hipMemcpyDeviceToHost, c->stream), "sums download");
   HIPCHK(c, hipStreamSynchronize(c->stream), "stream sync");
   if (obs) {
-    double kin = 0;  // shells in order
-    for (int b = 0; b < nb; ++b) kin += h[nb + b];
-    sums[gpe::kSlotKin] = kin;
+    sums[gpe::kSlotKin] = h[nb];  // the shell kernel's |k|^2 sum
     gpe_status ost = obs_from_sums(c, sums.data(), obs);
     if (ost != GPE_OK) return ost;
   }

@@ -1,7 +1,7 @@
 // |k|-shell spectra: particle number, compressible and incompressible kinetic
 // energy, and the quantum-pressure part.  The particle-number kernel also
-// sums |k|^2 |psi_hat|^2 per shell: over all shells, the kinetic energy by
-// Parseval's identity on the whole grid.
+// sums |k|^2 |psi_hat|^2 over the grid: the kinetic energy by Parseval's
+// identity on the whole grid.
 //
 // The spectra of Z_j = u_j + i w_j (two real fields packed in one complex FFT)
 // are unpacked per wavenumber from Z_j(k) and Z_j(-k):
@@ -218,7 +218,7 @@ __device__ __forceinline__ long long site_of(const ShellArgs &a, long long e, in
 // any arithmetic.
 template <typename T, int KIND, int U, int RANGE>
 __device__ __forceinline__ void shell_range(const ShellArgs &a, double *h, bool rows_apart,
-                                            int l1, int l2, int lane) {
+                                            int l1, int l2, int lane, double &kin) {
   constexpr int NF = KIND == 0 ? 1 : 3;
   const int nb = a.nbins, n2 = a.n[2];
   const long long count = range_count(a, RANGE);
@@ -257,24 +257,23 @@ __device__ __forceinline__ void shell_range(const ShellArgs &a, double *h, bool 
 #pragma unroll
       for (int j = 0; j < NF; ++j)
         if (!q[u].on) zp[u][j] = zm[u][j] = cxs<T>{0, 0};
-    // kind 0: the weighted |Z|^2 of each site and its |k|^2 multiple, formed
-    // once all loads are issued
-    double en[U], ek[U];
+    // kind 0: the weighted |Z|^2 of each site, formed once all loads are
+    // issued, and this thread's running |k|^2 |Z|^2 sum (in program order)
+    double en[U];
 #pragma unroll
     for (int u = 0; u < U; ++u) {
       const double z2 = (double)zp[u][0].x * zp[u][0].x + (double)zp[u][0].y * zp[u][0].y;
       en[u] = a.w * z2;
-      ek[u] = a.wk * q[u].kk * z2;
+      if constexpr (KIND == 0) kin += a.wk * q[u].kk * z2;
     }
 #pragma unroll
     for (int u = 0; u < U; ++u) {
       const int key_next = __shfl_down(q[u].key, 1, 64);
       const bool last = q[u].on && (lane == 63 || key_next != q[u].key);
       if constexpr (KIND == 0) {
-        double e[2] = {en[u], ek[u]};
+        double e[1] = {en[u]};
         run_sums(e, q[u].key);
         add_run(h, q[u].bin, e[0], last, rows_apart, lane);
-        add_run(h + nb, q[u].bin, e[1], last, rows_apart, lane);
       } else {
         double csum = 0, isum = 0, qsum = 0;
         if (q[u].on) {
@@ -320,9 +319,9 @@ __device__ __forceinline__ void shell_range(const ShellArgs &a, double *h, bool 
 
 template <typename T, int KIND, int U>
 __global__ void __launch_bounds__(kShellThreads) shell_kernel(const ShellArgs a) {
-  // two histograms (kind 0: particle number, |k|^2-weighted) or three (kind
-  // 1: compressible, incompressible, quantum pressure) of nbins per wavefront
-  constexpr int NH = KIND == 0 ? 2 : 3;
+  // one histogram (kind 0: particle number) or three (kind 1: compressible,
+  // incompressible, quantum pressure) of nbins per wavefront
+  constexpr int NH = KIND == 0 ? 1 : 3;
   extern __shared__ double hist[];
   const int nb = a.nbins, nw = blockDim.x >> 6;
   for (int i = threadIdx.x; i < nw * NH * nb; i += blockDim.x) hist[i] = 0;
@@ -330,22 +329,34 @@ __global__ void __launch_bounds__(kShellThreads) shell_kernel(const ShellArgs a)
   double *h = hist + (threadIdx.x >> 6) * NH * nb;
   const int l1 = log2_of(a.n[1]), l2 = log2_of(a.n[2]);
   const int lane = threadIdx.x & 63;
+  double kin = 0;
   if constexpr (KIND == 0) {
-    shell_range<T, 0, U, RANGE_ALL>(a, h, a.n[2] < 128, l1, l2, lane);
+    shell_range<T, 0, U, RANGE_ALL>(a, h, a.n[2] < 128, l1, l2, lane, kin);
   } else {
     // a wavefront's 64 half-row indices share one half-row when n2/2 >= 64
-    shell_range<T, 1, U, RANGE_HALF>(a, h, a.n[2] < 128, l1, l2, lane);
-    shell_range<T, 1, 1, RANGE_EXTRA>(a, h, true, l1, l2, lane);
+    shell_range<T, 1, U, RANGE_HALF>(a, h, a.n[2] < 128, l1, l2, lane, kin);
+    shell_range<T, 1, 1, RANGE_EXTRA>(a, h, true, l1, l2, lane, kin);
+  }
+  // kind 0: the workgroup's |k|^2 sum, lanes by a fixed butterfly (lane 0's
+  // result), then the wavefronts in order
+  __shared__ double kin_wave[kShellThreads / 64];
+  if constexpr (KIND == 0) {
+#pragma unroll
+    for (int o = 32; o >= 1; o >>= 1) kin += __shfl_xor(kin, o, 64);
+    if (lane == 0) kin_wave[threadIdx.x >> 6] = kin;
   }
   __syncthreads();
-  // row of this workgroup: kind 0 N(n) in [0, nb) and the |k|^2 sums in
-  // [nb, 2 nb); kind 1 the energies in [nb, 4 nb)
+  // row of this workgroup: kind 0 N(n) in [0, nb) and the |k|^2 sum at nb;
+  // kind 1 the energies in [nb, 4 nb)
   double *out = a.partial + (long long)blockIdx.x * 4 * nb;
   for (int i = threadIdx.x; i < 4 * nb; i += blockDim.x) {
     const int j = KIND == 0 ? i : i - nb;  // index within the wavefront histograms
     double t = 0;
-    if (j >= 0 && j < NH * nb)
+    if (j >= 0 && j < NH * nb) {
       for (int w = 0; w < nw; ++w) t += hist[w * NH * nb + j];
+    } else if (KIND == 0 && i == nb) {
+      for (int w = 0; w < nw; ++w) t += kin_wave[w];
+    }
     out[i] = t;
   }
 }
@@ -380,7 +391,7 @@ struct ShellShape {
   size_t lds;
 };
 ShellShape shell_shape(int kind, int nbins) {
-  const size_t per_wave = (kind == 0 ? 2 : 3) * (size_t)nbins * sizeof(double);
+  const size_t per_wave = (kind == 0 ? 1 : 3) * (size_t)nbins * sizeof(double);
   int waves = (int)((64 * 1024) / per_wave);
   if (waves > kShellThreads / 64) waves = kShellThreads / 64;
   return {waves, waves > 0 ? waves * per_wave : 0};
